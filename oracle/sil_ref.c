@@ -1,0 +1,314 @@
+/*
+ * sil_ref.c -- CPU oracle of the sea-ice auto-labeller (test infrastructure
+ * only; see sil_ref.h for the definition and for who may use it).
+ *
+ * Written for a reader checking it against the paper by eye: every step runs
+ * over the whole scene in the order the definition gives, with no blocking,
+ * fusion or reordering.  Arithmetic is integer; products that can exceed 64
+ * bits use unsigned __int128.
+ */
+#include "sil_ref.h"
+
+#include <stdlib.h>
+#include <string.h>
+
+typedef unsigned __int128 u128;
+
+/* ---- parameters -------------------------------------------------------- */
+
+void sil_ref_params_default(sil_ref_params* p) {
+  memset(p, 0, sizeof(*p));
+  p->abi = SIL_REF_ABI_VERSION;
+  p->dtype = SIL_REF_U8;
+  p->refl_max = 10000; /* Sentinel-2 L1C/L2A quantification: 10000 = reflectance 1 */
+  /* Section III-B: thick ice (0,0,205)-(185,255,255), thin ice
+   * (0,0,31)-(185,255,204), open water (0,0,0)-(185,255,30).  Class ids are
+   * ordered by V: 0 water, 1 thin ice, 2 thick ice. */
+  const uint8_t lo[3][3] = {{0, 0, 0}, {0, 0, 31}, {0, 0, 205}};
+  const uint8_t hi[3][3] = {{185, 255, 30}, {185, 255, 204}, {185, 255, 255}};
+  memcpy(p->lo, lo, sizeof(lo));
+  memcpy(p->hi, hi, sizeof(hi));
+  p->filter = 1;
+  p->chip = 256;       /* the 256x256 images of sections III-A and IV-A */
+  p->clip_shift = 8;   /* k = N/256 pixels clipped at each tail */
+  p->eta_num = 3;      /* gate: eta >= 3/4 */
+  p->eta_den = 4;
+  p->patch_h = 256;
+  p->patch_w = 256;
+}
+
+const char* sil_ref_strerror(int code) {
+  switch (code) {
+    case SIL_REF_OK: return "ok";
+    case SIL_REF_EINVAL: return "invalid argument";
+    case SIL_REF_EUNSUPPORTED: return "unsupported parameters";
+    default: return "unknown error";
+  }
+}
+
+/* Number of classes whose V-interval holds v. */
+static int classes_holding(uint32_t v, const sil_ref_params* p) {
+  int n = 0;
+  for (int c = 0; c < 3; ++c)
+    if (p->lo[c][2] <= v && v <= p->hi[c][2]) ++n;
+  return n;
+}
+
+int sil_ref_validate(int32_t nbands, const int32_t* sel, int32_t H, int32_t W,
+                     int64_t pitch, int64_t label_pitch, const sil_ref_params* p) {
+  if (!p || !sel) return SIL_REF_EINVAL;
+  if (p->abi != SIL_REF_ABI_VERSION) return SIL_REF_EINVAL;
+  if (p->dtype != SIL_REF_U8 && p->dtype != SIL_REF_U16) return SIL_REF_EINVAL;
+  if (p->dtype == SIL_REF_U16 && p->refl_max < 1) return SIL_REF_EINVAL;
+  if (p->filter > 1) return SIL_REF_EINVAL;
+  if (p->chip < 1 || p->clip_shift < 1 || p->clip_shift > 31) return SIL_REF_EINVAL;
+  if (p->eta_den < 1 || p->eta_num > p->eta_den) return SIL_REF_EINVAL;
+  if (p->patch_h < 1 || p->patch_w < 1) return SIL_REF_EINVAL;
+  if (H < 1 || W < 1 || pitch < W || label_pitch < W || nbands < 1) return SIL_REF_EINVAL;
+  for (int i = 0; i < 3; ++i)
+    if (sel[i] < 0 || sel[i] >= nbands) return SIL_REF_EINVAL;
+  /* Section III-B states the three ranges do not intersect. */
+  for (uint32_t v = 0; v < 256; ++v)
+    if (classes_holding(v, p) > 1) return SIL_REF_EINVAL;
+  /* A V value in no range would leave a pixel unlabelled. */
+  for (uint32_t v = 0; v < 256; ++v)
+    if (classes_holding(v, p) == 0) return SIL_REF_EUNSUPPORTED;
+  /* OpenCV 8-bit HSV: H in [0,179], S in [0,255].  Limits that do not span
+   * those ranges would make the masks depend on hue/saturation. */
+  for (int c = 0; c < 3; ++c)
+    if (p->lo[c][0] != 0 || p->hi[c][0] < 179 || p->lo[c][1] != 0 || p->hi[c][1] != 255)
+      return SIL_REF_EUNSUPPORTED;
+  /* Exact Otsu comparisons below fit 128 bits for chips of at most 256^2. */
+  if (p->filter == 1 && p->chip > 256) return SIL_REF_EUNSUPPORTED;
+  return SIL_REF_OK;
+}
+
+int sil_ref_hist_dims(int32_t H, int32_t W, const sil_ref_params* p, int32_t* ny,
+                      int32_t* nx) {
+  if (!p || !ny || !nx || H < 1 || W < 1 || p->patch_h < 1 || p->patch_w < 1)
+    return SIL_REF_EINVAL;
+  *ny = (int32_t)(((int64_t)H + p->patch_h - 1) / p->patch_h);
+  *nx = (int32_t)(((int64_t)W + p->patch_w - 1) / p->patch_w);
+  return SIL_REF_OK;
+}
+
+/* ---- step 1: V plane --------------------------------------------------- */
+
+/* round-half-up of x*255/refl_max, saturating at 255 */
+uint8_t sil_ref_rescale(uint32_t x, uint32_t refl_max) {
+  uint64_t q = ((uint64_t)x * 255u + refl_max / 2u) / refl_max;
+  return (uint8_t)(q > 255u ? 255u : q);
+}
+
+void sil_ref_value_plane(const void* scene, int32_t nbands, const int32_t* sel,
+                         int32_t H, int32_t W, int64_t pitch, uint32_t dtype,
+                         uint32_t refl_max, uint8_t* V) {
+  (void)nbands;
+  const int64_t plane = (int64_t)H * pitch;
+  for (int32_t y = 0; y < H; ++y)
+    for (int32_t x = 0; x < W; ++x) {
+      uint32_t m = 0;
+      for (int i = 0; i < 3; ++i) {
+        int64_t idx = sel[i] * plane + (int64_t)y * pitch + x;
+        uint32_t v = dtype == SIL_REF_U8 ? ((const uint8_t*)scene)[idx]
+                                         : ((const uint16_t*)scene)[idx];
+        if (v > m) m = v;
+      }
+      V[(int64_t)y * W + x] = dtype == SIL_REF_U8 ? (uint8_t)m : sil_ref_rescale(m, refl_max);
+    }
+}
+
+/* ---- step 3: 3x3 median, clamped border ------------------------------- */
+
+static int32_t clampi(int32_t v, int32_t lo, int32_t hi) {
+  return v < lo ? lo : (v > hi ? hi : v);
+}
+
+void sil_ref_median3x3(const uint8_t* V, int32_t H, int32_t W, uint8_t* Vm) {
+  for (int32_t y = 0; y < H; ++y)
+    for (int32_t x = 0; x < W; ++x) {
+      uint8_t w[9];
+      int n = 0;
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx)
+          w[n++] = V[(int64_t)clampi(y + dy, 0, H - 1) * W + clampi(x + dx, 0, W - 1)];
+      /* insertion sort, then the 5th smallest */
+      for (int i = 1; i < 9; ++i)
+        for (int j = i; j > 0 && w[j - 1] > w[j]; --j) {
+          uint8_t t = w[j];
+          w[j] = w[j - 1];
+          w[j - 1] = t;
+        }
+      Vm[(int64_t)y * W + x] = w[4];
+    }
+}
+
+/* ---- step 4: per-chip statistics --------------------------------------- */
+
+uint8_t sil_ref_stretch(uint8_t m, uint8_t lo, uint8_t hi) {
+  /* min-max normalisation of [lo,hi] to [0,255] after truncation to
+   * [lo,hi]; round half up */
+  uint32_t c = m < lo ? lo : (m > hi ? hi : m);
+  uint32_t d = (uint32_t)hi - lo;
+  return (uint8_t)(((c - lo) * 255u + d / 2u) / d);
+}
+
+int sil_ref_class_of(uint8_t vc, const sil_ref_params* p) {
+  /* The three inRange masks; hue/saturation limits are vacuous (checked by
+   * validation), so mask c holds iff lo_V[c] <= Vc <= hi_V[c]. */
+  int label = -1;
+  for (int c = 0; c < 3; ++c)
+    if (p->lo[c][2] <= vc && vc <= p->hi[c][2]) label = c;
+  return label;
+}
+
+static uint8_t filtered_value(uint8_t m, const sil_ref_chip_info* info) {
+  return info->stretch ? sil_ref_stretch(m, info->lo, info->hi) : m;
+}
+
+void sil_ref_chip_stats(const uint32_t* h, const sil_ref_params* p,
+                        sil_ref_chip_info* info) {
+  uint64_t N = 0, S = 0, Q = 0;
+  for (uint32_t v = 0; v < 256; ++v) {
+    N += h[v];
+    S += (uint64_t)v * h[v];
+    Q += (uint64_t)v * v * h[v];
+  }
+
+  /* Otsu: maximise the between-class variance over splits {v <= t} |
+   * {v > t}.  With class weights w0, w1 and sums S0, S1,
+   *   sigma_B^2 * N^2 = (w1*S0 - w0*S1)^2 / (w0*w1),
+   * compared exactly as fractions num/den; the smallest t wins ties. */
+  int32_t best_t = -1;
+  u128 best_num = 0;
+  uint64_t best_den = 1;
+  uint64_t w0 = 0, S0 = 0;
+  for (uint32_t t = 0; t < 255; ++t) {
+    w0 += h[t];
+    S0 += (uint64_t)t * h[t];
+    uint64_t w1 = N - w0, S1 = S - S0;
+    if (w0 == 0 || w1 == 0) continue;
+    __int128 diff = (__int128)w1 * S0 - (__int128)w0 * S1;
+    u128 num = (u128)(diff < 0 ? -diff : diff);
+    num *= num;
+    uint64_t den = w0 * w1;
+    if (best_t < 0 || num * best_den > best_num * den) {
+      best_t = (int32_t)t;
+      best_num = num;
+      best_den = den;
+    }
+  }
+  info->t = best_t;
+
+  /* Binary threshold on separability eta = sigma_B^2 / sigma_T^2 with
+   *   sigma_T^2 * N^2 = N*Q - S^2. */
+  info->gate = 0;
+  if (best_t >= 0) {
+    u128 var = (u128)N * Q - (u128)S * S;
+    info->gate = (u128)p->eta_den * best_num >= (u128)p->eta_num * best_den * var;
+  }
+
+  /* Truncation levels: lo is the (k+1)-th smallest value, hi the (k+1)-th
+   * largest, k = N >> clip_shift. */
+  uint64_t k = N >> p->clip_shift;
+  uint64_t cum = 0;
+  int lo = 255;
+  for (int v = 0; v < 256; ++v) {
+    cum += h[v];
+    if (cum > k) {
+      lo = v;
+      break;
+    }
+  }
+  cum = 0;
+  int hi = 0;
+  for (int v = 255; v >= 0; --v) {
+    cum += h[v];
+    if (cum > k) {
+      hi = v;
+      break;
+    }
+  }
+  info->lo = (uint8_t)lo;
+  info->hi = (uint8_t)hi;
+  info->stretch = info->gate && hi > lo;
+
+  /* Debug summary: the smallest median value whose label reaches 1 and 2. */
+  info->a1 = 256;
+  info->a2 = 256;
+  for (int m = 255; m >= 0; --m) {
+    int c = sil_ref_class_of(filtered_value((uint8_t)m, info), p);
+    if (c >= 1) info->a1 = (uint16_t)m;
+    if (c >= 2) info->a2 = (uint16_t)m;
+  }
+}
+
+/* ---- the whole labeller ------------------------------------------------ */
+
+int sil_ref_label(const void* scene, int32_t nbands, const int32_t* sel, int32_t H,
+                  int32_t W, int64_t pitch, const sil_ref_params* p, uint8_t* labels,
+                  int64_t label_pitch, uint32_t* hist, sil_ref_chip_info* chips) {
+  if (!scene || !labels || !hist) return SIL_REF_EINVAL;
+  int rc = sil_ref_validate(nbands, sel, H, W, pitch, label_pitch, p);
+  if (rc != SIL_REF_OK) return rc;
+  int32_t ny, nx;
+  sil_ref_hist_dims(H, W, p, &ny, &nx);
+
+  const int64_t npx = (int64_t)H * W;
+  uint8_t* V = malloc((size_t)npx);
+  uint8_t* Vc = malloc((size_t)npx);
+  if (!V || !Vc) {
+    free(V);
+    free(Vc);
+    return SIL_REF_EINVAL;
+  }
+
+  /* 1. V plane */
+  sil_ref_value_plane(scene, nbands, sel, H, W, pitch, p->dtype, p->refl_max, V);
+
+  if (p->filter == 0) {
+    /* 2. no filter */
+    memcpy(Vc, V, (size_t)npx);
+  } else {
+    /* 3. median */
+    uint8_t* Vm = malloc((size_t)npx);
+    if (!Vm) {
+      free(V);
+      free(Vc);
+      return SIL_REF_EINVAL;
+    }
+    sil_ref_median3x3(V, H, W, Vm);
+    /* 4. per chip: statistics, then the stretch of every pixel */
+    const int32_t C = (int32_t)p->chip;
+    const int32_t ncy = (H + C - 1) / C, ncx = (W + C - 1) / C;
+    for (int32_t cy = 0; cy < ncy; ++cy)
+      for (int32_t cx = 0; cx < ncx; ++cx) {
+        int32_t y0 = cy * C, y1 = y0 + C < H ? y0 + C : H;
+        int32_t x0 = cx * C, x1 = x0 + C < W ? x0 + C : W;
+        uint32_t h[256] = {0};
+        for (int32_t y = y0; y < y1; ++y)
+          for (int32_t x = x0; x < x1; ++x) h[Vm[(int64_t)y * W + x]]++;
+        sil_ref_chip_info info;
+        sil_ref_chip_stats(h, p, &info);
+        if (chips) chips[(int64_t)cy * ncx + cx] = info;
+        for (int32_t y = y0; y < y1; ++y)
+          for (int32_t x = x0; x < x1; ++x)
+            Vc[(int64_t)y * W + x] = filtered_value(Vm[(int64_t)y * W + x], &info);
+      }
+    free(Vm);
+  }
+
+  /* 5. masks -> label; 6. per-patch counts */
+  memset(hist, 0, sizeof(uint32_t) * 3 * (size_t)ny * (size_t)nx);
+  for (int32_t y = 0; y < H; ++y)
+    for (int32_t x = 0; x < W; ++x) {
+      int c = sil_ref_class_of(Vc[(int64_t)y * W + x], p);
+      labels[(int64_t)y * label_pitch + x] = (uint8_t)c;
+      int64_t py = y / (int64_t)p->patch_h, px = x / (int64_t)p->patch_w;
+      hist[(py * nx + px) * 3 + c]++;
+    }
+
+  free(V);
+  free(Vc);
+  return SIL_REF_OK;
+}
