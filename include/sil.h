@@ -1,0 +1,151 @@
+/*
+ * sil.h -- C ABI of libsil, the GPU (gfx950) sea-ice auto-labeller.
+ *
+ * Method: arXiv 2403.13135, "A Parallel Workflow for Polar Sea-Ice
+ * Classification using Auto-labeling of Sentinel-2 Imagery".
+ *   - bands B2, B3, B4 (blue, green, red): section III-A;
+ *   - thin-cloud/shadow filter built from the OpenCV operations the paper
+ *     lists (HSV conversion, noise filtering, Otsu, truncated and binary
+ *     thresholding, min-max normalisation): section III-A, "Filtering Out
+ *     the Thin Clouds and Shadows";
+ *   - HSV inRange segmentation with inclusive limits, water (0,0,0)-
+ *     (185,255,30), thin ice (0,0,31)-(185,255,204), thick ice (0,0,205)-
+ *     (185,255,255), non-intersecting masks merged into one label image:
+ *     section III-B, "Auto-labeling Method";
+ *   - per-patch class counts as the map-reduce output: section III-B,
+ *     "Scaling Auto-labeling" (PySpark Map-Reduce).
+ *
+ * The filter composition the library implements (the paper lists the
+ * operations without order or constants):
+ *   V = max(B, G, R) (16-bit input: round-half-up of x*255/refl_max,
+ *   saturating) -> 3x3 median with clamped borders -> per chip (chip x chip
+ *   tiles anchored at the origin): 256-bin histogram, exact Otsu split t*
+ *   (ties to the smallest t), gate eta = sigma_B^2/sigma_T^2 >= eta_num /
+ *   eta_den, truncation levels lo/hi at rank k = N >> clip_shift from each
+ *   tail, and, if the gate passes and hi > lo, the stretch
+ *   Vc = ((clamp(Vm,lo,hi) - lo)*255 + (hi-lo)/2) div (hi-lo); else Vc = Vm.
+ *   The label is the class whose V-interval holds Vc.
+ *
+ * Conventions for every entry point:
+ *   - All arithmetic is integer; results are bit-exact and deterministic.
+ *   - Device buffers are owned by the caller.  The library allocates no device
+ *     or host memory per call and keeps no pointer after it returns.
+ *   - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is the
+ *     default stream).  Buffers must stay valid until that work completes.
+ *   - Argument errors are detected before anything is enqueued and leave every
+ *     output untouched.  A launch failure returns SIL_EDEVICE.  Faults during
+ *     execution surface at the caller's next synchronisation of `stream`.
+ *   - Thread-safe: no mutable global state besides a per-process cache of
+ *     host-side derived constants guarded by a mutex.
+ */
+#ifndef SIL_H
+#define SIL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SIL_ABI_VERSION 1u
+
+/* Return codes. */
+enum {
+  SIL_OK = 0,
+  SIL_EINVAL = -1,       /* bad pointer, size, pitch, band index or parameter */
+  SIL_EUNSUPPORTED = -2, /* valid in the paper's model but outside this library */
+  SIL_EDEVICE = -3       /* HIP launch error */
+};
+
+/* Input element types. */
+enum { SIL_U8 = 1, SIL_U16 = 2 };
+
+/* Labelling parameters.  sil_params_default() gives the paper's values. */
+typedef struct sil_params {
+  uint32_t abi;        /* must equal SIL_ABI_VERSION */
+  uint32_t dtype;      /* SIL_U8 or SIL_U16 */
+  uint32_t refl_max;   /* SIL_U16 only: reflectance full scale mapped to V = 255;
+                          1..65535, default 10000 (Sentinel-2 quantification) */
+  uint8_t lo[3][3];    /* [class][H,S,V] inclusive lower limits, class 0 water,
+                          1 thin ice, 2 thick ice (section III-B) */
+  uint8_t hi[3][3];    /* [class][H,S,V] inclusive upper limits */
+  uint8_t pad[2];      /* zero */
+  uint32_t filter;     /* 0: thresholds only (the paper's "original" images),
+                          1: cloud/shadow filter, then thresholds (default) */
+  uint32_t chip;       /* filter unit side in pixels, 1..256, default 256 */
+  uint32_t clip_shift; /* truncation rank k = N >> clip_shift, 1..31, default 8 */
+  uint32_t eta_num;    /* gate eta >= eta_num/eta_den, 0 <= num <= den, */
+  uint32_t eta_den;    /*   den >= 1, default 3/4 */
+  uint32_t patch_h;    /* count patch height, >= 1, default 256 */
+  uint32_t patch_w;    /* count patch width, >= 1, default 256 */
+} sil_params;
+
+/* Per-chip filter statistics (optional debug output of sil_label). */
+typedef struct sil_chip_info {
+  int32_t t;       /* Otsu split t* in 0..254, -1 if the chip has one value */
+  uint8_t lo, hi;  /* truncation levels */
+  uint8_t gate;    /* 1 if eta >= eta_num/eta_den */
+  uint8_t stretch; /* 1 if the min-max stretch was applied (gate && hi > lo) */
+  uint16_t a1, a2; /* smallest median value labelled >= 1 and >= 2; 256 if none */
+} sil_chip_info;
+
+/* Fill *p with the paper's limits (section III-B) and the filter defaults
+ * above.  p must be non-NULL. */
+void sil_params_default(sil_params* p);
+
+/* ABI version the library was built with (SIL_ABI_VERSION). */
+uint32_t sil_abi_version(void);
+
+/* Dimensions of the per-patch count array: ny = ceil(H/patch_h),
+ * nx = ceil(W/patch_w).  Returns SIL_EINVAL on NULL pointers, H or W < 1, or
+ * zero patch sides. */
+int sil_hist_dims(int32_t H, int32_t W, const sil_params* p, int32_t* ny, int32_t* nx);
+
+/* Check arguments exactly as sil_label does, without touching any buffer.
+ * Same return codes as sil_label (never SIL_EDEVICE). */
+int sil_validate(int32_t nbands, const int32_t sel[3], int32_t H, int32_t W,
+                 int64_t pitch, int64_t label_pitch, const sil_params* p);
+
+/* Label one scene and count classes per patch.
+ *
+ *   scene        device, planar [nbands][H][pitch] elements of p->dtype (plane
+ *                stride H*pitch).  Any alignment and pitch is accepted;
+ *                8-byte (u16) / 4-byte (u8) aligned rows take the vector path.
+ *   nbands, sel  sel[0..2] are the plane indices of B2 (blue), B3 (green) and
+ *                B4 (red), each in [0, nbands).
+ *   H, W         scene height and width, >= 1; pitch >= W (elements).
+ *   labels       device, [H][label_pitch] bytes, label_pitch >= W; every pixel
+ *                (y < H, x < W) is written with 0 (water), 1 (thin ice) or
+ *                2 (thick ice); bytes beyond W are not touched.
+ *   hist         device, uint32 [ny][nx][3] (see sil_hist_dims), fully
+ *                overwritten: hist[py][px][c] = number of pixels of class c in
+ *                patch (py, px); patches are anchored at (0,0), partial at
+ *                the right/bottom edges.
+ *   chips        device, nullable; with filter = 1, [ceil(H/chip)][ceil(W/chip)]
+ *                per-chip statistics.  Ignored when filter = 0.
+ *   stream       hipStream_t or NULL.
+ *
+ * Errors:
+ *   SIL_EINVAL        NULL scene/labels/hist/sel/p; H or W < 1; pitch < W;
+ *                     label_pitch < W; nbands < 1; sel out of range; abi
+ *                     mismatch; bad dtype, refl_max, filter, chip, clip_shift,
+ *                     eta or patch; V-intervals that intersect (section III-B
+ *                     states they do not).
+ *   SIL_EUNSUPPORTED  V-intervals leaving a value unlabelled; hue/saturation
+ *                     limits that do not span H in [0,179] and S in [0,255]
+ *                     (OpenCV 8-bit HSV); class order along V other than
+ *                     water <= thin <= thick; chip > 256; refl_max > 65535;
+ *                     H*W beyond 2^31 chips or pixel offsets beyond int64.
+ *   SIL_EDEVICE       the kernel launch failed.
+ */
+int sil_label(const void* scene, int32_t nbands, const int32_t sel[3], int32_t H,
+              int32_t W, int64_t pitch, const sil_params* p, uint8_t* labels,
+              int64_t label_pitch, uint32_t* hist, sil_chip_info* chips, void* stream);
+
+/* Human-readable text of a return code (static storage). */
+const char* sil_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,202 @@
+"""Python binding of libsil (argument marshalling only).
+
+Every step of the labelling runs in the gfx950 kernels of ``libsil.so``; this
+module only checks tensor shapes, picks the current HIP stream and forwards
+raw device pointers through the C ABI declared in ``include/sil.h``.  There
+is no CPU path: if the library is missing, importing the binding's entry
+points raises.
+"""
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import Optional, Sequence, Tuple
+
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsil.so")
+
+OK, EINVAL, EUNSUPPORTED, EDEVICE = 0, -1, -2, -3
+U8, U16 = 1, 2
+ABI_VERSION = 1
+
+
+class SilError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"sil error {code}: {msg}")
+        self.code = code
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("abi", ctypes.c_uint32),
+        ("dtype", ctypes.c_uint32),
+        ("refl_max", ctypes.c_uint32),
+        ("lo", (ctypes.c_uint8 * 3) * 3),
+        ("hi", (ctypes.c_uint8 * 3) * 3),
+        ("pad", ctypes.c_uint8 * 2),
+        ("filter", ctypes.c_uint32),
+        ("chip", ctypes.c_uint32),
+        ("clip_shift", ctypes.c_uint32),
+        ("eta_num", ctypes.c_uint32),
+        ("eta_den", ctypes.c_uint32),
+        ("patch_h", ctypes.c_uint32),
+        ("patch_w", ctypes.c_uint32),
+    ]
+
+
+CHIP_INFO_BYTES = 12  # sil_chip_info: int32 t; u8 lo, hi, gate, stretch; u16 a1, a2
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded ``libsil.so``; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it first (python -m paper_2403_13135_amd._build)")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        L.sil_params_default.argtypes = [P(_Params)]
+        L.sil_params_default.restype = None
+        L.sil_abi_version.argtypes = []
+        L.sil_abi_version.restype = ctypes.c_uint32
+        L.sil_hist_dims.argtypes = [ctypes.c_int32, ctypes.c_int32, P(_Params),
+                                    P(ctypes.c_int32), P(ctypes.c_int32)]
+        L.sil_hist_dims.restype = ctypes.c_int
+        L.sil_validate.argtypes = [ctypes.c_int32, P(ctypes.c_int32), ctypes.c_int32,
+                                   ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, P(_Params)]
+        L.sil_validate.restype = ctypes.c_int
+        L.sil_label.argtypes = [ctypes.c_void_p, ctypes.c_int32, P(ctypes.c_int32),
+                                ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, P(_Params),
+                                ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                ctypes.c_void_p, ctypes.c_void_p]
+        L.sil_label.restype = ctypes.c_int
+        L.sil_strerror.argtypes = [ctypes.c_int]
+        L.sil_strerror.restype = ctypes.c_char_p
+        if L.sil_abi_version() != ABI_VERSION:
+            raise RuntimeError("libsil ABI version mismatch")
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().sil_strerror(code).decode()
+
+
+def _check(code: int):
+    if code != OK:
+        raise SilError(code, strerror(code))
+
+
+@dataclass
+class Params:
+    """Labelling parameters (``sil_params``).  Defaults are the paper's HSV
+    limits (section III-B) and the filter constants of include/sil.h."""
+    dtype: int = U8
+    refl_max: int = 10000
+    lo: Sequence[Sequence[int]] = field(
+        default_factory=lambda: [[0, 0, 0], [0, 0, 31], [0, 0, 205]])
+    hi: Sequence[Sequence[int]] = field(
+        default_factory=lambda: [[185, 255, 30], [185, 255, 204], [185, 255, 255]])
+    filter: int = 1
+    chip: int = 256
+    clip_shift: int = 8
+    eta_num: int = 3
+    eta_den: int = 4
+    patch_h: int = 256
+    patch_w: int = 256
+
+    def to_c(self) -> _Params:
+        p = _Params()
+        lib().sil_params_default(ctypes.byref(p))
+        for name in ("dtype", "refl_max", "filter", "chip", "clip_shift", "eta_num",
+                     "eta_den", "patch_h", "patch_w"):
+            setattr(p, name, int(getattr(self, name)))
+        for c in range(3):
+            for j in range(3):
+                p.lo[c][j] = int(self.lo[c][j])
+                p.hi[c][j] = int(self.hi[c][j])
+        return p
+
+    def fields(self) -> dict:
+        """Plain field dict (for handing the same run to another implementation)."""
+        return {k: getattr(self, k) for k in self.__dataclass_fields__}
+
+
+def hist_dims(H: int, W: int, params: Params) -> Tuple[int, int]:
+    ny, nx = ctypes.c_int32(), ctypes.c_int32()
+    p = params.to_c()
+    _check(lib().sil_hist_dims(H, W, ctypes.byref(p), ctypes.byref(ny), ctypes.byref(nx)))
+    return ny.value, nx.value
+
+
+def validate(nbands: int, sel, H: int, W: int, pitch: int, label_pitch: int,
+             params: Params) -> int:
+    s = (ctypes.c_int32 * 3)(*[int(v) for v in sel])
+    p = params.to_c()
+    return lib().sil_validate(nbands, s, H, W, pitch, label_pitch, ctypes.byref(p))
+
+
+_SCENE_DTYPES = {U8: (torch.uint8,), U16: (torch.uint16, torch.int16)}
+
+
+def label(scene: torch.Tensor, params: Optional[Params] = None, sel=(0, 1, 2),
+          W: Optional[int] = None, labels: Optional[torch.Tensor] = None,
+          hist: Optional[torch.Tensor] = None, chips: bool = False,
+          stream: Optional[torch.cuda.Stream] = None):
+    """Label ``scene`` ([nbands, H, pitch] on the GPU) with ``sil_label``.
+
+    ``W`` defaults to the pitch (the last dimension).  ``labels`` ([H, >=W]
+    uint8) and ``hist`` ([ny, nx, 3] int32/uint32) may be given to reuse
+    buffers.  Returns (labels, hist) or (labels, hist, chip_info_bytes) with
+    ``chips=True`` (a uint8 tensor of ``[ncy, ncx, 12]`` raw sil_chip_info).
+    Enqueued on ``stream`` (default: the current stream); not synchronised.
+    """
+    if params is None:
+        params = Params(dtype=U16 if scene.dtype in _SCENE_DTYPES[U16] else U8)
+    if scene.dim() != 3 or not scene.is_cuda:
+        raise ValueError("scene must be a [nbands, H, pitch] GPU tensor")
+    if scene.dtype not in _SCENE_DTYPES[params.dtype]:
+        raise ValueError(f"scene dtype {scene.dtype} does not match params.dtype")
+    if not scene.is_contiguous():
+        raise ValueError("scene must be contiguous (planar, rows of `pitch` elements)")
+    nb, H, pitch = scene.shape
+    W = pitch if W is None else int(W)
+    dev = scene.device
+    ny, nx = hist_dims(H, W, params)
+    if labels is None:
+        labels = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    if labels.dtype != torch.uint8 or labels.dim() != 2 or labels.shape[0] != H \
+            or labels.shape[1] < W or labels.stride(1) != 1:
+        raise ValueError("labels must be uint8 [H, >=W] with unit column stride")
+    if hist is None:
+        hist = torch.empty((ny, nx, 3), dtype=torch.int32, device=dev)
+    if hist.shape != (ny, nx, 3) or hist.dtype not in (torch.int32, torch.uint32) \
+            or not hist.is_contiguous():
+        raise ValueError(f"hist must be contiguous int32 [{ny}, {nx}, 3]")
+    chip_t = None
+    if chips:
+        C = params.chip
+        chip_t = torch.zeros(((H + C - 1) // C, (W + C - 1) // C, CHIP_INFO_BYTES),
+                             dtype=torch.uint8, device=dev)
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    sel_c = (ctypes.c_int32 * 3)(*[int(v) for v in sel])
+    p = params.to_c()
+    rc = lib().sil_label(ctypes.c_void_p(scene.data_ptr()), nb, sel_c, H, W, pitch,
+                         ctypes.byref(p), ctypes.c_void_p(labels.data_ptr()),
+                         labels.stride(0), ctypes.c_void_p(hist.data_ptr()),
+                         ctypes.c_void_p(chip_t.data_ptr()) if chips else None,
+                         ctypes.c_void_p(s.cuda_stream))
+    _check(rc)
+    return (labels, hist, chip_t) if chips else (labels, hist)
+
+
+def decode_chip_info(raw) -> list:
+    """Decode a [..., 12] uint8 array of sil_chip_info into dicts (host side)."""
+    import numpy as np
+    dt = np.dtype([("t", "<i4"), ("lo", "u1"), ("hi", "u1"), ("gate", "u1"),
+                   ("stretch", "u1"), ("a1", "<u2"), ("a2", "<u2")])
+    arr = np.ascontiguousarray(np.asarray(raw, dtype=np.uint8))
+    return arr.reshape(-1).view(dt).reshape(arr.shape[:-1])
