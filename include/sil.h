@@ -142,6 +142,44 @@ int sil_label(const void* scene, int32_t nbands, const int32_t sel[3], int32_t H
               int32_t W, int64_t pitch, const sil_params* p, uint8_t* labels,
               int64_t label_pitch, uint32_t* hist, sil_chip_info* chips, void* stream);
 
+/* Number of chips ceil(H/chip) * ceil(W/chip) of a scene (raster order:
+ * chip id = cy * ceil(W/chip) + cx).  SIL_EINVAL on NULL or sizes < 1. */
+int sil_chip_count(int32_t H, int32_t W, const sil_params* p, int32_t* nchips);
+
+/* Scenes per sil_label_batch call. */
+#define SIL_BATCH_MAX_JOBS 24
+
+/* One scene's share of a batched launch: the scene and output buffers exactly
+ * as for sil_label, plus the chip range [chip_begin, chip_begin + chip_count)
+ * (raster order) to label in this call. */
+typedef struct sil_job {
+  const void* scene;     /* device, [nbands][H][pitch] */
+  int32_t nbands;
+  int32_t sel[3];
+  int32_t H, W;
+  int64_t pitch;
+  uint8_t* labels;       /* device, [H][label_pitch] */
+  int64_t label_pitch;
+  uint32_t* hist;        /* device, [ceil(H/chip)][ceil(W/chip)][3] */
+  sil_chip_info* chips;  /* device, nullable */
+  int32_t chip_begin;
+  int32_t chip_count;
+} sil_job;
+
+/* Label chip ranges of up to SIL_BATCH_MAX_JOBS scenes in ONE kernel launch
+ * (the filter, segmentation and counts of section III of the paper, as in
+ * sil_label).  Used for continuous batching: a long scene can be split over
+ * several calls and small scenes share one launch.  Results of a chip do not
+ * depend on which call labels it or what else that call contains.
+ *
+ * Requirements beyond sil_label's: filter = 1 and patch_h = patch_w = chip
+ * (counts come straight from each chip), else SIL_EUNSUPPORTED; all jobs use
+ * `p`.  Only the labels, counts and chip statistics of the listed chips are
+ * written.  Errors: SIL_EINVAL for NULL/0/too many jobs or a chip range
+ * outside the scene, plus every sil_label argument error of any job; nothing
+ * is enqueued on error.  Allocates nothing; asynchronous on `stream`. */
+int sil_label_batch(const sil_job* jobs, int32_t njobs, const sil_params* p, void* stream);
+
 /* Human-readable text of a return code (static storage). */
 const char* sil_strerror(int code);
 

@@ -9,7 +9,8 @@
 // columns [4l, 4l + 4).  Each wave walks its 34 input rows (one halo row
 // above and below) once, keeping a three-row window of V = max(B,G,R) in
 // registers; horizontal neighbours come from the adjacent lanes through DPP
-// wave shifts and the two chip-edge halo columns are fetched once per wave.
+// wave shifts and the two chip-edge halo columns are fetched with each row,
+// at the point of the walk where the neighbouring chip reads those lines.
 // Even waves walk down and odd waves walk up, so the halo row two adjacent
 // waves share is read by both at about the same time (one HBM fetch).
 //   phase 1: 3x3 median (column sort + median of three triples, exact), the
@@ -27,7 +28,9 @@
 // contiguous run of chips in raster order: horizontally adjacent chips run
 // concurrently on one XCD and share their halo cache lines in its L2.
 //
-// filter = 0 uses a plain streaming kernel over the same tiling.
+// filter = 0 uses a plain streaming kernel over the same tiling.  A batched
+// launch (sil_label_batch) covers chip ranges of several scenes, each scene's
+// descriptor passed by value in the kernel arguments.
 
 #include <hip/hip_runtime.h>
 
@@ -46,7 +49,8 @@ constexpr int kRowsPerWave = 32;
 constexpr int kTile = kWaves * kRowsPerWave;  // 256: chip side handled per workgroup
 constexpr int kCopies = 32;                   // LDS histogram copies
 constexpr int kMaxPatchSlots = 1024;          // LDS per-patch counters per workgroup
-constexpr int kPrefetch = 4;                  // rows of loads in flight per wave
+constexpr int kPrefetch = 3;                  // rows of loads in flight per wave
+constexpr int kMaxBatch = SIL_BATCH_MAX_JOBS; // scenes per batched launch
 
 enum CountMode : uint32_t {
   CM_HIST_STORE = 0,   // patch == chip: counts from the chip histogram, plain store
@@ -55,17 +59,27 @@ enum CountMode : uint32_t {
   CM_PIX_GLOBAL = 3    // per-pixel counts straight to global atomics
 };
 
-struct KArgs {
-  const void* scene;
-  int64_t off[3];  // element offsets of the blue, green, red planes
-  int64_t pitch;
-  int32_t H, W;
+// Per-scene arguments.
+struct Scene {
+  const char* scene;     // planar bands, bytes
   uint8_t* labels;
-  int64_t lpitch;
   uint32_t* hist;
-  int32_t ny, nx, ph, pw;
-  sil_chip_info* chips;
-  int32_t chip, ncy, ncx, nchips, per_xcd;
+  sil_chip_info* chips;  // nullable
+  int64_t off[3];        // byte offsets of the blue, green, red planes
+  int64_t pitch;         // input row pitch, bytes
+  int64_t lpitch;        // label row pitch, bytes
+  int32_t H, W;
+  int32_t ny, nx;        // count array
+  int32_t ncx, nchips;   // chip grid
+  int32_t chip_begin;    // first chip (raster order) labelled by this launch
+  uint32_t vec;          // aligned rows: vector loads allowed
+  uint32_t label_vec;    // 4-byte label stores allowed
+  uint32_t pad;
+};
+
+// Arguments shared by every scene of a launch.
+struct Shared {
+  int32_t chip, ph, pw;
   // 16-bit rescale: V = ((min(x, x_sat) * 255 + half) * magic) >> shift
   uint32_t x_sat, half, magic, shift;
   uint32_t t1, t2;  // first V of class >= 1 and >= 2 (256 if none)
@@ -74,7 +88,13 @@ struct KArgs {
   uint32_t count_mode;
   uint32_t pix_store;  // CM_PIX_LDS: 1 plain store (patches nest in chips), 0 atomic
   int32_t npy_l, npx_l;
-  uint32_t label_vec;  // 4-byte label stores allowed
+};
+
+struct Batch {
+  Scene sc[kMaxBatch];
+  int32_t prefix[kMaxBatch + 1];  // chips of scenes [0, j) in this launch
+  int32_t n;
+  int32_t per_xcd;
 };
 
 __device__ __forceinline__ uint32_t min3u(uint32_t a, uint32_t b, uint32_t c) {
@@ -98,56 +118,72 @@ __device__ __forceinline__ uint32_t from_right(uint32_t v, uint32_t edge) {
                                                0xF, false);
 }
 
+// Workgroup id -> logical work index: XCD k = id % 8 gets the contiguous run
+// [k * per_xcd, (k+1) * per_xcd) in order.
+__device__ __forceinline__ int xcd_work_index(int per_xcd) {
+  const int b = blockIdx.x;
+  return (b & 7) * per_xcd + (b >> 3);
+}
+
 template <typename T>
-__device__ __forceinline__ uint32_t rescale(uint32_t x, const KArgs& a, bool fast24) {
+__device__ __forceinline__ uint32_t rescale(uint32_t x, const Shared& sh, bool fast24) {
   if constexpr (sizeof(T) == 1) {
     return x;
   } else {
-    uint32_t n = min(x, a.x_sat) * 255u + a.half;
+    uint32_t n = min(x, sh.x_sat) * 255u + sh.half;
     if (fast24) {
       // n < 2^24 and magic < 2^24 (checked on the host): 24-bit multiplies
-      uint64_t p = (uint64_t)(n & 0xFFFFFFu) * (uint64_t)(a.magic & 0xFFFFFFu);
-      return (uint32_t)(p >> a.shift);
+      uint64_t p = (uint64_t)(n & 0xFFFFFFu) * (uint64_t)(sh.magic & 0xFFFFFFu);
+      return (uint32_t)(p >> sh.shift);
     }
-    return (uint32_t)(((uint64_t)n * a.magic) >> a.shift);
+    return (uint32_t)(((uint64_t)n * sh.magic) >> sh.shift);
   }
 }
 
 // ---- loads ------------------------------------------------------------------
+//
+// Row bases are wave-uniform (scalar registers); each lane adds a 32-bit byte
+// offset, so every load is a scalar-base + vector-offset global load.
 
-// Raw 4-pixel row segments of the three bands.
+// Raw 4-pixel row segments of the three bands, plus one halo pixel per band
+// (lanes 0-31 fetch the chip's left halo column, lanes 32-63 its right one,
+// so every halo load instruction touches only two cache lines).
 template <typename T, bool VEC>
 struct Raw {
   uint32_t v[3][4];
+  uint32_t h[3];
 };
 template <>
 struct Raw<uint16_t, true> {
   uint2 v[3];
+  uint32_t h[3];
 };
 template <>
 struct Raw<uint8_t, true> {
   uint32_t v[3];
+  uint32_t h[3];
 };
 
-// Load columns [gx, gx+4) of row gy.  VEC: one aligned vector per band (the
-// caller guarantees gx + 3 < W and alignment).  Otherwise element loads with
-// columns clamped to W - 1.
+// Row gy (wave-uniform).  VEC: one aligned vector per band at coff[0] (the
+// caller guarantees the 4 columns lie inside the scene).  Otherwise element
+// loads at the 4 (clamped) column offsets coff[j].
 template <typename T, bool VEC>
-__device__ __forceinline__ void load_raw(const KArgs& a, int32_t gy, int32_t gx, Raw<T, VEC>& r) {
-  const T* base = (const T*)a.scene + (int64_t)gy * a.pitch;
-  if constexpr (VEC) {
-    if constexpr (sizeof(T) == 2) {
+__device__ __forceinline__ void load_raw(const Scene& sc, int32_t gy, const uint32_t coff[4],
+                                         uint32_t hoff, Raw<T, VEC>& r) {
+  const char* row = sc.scene + (int64_t)gy * sc.pitch;
 #pragma unroll
-      for (int b = 0; b < 3; ++b) r.v[b] = *(const uint2*)(base + a.off[b] + gx);
+  for (int b = 0; b < 3; ++b) {
+    const char* rb = row + sc.off[b];
+    if constexpr (VEC) {
+      if constexpr (sizeof(T) == 2)
+        r.v[b] = *(const uint2*)(rb + coff[0]);
+      else
+        r.v[b] = *(const uint32_t*)(rb + coff[0]);
     } else {
 #pragma unroll
-      for (int b = 0; b < 3; ++b) r.v[b] = *(const uint32_t*)(base + a.off[b] + gx);
+      for (int j = 0; j < 4; ++j) r.v[b][j] = *(const T*)(rb + coff[j]);
     }
-  } else {
-#pragma unroll
-    for (int b = 0; b < 3; ++b)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) r.v[b][j] = base[a.off[b] + min(gx + j, a.W - 1)];
+    r.h[b] = *(const T*)(rb + hoff);
   }
 }
 
@@ -176,14 +212,6 @@ __device__ __forceinline__ void max_bands(const Raw<T, VEC>& r, uint32_t x[4]) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) x[j] = max3u(r.v[0][j], r.v[1][j], r.v[2][j]);
   }
-}
-
-// One pixel: max over the bands at (gy, gx), gx clamped into [0, W).
-template <typename T>
-__device__ __forceinline__ uint32_t max_bands_at(const KArgs& a, int32_t gy, int32_t gx) {
-  gx = min(max(gx, 0), a.W - 1);
-  const T* base = (const T*)a.scene + (int64_t)gy * a.pitch + gx;
-  return max3u(base[a.off[0]], base[a.off[1]], base[a.off[2]]);
 }
 
 // ---- wave helpers -----------------------------------------------------------
@@ -224,7 +252,7 @@ struct PixCount {
   uint32_t cnt;  // three 10-bit class counters
 };
 
-__device__ __forceinline__ void pix_flush(const KArgs& a, uint32_t* s_cnt, bool lds, int32_t key,
+__device__ __forceinline__ void pix_flush(const Scene& sc, uint32_t* s_cnt, bool lds, int32_t key,
                                           uint32_t cnt) {
   if (cnt == 0) return;
   uint32_t c[3] = {cnt & 1023u, (cnt >> 10) & 1023u, cnt >> 20};
@@ -235,14 +263,14 @@ __device__ __forceinline__ void pix_flush(const KArgs& a, uint32_t* s_cnt, bool 
   } else {
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-      if (c[k]) atomicAdd(&a.hist[(int64_t)key * 3 + k], c[k]);
+      if (c[k]) atomicAdd(&sc.hist[(int64_t)key * 3 + k], c[k]);
   }
 }
 
-__device__ __forceinline__ void pix_add(const KArgs& a, uint32_t* s_cnt, bool lds, PixCount& pc,
+__device__ __forceinline__ void pix_add(const Scene& sc, uint32_t* s_cnt, bool lds, PixCount& pc,
                                         int32_t key, uint32_t cls) {
   if (key != pc.key) {
-    pix_flush(a, s_cnt, lds, pc.key, pc.cnt);
+    pix_flush(sc, s_cnt, lds, pc.key, pc.cnt);
     pc.key = key;
     pc.cnt = 0;
   }
@@ -250,34 +278,32 @@ __device__ __forceinline__ void pix_add(const KArgs& a, uint32_t* s_cnt, bool ld
 }
 
 // Copy a workgroup's LDS patch counters to the global counts.
-__device__ __forceinline__ void pix_publish(const KArgs& a, const uint32_t* s_cnt, int32_t y0,
-                                            int32_t ch, int32_t x0, int32_t cw) {
-  const int32_t py0 = y0 / a.ph, px0 = x0 / a.pw;
-  const int32_t npy = (y0 + ch - 1) / a.ph - py0 + 1;
-  const int32_t npx = (x0 + cw - 1) / a.pw - px0 + 1;
+__device__ __forceinline__ void pix_publish(const Shared& sh, const Scene& sc,
+                                            const uint32_t* s_cnt, int32_t y0, int32_t ch,
+                                            int32_t x0, int32_t cw) {
+  const int32_t py0 = y0 / sh.ph, px0 = x0 / sh.pw;
+  const int32_t npy = (y0 + ch - 1) / sh.ph - py0 + 1;
+  const int32_t npx = (x0 + cw - 1) / sh.pw - px0 + 1;
   for (int32_t i = threadIdx.x; i < npy * npx * 3; i += kThreads) {
     int32_t k = i % 3, slot = i / 3;
     int32_t ly = slot / npx, lx = slot - ly * npx;
-    uint32_t v = s_cnt[(ly * a.npx_l + lx) * 3 + k];
-    uint32_t* dst = &a.hist[((int64_t)(py0 + ly) * a.nx + (px0 + lx)) * 3 + k];
-    if (a.pix_store)
+    uint32_t v = s_cnt[(ly * sh.npx_l + lx) * 3 + k];
+    uint32_t* dst = &sc.hist[((int64_t)(py0 + ly) * sc.nx + (px0 + lx)) * 3 + k];
+    if (sh.pix_store)
       *dst = v;
     else if (v)
       atomicAdd(dst, v);
   }
 }
 
-// ---- stores -----------------------------------------------------------------
-
-// Store 4 packed labels of row gy at chip-relative columns [c, c+4); valid_n
-// of them (0..4) lie inside the chip.
-__device__ __forceinline__ void store_labels(const KArgs& a, int32_t gy, int32_t gx, int valid_n,
+// Store 4 packed labels at byte offset `off` of a label row; valid_n (0..4)
+// of them lie inside the chip.
+__device__ __forceinline__ void store_labels(uint8_t* row, uint32_t off, int valid_n, bool vec4,
                                              uint32_t packed) {
-  uint8_t* dst = a.labels + (int64_t)gy * a.lpitch + gx;
-  if (valid_n == 4 && a.label_vec) {
-    *(uint32_t*)dst = packed;
+  if (valid_n == 4 && vec4) {
+    *(uint32_t*)(row + off) = packed;
   } else {
-    for (int j = 0; j < valid_n; ++j) dst[j] = (uint8_t)(packed >> (8 * j));
+    for (int j = 0; j < valid_n; ++j) row[off + j] = (uint8_t)(packed >> (8 * j));
   }
 }
 
@@ -291,56 +317,59 @@ struct FilterLds {
 };
 
 // Phase 1 for one wave: walk 34 rows, median, rescale, histogram, keep the
-// packed 8-bit medians in vm[].
+// packed 8-bit medians in vm[].  `wave` is wave-uniform.
 template <typename T, bool VEC, bool FAST24>
-__device__ __forceinline__ void filter_phase1(const KArgs& a, FilterLds& s, int32_t y0, int32_t x0,
-                                              int32_t ch, int32_t cw, int wave, int lane,
-                                              uint32_t vm[kRowsPerWave]) {
+__device__ __forceinline__ void filter_phase1(const Shared& sh, const Scene& sc, FilterLds& s,
+                                              int32_t y0, int32_t x0, int32_t ch, int32_t cw,
+                                              int wave, int lane, uint32_t vm[kRowsPerWave]) {
   const bool down = (wave & 1) == 0;
   const int32_t wy0 = wave * kRowsPerWave;
   const int32_t gx = x0 + 4 * lane;
 
-  // input row of walk step s (0..33): chip row -1..32 (down) or 32..-1 (up)
+  // input row of walk step st (0..33): chip row -1..32 (down) or 32..-1 (up)
   auto row_of = [&](int st) -> int32_t {
     int32_t r = down ? st - 1 : kRowsPerWave - st;
-    return min(max(y0 + wy0 + r, 0), a.H - 1);
+    return min(max(y0 + wy0 + r, 0), sc.H - 1);
   };
 
-  // Halo columns of the chip, one value per walk step held by lane `step`.
-  int32_t hstep = min(lane, kRowsPerWave + 1);
-  uint32_t halo_l = max_bands_at<T>(a, row_of(hstep), x0 - 1);
-  uint32_t halo_r = max_bands_at<T>(a, row_of(hstep), x0 + 4 * 64);
+  uint32_t coff[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) coff[j] = (uint32_t)(min(gx + j, sc.W - 1) * (int)sizeof(T));
+  // Halo column fetched by this lane with every row (clamped into the scene).
+  const uint32_t hoff =
+      (uint32_t)(min(max(lane < 32 ? x0 - 1 : x0 + 4 * 64, 0), sc.W - 1) * (int)sizeof(T));
 
   // columns of this lane that lie inside the chip
   const int valid_cols = min(max(cw - 4 * lane, 0), 4);
-  const uint32_t copy = (uint32_t)(lane & (kCopies - 1));
+  const uint32_t hist_lane = (uint32_t)(lane & (kCopies - 1));
 
   Raw<T, VEC> ring[kPrefetch];
 #pragma unroll
-  for (int p = 0; p < kPrefetch; ++p) load_raw<T, VEC>(a, row_of(p), gx, ring[p]);
+  for (int p = 0; p < kPrefetch; ++p) load_raw<T, VEC>(sc, row_of(p), coff, hoff, ring[p]);
 
-  uint32_t w0[6], w1[6], w2[6];  // rows at steps s-2, s-1, s: [left, 4 own, right]
+  uint32_t w0[6], w1[6] = {0, 0, 0, 0, 0, 0}, w2[6] = {0, 0, 0, 0, 0, 0};
 
 #pragma unroll
   for (int st = 0; st < kRowsPerWave + 2; ++st) {
     uint32_t x[4];
-    max_bands<T, VEC>(ring[st % kPrefetch], x);
+    const Raw<T, VEC>& cur = ring[st % kPrefetch];
+    max_bands<T, VEC>(cur, x);
+    // lane 0 takes the left halo, lane 63 the right one (as the DPP fill value)
+    const uint32_t hv = max3u(cur.h[0], cur.h[1], cur.h[2]);
     if (st + kPrefetch < kRowsPerWave + 2)
-      load_raw<T, VEC>(a, row_of(st + kPrefetch), gx, ring[st % kPrefetch]);
+      load_raw<T, VEC>(sc, row_of(st + kPrefetch), coff, hoff, ring[st % kPrefetch]);
 
-    uint32_t hl = (uint32_t)__builtin_amdgcn_readlane((int)halo_l, st);
-    uint32_t hr = (uint32_t)__builtin_amdgcn_readlane((int)halo_r, st);
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
       w0[c] = w1[c];
       w1[c] = w2[c];
     }
-    w2[0] = from_left(x[3], hl);
+    w2[0] = from_left(x[3], hv);
     w2[1] = x[0];
     w2[2] = x[1];
     w2[3] = x[2];
     w2[4] = x[3];
-    w2[5] = from_right(x[0], hr);
+    w2[5] = from_right(x[0], hv);
     if (st < 2) continue;
 
     // output row of this step (chip-relative)
@@ -360,8 +389,8 @@ __device__ __forceinline__ void filter_phase1(const KArgs& a, FilterLds& s, int3
     for (int j = 0; j < 4; ++j) {
       uint32_t m = med3u(max3u(lo[j], lo[j + 1], lo[j + 2]), med3u(mi[j], mi[j + 1], mi[j + 2]),
                          min3u(hi[j], hi[j + 1], hi[j + 2]));
-      uint32_t v = rescale<T>(m, a, FAST24);
-      atomicAdd(&s.hist[(v << 5) | copy], j < nvalid ? 1u : 0u);
+      uint32_t v = rescale<T>(m, sh, FAST24);
+      atomicAdd(&s.hist[(v << 5) | hist_lane], j < nvalid ? 1u : 0u);
       packed |= v << (8 * j);
     }
     vm[k] = packed;
@@ -369,8 +398,8 @@ __device__ __forceinline__ void filter_phase1(const KArgs& a, FilterLds& s, int3
 }
 
 // Phase 2: exact chip statistics in one wave; writes the class table.
-__device__ void filter_phase2(const KArgs& a, FilterLds& s, int chip_id, int32_t y0, int32_t x0,
-                              int lane) {
+__device__ void filter_phase2(const Shared& sh, const Scene& sc, FilterLds& s, int chip_id,
+                              int32_t y0, int32_t x0, int lane) {
   uint32_t h[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) h[i] = s.hsum[4 * lane + i];
@@ -445,11 +474,11 @@ __device__ void filter_phase2(const KArgs& a, FilterLds& s, int chip_id, int32_t
   bool gate = false;
   if (have) {
     uint64_t var = (uint64_t)N * Q - (uint64_t)S * S;
-    gate = (u128)a.eta_den * bnum >= (u128)((uint64_t)a.eta_num * bden) * var;
+    gate = (u128)sh.eta_den * bnum >= (u128)((uint64_t)sh.eta_num * bden) * var;
   }
 
   // truncation levels at rank k from each tail
-  const uint32_t kk = N >> a.clip_shift;
+  const uint32_t kk = N >> sh.clip_shift;
   uint32_t lo_c = 256;
   int32_t hi_c = -1;
   {
@@ -477,7 +506,7 @@ __device__ void filter_phase2(const KArgs& a, FilterLds& s, int chip_id, int32_t
       uint32_t c = min(max(m, lo), hi);
       vc = ((c - lo) * 255u + (hi - lo) / 2u) / (hi - lo);
     }
-    const uint32_t cls = (vc >= a.t1) + (vc >= a.t2);
+    const uint32_t cls = (vc >= sh.t1) + (vc >= sh.t2);
     s.lut[m] = (uint8_t)cls;
     cc0 += cls == 0 ? h[i] : 0;
     cc1 += cls == 1 ? h[i] : 0;
@@ -491,7 +520,7 @@ __device__ void filter_phase2(const KArgs& a, FilterLds& s, int chip_id, int32_t
   const uint32_t a1 = wave_min32(a1c), a2 = wave_min32(a2c);
 
   if (lane == 0) {
-    if (a.chips) {
+    if (sc.chips) {
       sil_chip_info ci;
       ci.t = have ? (int32_t)bt : -1;
       ci.lo = (uint8_t)lo;
@@ -500,50 +529,49 @@ __device__ void filter_phase2(const KArgs& a, FilterLds& s, int chip_id, int32_t
       ci.stretch = stretch;
       ci.a1 = (uint16_t)a1;
       ci.a2 = (uint16_t)a2;
-      a.chips[chip_id] = ci;
+      sc.chips[chip_id] = ci;
     }
-    if (a.count_mode == CM_HIST_STORE || a.count_mode == CM_HIST_ATOMIC) {
-      const int64_t pidx = ((int64_t)(y0 / a.ph) * a.nx + (x0 / a.pw)) * 3;
-      if (a.count_mode == CM_HIST_STORE) {
-        a.hist[pidx + 0] = cc0;
-        a.hist[pidx + 1] = cc1;
-        a.hist[pidx + 2] = cc2;
+    if (sh.count_mode == CM_HIST_STORE || sh.count_mode == CM_HIST_ATOMIC) {
+      const int64_t pidx = ((int64_t)(y0 / sh.ph) * sc.nx + (x0 / sh.pw)) * 3;
+      if (sh.count_mode == CM_HIST_STORE) {
+        sc.hist[pidx + 0] = cc0;
+        sc.hist[pidx + 1] = cc1;
+        sc.hist[pidx + 2] = cc2;
       } else {
-        atomicAdd(&a.hist[pidx + 0], cc0);
-        atomicAdd(&a.hist[pidx + 1], cc1);
-        atomicAdd(&a.hist[pidx + 2], cc2);
+        atomicAdd(&sc.hist[pidx + 0], cc0);
+        atomicAdd(&sc.hist[pidx + 1], cc1);
+        atomicAdd(&sc.hist[pidx + 2], cc2);
       }
     }
   }
 }
 
-template <typename T, bool VEC, bool FAST24>
-__global__ __launch_bounds__(kThreads, 4) void k_filter(KArgs a) {
-  __shared__ FilterLds s;
-  const int b = blockIdx.x;
-  const int chip_id = (b & 7) * a.per_xcd + (b >> 3);
-  if (chip_id >= a.nchips) return;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int32_t cy = chip_id / a.ncx, cx = chip_id - cy * a.ncx;
-  const int32_t y0 = cy * a.chip, x0 = cx * a.chip;
-  const int32_t ch = min(a.chip, a.H - y0), cw = min(a.chip, a.W - x0);
+// One chip, all three phases, by the whole workgroup.
+template <typename T, bool FAST24>
+__device__ __forceinline__ void filter_chip(const Shared& sh, const Scene& sc, int chip_id,
+                                            FilterLds& s) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int32_t cy = chip_id / sc.ncx, cx = chip_id - cy * sc.ncx;
+  const int32_t y0 = cy * sh.chip, x0 = cx * sh.chip;
+  const int32_t ch = min(sh.chip, sc.H - y0), cw = min(sh.chip, sc.W - x0);
   const bool active = wave * kRowsPerWave < ch;
-  const bool pix = a.count_mode >= CM_PIX_LDS;
-  const bool pix_lds = a.count_mode == CM_PIX_LDS;
+  const bool pix = sh.count_mode >= CM_PIX_LDS;
+  const bool pix_lds = sh.count_mode == CM_PIX_LDS;
 
   for (int i = threadIdx.x; i < 256 * kCopies / 4; i += kThreads)
     ((uint4*)s.hist)[i] = make_uint4(0, 0, 0, 0);
   if (pix_lds)
-    for (int i = threadIdx.x; i < a.npy_l * a.npx_l * 3; i += kThreads) s.cnt[i] = 0;
+    for (int i = threadIdx.x; i < sh.npy_l * sh.npx_l * 3; i += kThreads) s.cnt[i] = 0;
   __syncthreads();
 
   uint32_t vm[kRowsPerWave];
   if (active) {
-    // Whole-vector loads need every lane's 4 columns inside the scene.
-    if (VEC && x0 + 4 * 64 <= a.W)
-      filter_phase1<T, VEC, FAST24>(a, s, y0, x0, ch, cw, wave, lane, vm);
+    // whole-vector loads need aligned rows and every lane's 4 columns inside the scene
+    if (sc.vec && x0 + 4 * 64 <= sc.W)
+      filter_phase1<T, true, FAST24>(sh, sc, s, y0, x0, ch, cw, wave, lane, vm);
     else
-      filter_phase1<T, false, FAST24>(a, s, y0, x0, ch, cw, wave, lane, vm);
+      filter_phase1<T, false, FAST24>(sh, sc, s, y0, x0, ch, cw, wave, lane, vm);
   }
   __syncthreads();
 
@@ -555,7 +583,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_filter(KArgs a) {
     s.hsum[bin] = sum;
   }
   __syncthreads();
-  if (wave == 0) filter_phase2(a, s, chip_id, y0, x0, lane);
+  if (wave == 0) filter_phase2(sh, sc, s, chip_id, y0, x0, lane);
   __syncthreads();
 
   if (active) {
@@ -563,12 +591,14 @@ __global__ __launch_bounds__(kThreads, 4) void k_filter(KArgs a) {
     const int32_t wy0 = wave * kRowsPerWave;
     const int valid_cols = min(max(cw - 4 * lane, 0), 4);
     const int32_t gx = x0 + 4 * lane;
+    const uint32_t loff = (uint32_t)gx;
+    const bool vec4 = sc.label_vec != 0;
     PixCount pc{-1, 0};
-    int32_t colkey[4];
+    int32_t colkey[4] = {0, 0, 0, 0};
     if (pix) {
-      const int32_t px_base = pix_lds ? x0 / a.pw : 0;
+      const int32_t px_base = pix_lds ? x0 / sh.pw : 0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) colkey[j] = min(gx + j, a.W - 1) / a.pw - px_base;
+      for (int j = 0; j < 4; ++j) colkey[j] = min(gx + j, sc.W - 1) / sh.pw - px_base;
     }
 #pragma unroll
     for (int k = 0; k < kRowsPerWave; ++k) {
@@ -580,74 +610,106 @@ __global__ __launch_bounds__(kThreads, 4) void k_filter(KArgs a) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) cls[j] = s.lut[(v >> (8 * j)) & 0xFFu];
       const uint32_t packed = cls[0] | (cls[1] << 8) | (cls[2] << 16) | (cls[3] << 24);
-      if (valid_cols > 0) store_labels(a, gy, gx, valid_cols, packed);
+      if (valid_cols > 0) store_labels(sc.labels + (int64_t)gy * sc.lpitch, loff, valid_cols, vec4,
+                                       packed);
       if (pix) {
-        const int32_t py = gy / a.ph - (pix_lds ? y0 / a.ph : 0);
-        const int32_t rowkey = py * (pix_lds ? a.npx_l : a.nx);
-        for (int j = 0; j < valid_cols; ++j) pix_add(a, s.cnt, pix_lds, pc, rowkey + colkey[j], cls[j]);
+        const int32_t py = gy / sh.ph - (pix_lds ? y0 / sh.ph : 0);
+        const int32_t rowkey = py * (pix_lds ? sh.npx_l : sc.nx);
+        for (int j = 0; j < valid_cols; ++j)
+          pix_add(sc, s.cnt, pix_lds, pc, rowkey + colkey[j], cls[j]);
       }
     }
-    if (pix) pix_flush(a, s.cnt, pix_lds, pc.key, pc.cnt);
+    if (pix) pix_flush(sc, s.cnt, pix_lds, pc.key, pc.cnt);
   }
   if (pix_lds) {
     __syncthreads();
-    pix_publish(a, s.cnt, y0, ch, x0, cw);
+    pix_publish(sh, sc, s.cnt, y0, ch, x0, cw);
   }
+}
+
+template <typename T, bool FAST24>
+__global__ __launch_bounds__(kThreads, 4) void k_filter(Shared sh, Scene sc, int per_xcd) {
+  __shared__ FilterLds s;
+  const int chip_id = xcd_work_index(per_xcd);
+  if (chip_id >= sc.nchips) return;
+  filter_chip<T, FAST24>(sh, sc, chip_id, s);
+}
+
+// Chips of up to kMaxBatch scenes in one launch: scene j contributes chips
+// [chip_begin, chip_begin + prefix[j+1] - prefix[j]).
+template <typename T, bool FAST24>
+__global__ __launch_bounds__(kThreads, 4) void k_filter_batch(Shared sh, Batch bt) {
+  __shared__ FilterLds s;
+  const int i = xcd_work_index(bt.per_xcd);
+  if (i >= bt.prefix[bt.n]) return;
+  int j = 0;
+  while (j + 1 < bt.n && bt.prefix[j + 1] <= i) ++j;
+  const Scene& sc = bt.sc[j];
+  filter_chip<T, FAST24>(sh, sc, sc.chip_begin + (i - bt.prefix[j]), s);
 }
 
 // ---- filter = 0: thresholds only ----------------------------------------------
 
 template <typename T, bool VEC>
-__global__ __launch_bounds__(kThreads, 4) void k_thresh(KArgs a) {
-  __shared__ uint32_t s_cnt[kMaxPatchSlots * 3];
-  const int b = blockIdx.x;
-  const int tile_id = (b & 7) * a.per_xcd + (b >> 3);
-  if (tile_id >= a.nchips) return;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int32_t ty = tile_id / a.ncx, tx = tile_id - ty * a.ncx;
-  const int32_t y0 = ty * kTile, x0 = tx * kTile;
-  const int32_t ch = min(kTile, a.H - y0), cw = min(kTile, a.W - x0);
-  const bool pix_lds = a.count_mode == CM_PIX_LDS;
-  if (pix_lds) {
-    for (int i = threadIdx.x; i < a.npy_l * a.npx_l * 3; i += kThreads) s_cnt[i] = 0;
-    __syncthreads();
-  }
+__device__ __forceinline__ void thresh_rows(const Shared& sh, const Scene& sc, uint32_t* s_cnt,
+                                            int32_t y0, int32_t x0, int32_t ch, int32_t cw,
+                                            int wave, int lane, bool pix_lds) {
   const int32_t wy0 = wave * kRowsPerWave;
-  if (wy0 < ch) {
-    const int32_t gx = x0 + 4 * lane;
-    const int valid_cols = min(max(cw - 4 * lane, 0), 4);
-    PixCount pc{-1, 0};
-    int32_t colkey[4];
-    const int32_t px_base = pix_lds ? x0 / a.pw : 0;
+  const int32_t gx = x0 + 4 * lane;
+  const int valid_cols = min(max(cw - 4 * lane, 0), 4);
+  uint32_t coff[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) colkey[j] = min(gx + j, a.W - 1) / a.pw - px_base;
-    const bool vec = VEC && x0 + 4 * 64 <= a.W;
-    for (int r = 0; r < kRowsPerWave && wy0 + r < ch; ++r) {
-      const int32_t gy = y0 + wy0 + r;
-      uint32_t x[4];
-      if (vec) {
-        Raw<T, VEC> raw;
-        load_raw<T, VEC>(a, gy, gx, raw);
-        max_bands<T, VEC>(raw, x);
-      } else {
-        Raw<T, false> raw;
-        load_raw<T, false>(a, gy, gx, raw);
-        max_bands<T, false>(raw, x);
-      }
-      uint32_t cls[4];
+  for (int j = 0; j < 4; ++j) coff[j] = (uint32_t)(min(gx + j, sc.W - 1) * (int)sizeof(T));
+  const bool vec4 = sc.label_vec != 0;
+  PixCount pc{-1, 0};
+  int32_t colkey[4];
+  const int32_t px_base = pix_lds ? x0 / sh.pw : 0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) cls[j] = (x[j] >= a.X1) + (x[j] >= a.X2);
-      const uint32_t packed = cls[0] | (cls[1] << 8) | (cls[2] << 16) | (cls[3] << 24);
-      if (valid_cols > 0) store_labels(a, gy, gx, valid_cols, packed);
-      const int32_t py = gy / a.ph - (pix_lds ? y0 / a.ph : 0);
-      const int32_t rowkey = py * (pix_lds ? a.npx_l : a.nx);
-      for (int j = 0; j < valid_cols; ++j) pix_add(a, s_cnt, pix_lds, pc, rowkey + colkey[j], cls[j]);
-    }
-    pix_flush(a, s_cnt, pix_lds, pc.key, pc.cnt);
+  for (int j = 0; j < 4; ++j) colkey[j] = min(gx + j, sc.W - 1) / sh.pw - px_base;
+  for (int r = 0; r < kRowsPerWave && wy0 + r < ch; ++r) {
+    const int32_t gy = y0 + wy0 + r;
+    Raw<T, VEC> raw;
+    load_raw<T, VEC>(sc, gy, coff, coff[0], raw);
+    uint32_t x[4];
+    max_bands<T, VEC>(raw, x);
+    uint32_t cls[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) cls[j] = (x[j] >= sh.X1) + (x[j] >= sh.X2);
+    const uint32_t packed = cls[0] | (cls[1] << 8) | (cls[2] << 16) | (cls[3] << 24);
+    if (valid_cols > 0)
+      store_labels(sc.labels + (int64_t)gy * sc.lpitch, (uint32_t)gx, valid_cols, vec4, packed);
+    const int32_t py = gy / sh.ph - (pix_lds ? y0 / sh.ph : 0);
+    const int32_t rowkey = py * (pix_lds ? sh.npx_l : sc.nx);
+    for (int j = 0; j < valid_cols; ++j)
+      pix_add(sc, s_cnt, pix_lds, pc, rowkey + colkey[j], cls[j]);
+  }
+  pix_flush(sc, s_cnt, pix_lds, pc.key, pc.cnt);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads, 4) void k_thresh(Shared sh, Scene sc, int per_xcd) {
+  __shared__ uint32_t s_cnt[kMaxPatchSlots * 3];
+  const int tile_id = xcd_work_index(per_xcd);
+  if (tile_id >= sc.nchips) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int32_t ty = tile_id / sc.ncx, tx = tile_id - ty * sc.ncx;
+  const int32_t y0 = ty * kTile, x0 = tx * kTile;
+  const int32_t ch = min(kTile, sc.H - y0), cw = min(kTile, sc.W - x0);
+  const bool pix_lds = sh.count_mode == CM_PIX_LDS;
+  if (pix_lds) {
+    for (int i = threadIdx.x; i < sh.npy_l * sh.npx_l * 3; i += kThreads) s_cnt[i] = 0;
+    __syncthreads();
+  }
+  if (wave * kRowsPerWave < ch) {
+    if (sc.vec && x0 + 4 * 64 <= sc.W)
+      thresh_rows<T, true>(sh, sc, s_cnt, y0, x0, ch, cw, wave, lane, pix_lds);
+    else
+      thresh_rows<T, false>(sh, sc, s_cnt, y0, x0, ch, cw, wave, lane, pix_lds);
   }
   if (pix_lds) {
     __syncthreads();
-    pix_publish(a, s_cnt, y0, ch, x0, cw);
+    pix_publish(sh, sc, s_cnt, y0, ch, x0, cw);
   }
 }
 
@@ -658,6 +720,8 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
 }
 
 // ---- host side ----------------------------------------------------------------
+
+static_assert(sizeof(Batch) + sizeof(Shared) <= 3584, "kernel arguments must stay under 4 KiB");
 
 // Host copy of the 16->8-bit rescale, used only to derive kernel constants.
 uint32_t host_rescale(uint32_t x, uint32_t d) {
@@ -736,9 +800,8 @@ int v_class_table(const sil_params* p, int cls[256]) {
   return SIL_OK;
 }
 
-int validate(int32_t nbands, const int32_t* sel, int32_t H, int32_t W, int64_t pitch,
-             int64_t label_pitch, const sil_params* p) {
-  if (!p || !sel) return SIL_EINVAL;
+int validate_params(const sil_params* p) {
+  if (!p) return SIL_EINVAL;
   if (p->abi != SIL_ABI_VERSION) return SIL_EINVAL;
   if (p->dtype != SIL_U8 && p->dtype != SIL_U16) return SIL_EINVAL;
   if (p->dtype == SIL_U16 && p->refl_max < 1) return SIL_EINVAL;
@@ -746,9 +809,6 @@ int validate(int32_t nbands, const int32_t* sel, int32_t H, int32_t W, int64_t p
     return SIL_EINVAL;
   if (p->eta_den < 1 || p->eta_num > p->eta_den) return SIL_EINVAL;
   if (p->patch_h < 1 || p->patch_w < 1) return SIL_EINVAL;
-  if (H < 1 || W < 1 || nbands < 1 || pitch < W || label_pitch < W) return SIL_EINVAL;
-  for (int i = 0; i < 3; ++i)
-    if (sel[i] < 0 || sel[i] >= nbands) return SIL_EINVAL;
   int cls[256];
   int rc = v_class_table(p, cls);
   if (rc != SIL_OK) return rc;
@@ -759,32 +819,112 @@ int validate(int32_t nbands, const int32_t* sel, int32_t H, int32_t W, int64_t p
     if (cls[v] < cls[v - 1]) return SIL_EUNSUPPORTED;
   if (p->filter == 1 && p->chip > 256) return SIL_EUNSUPPORTED;
   if (p->dtype == SIL_U16 && p->refl_max > 65535) return SIL_EUNSUPPORTED;
-  if ((int64_t)nbands * H > INT64_MAX / pitch) return SIL_EUNSUPPORTED;
-  if ((int64_t)H > INT64_MAX / label_pitch) return SIL_EUNSUPPORTED;
   return SIL_OK;
 }
 
-template <typename T>
-void launch_typed(const KArgs& a, bool vec, bool fast24, int filter, int grid,
-                  hipStream_t stream) {
-  if (filter == 1) {
-    if (vec) {
-      if (fast24)
-        hipLaunchKernelGGL((k_filter<T, true, true>), dim3(grid), dim3(kThreads), 0, stream, a);
-      else
-        hipLaunchKernelGGL((k_filter<T, true, false>), dim3(grid), dim3(kThreads), 0, stream, a);
-    } else {
-      if (fast24)
-        hipLaunchKernelGGL((k_filter<T, false, true>), dim3(grid), dim3(kThreads), 0, stream, a);
-      else
-        hipLaunchKernelGGL((k_filter<T, false, false>), dim3(grid), dim3(kThreads), 0, stream, a);
+int validate(int32_t nbands, const int32_t* sel, int32_t H, int32_t W, int64_t pitch,
+             int64_t label_pitch, const sil_params* p) {
+  if (!p || !sel) return SIL_EINVAL;
+  int rc = validate_params(p);
+  if (rc == SIL_EINVAL) return rc;
+  if (H < 1 || W < 1 || nbands < 1 || pitch < W || label_pitch < W) return SIL_EINVAL;
+  for (int i = 0; i < 3; ++i)
+    if (sel[i] < 0 || sel[i] >= nbands) return SIL_EINVAL;
+  if (rc != SIL_OK) return rc;
+  const int64_t esize = p->dtype == SIL_U16 ? 2 : 1;
+  if ((int64_t)nbands * H > INT64_MAX / (pitch * esize)) return SIL_EUNSUPPORTED;
+  if ((int64_t)H > INT64_MAX / label_pitch) return SIL_EUNSUPPORTED;
+  if ((int64_t)W * esize + 1024 > INT32_MAX) return SIL_EUNSUPPORTED;  // 32-bit lane offsets
+  return SIL_OK;
+}
+
+// Launch-wide constants from validated parameters.  `tile` is the chip side
+// (filter = 1) or the streaming tile (filter = 0).
+bool derive_shared(const sil_params* p, int32_t tile, Shared* sh, bool* fast24) {
+  memset(sh, 0, sizeof(*sh));
+  sh->chip = tile;
+  sh->ph = (int32_t)p->patch_h;
+  sh->pw = (int32_t)p->patch_w;
+  sh->clip_shift = p->clip_shift;
+  sh->eta_num = p->eta_num;
+  sh->eta_den = p->eta_den;
+  int cls[256];
+  v_class_table(p, cls);
+  sh->t1 = 256;
+  sh->t2 = 256;
+  for (int v = 255; v >= 0; --v) {
+    if (cls[v] >= 1) sh->t1 = (uint32_t)v;
+    if (cls[v] >= 2) sh->t2 = (uint32_t)v;
+  }
+  *fast24 = false;
+  if (p->dtype == SIL_U16) {
+    RescaleConst rc;
+    if (!derive_rescale(p->refl_max, &rc)) return false;
+    sh->x_sat = rc.x_sat;
+    sh->half = rc.half;
+    sh->magic = rc.magic;
+    sh->shift = rc.shift;
+    *fast24 = rc.fast24;
+    // raw-value boundaries for filter = 0
+    sh->X1 = 65536;
+    sh->X2 = 65536;
+    for (uint32_t x = 65536; x-- > 0;) {
+      uint32_t v = host_rescale(x, p->refl_max);
+      if (v >= sh->t1) sh->X1 = x;
+      if (v >= sh->t2) sh->X2 = x;
     }
   } else {
-    if (vec)
-      hipLaunchKernelGGL((k_thresh<T, true>), dim3(grid), dim3(kThreads), 0, stream, a);
-    else
-      hipLaunchKernelGGL((k_thresh<T, false>), dim3(grid), dim3(kThreads), 0, stream, a);
+    sh->X1 = sh->t1;
+    sh->X2 = sh->t2;
   }
+  return true;
+}
+
+void fill_scene(const void* scene, const int32_t* sel, int32_t H, int32_t W, int64_t pitch,
+                const sil_params* p, uint8_t* labels, int64_t label_pitch, uint32_t* hist,
+                sil_chip_info* chips, int32_t tile, Scene* sc) {
+  memset(sc, 0, sizeof(*sc));
+  const int64_t esize = p->dtype == SIL_U16 ? 2 : 1;
+  sc->scene = (const char*)scene;
+  sc->labels = labels;
+  sc->hist = hist;
+  sc->chips = p->filter == 1 ? chips : nullptr;
+  for (int b = 0; b < 3; ++b) sc->off[b] = (int64_t)sel[b] * H * pitch * esize;
+  sc->pitch = pitch * esize;
+  sc->lpitch = label_pitch;
+  sc->H = H;
+  sc->W = W;
+  sil_hist_dims(H, W, p, &sc->ny, &sc->nx);
+  sc->ncx = (W + tile - 1) / tile;
+  sc->nchips = ((H + tile - 1) / tile) * sc->ncx;
+  // vector loads need 4-pixel-aligned rows and chip origins
+  const uintptr_t vbytes = 4 * (uintptr_t)esize;
+  sc->vec = ((uintptr_t)scene % vbytes == 0) && ((pitch * esize) % (int64_t)vbytes == 0) &&
+            (tile % 4 == 0);
+  sc->label_vec = ((uintptr_t)labels % 4 == 0) && (label_pitch % 4 == 0) && (tile % 4 == 0);
+}
+
+template <typename T>
+void launch_single(const Shared& sh, const Scene& sc, bool fast24, int filter, int per_xcd,
+                   hipStream_t stream) {
+  const dim3 grid(per_xcd * 8), block(kThreads);
+  if (filter == 1) {
+    if (fast24)
+      hipLaunchKernelGGL((k_filter<T, true>), grid, block, 0, stream, sh, sc, per_xcd);
+    else
+      hipLaunchKernelGGL((k_filter<T, false>), grid, block, 0, stream, sh, sc, per_xcd);
+  } else {
+    hipLaunchKernelGGL((k_thresh<T>), grid, block, 0, stream, sh, sc, per_xcd);
+  }
+}
+
+template <typename T>
+void launch_batch(const Shared& sh, const Batch& bt, bool fast24, hipStream_t stream) {
+  const dim3 grid(bt.per_xcd * 8), block(kThreads);
+  if (fast24)
+    hipLaunchKernelGGL((k_filter_batch<T, true>), grid, block, 0, stream, sh, bt);
+  else
+    hipLaunchKernelGGL((k_filter_batch<T, false>), grid, block, 0, stream, sh, bt);
 }
 
 }  // namespace
@@ -821,6 +961,14 @@ int sil_hist_dims(int32_t H, int32_t W, const sil_params* p, int32_t* ny, int32_
   return SIL_OK;
 }
 
+int sil_chip_count(int32_t H, int32_t W, const sil_params* p, int32_t* nchips) {
+  if (!p || !nchips || H < 1 || W < 1 || p->chip < 1) return SIL_EINVAL;
+  const int64_t n = (((int64_t)H + p->chip - 1) / p->chip) * (((int64_t)W + p->chip - 1) / p->chip);
+  if (n > INT32_MAX) return SIL_EUNSUPPORTED;
+  *nchips = (int32_t)n;
+  return SIL_OK;
+}
+
 int sil_validate(int32_t nbands, const int32_t sel[3], int32_t H, int32_t W, int64_t pitch,
                  int64_t label_pitch, const sil_params* p) {
   return validate(nbands, sel, H, W, pitch, label_pitch, p);
@@ -843,103 +991,92 @@ int sil_label(const void* scene, int32_t nbands, const int32_t sel[3], int32_t H
   int rc = validate(nbands, sel, H, W, pitch, label_pitch, p);
   if (rc != SIL_OK) return rc;
 
-  KArgs a;
-  memset(&a, 0, sizeof(a));
-  a.scene = scene;
-  for (int b = 0; b < 3; ++b) a.off[b] = (int64_t)sel[b] * H * pitch;
-  a.pitch = pitch;
-  a.H = H;
-  a.W = W;
-  a.labels = labels;
-  a.lpitch = label_pitch;
-  a.hist = hist;
-  sil_hist_dims(H, W, p, &a.ny, &a.nx);
-  a.ph = (int32_t)p->patch_h;
-  a.pw = (int32_t)p->patch_w;
-  a.chips = p->filter == 1 ? chips : nullptr;
-  a.clip_shift = p->clip_shift;
-  a.eta_num = p->eta_num;
-  a.eta_den = p->eta_den;
-
   const int32_t tile = p->filter == 1 ? (int32_t)p->chip : kTile;
-  a.chip = tile;
-  a.ncy = (H + tile - 1) / tile;
-  a.ncx = (W + tile - 1) / tile;
-  const int64_t nchips = (int64_t)a.ncy * a.ncx;
+  const int64_t nchips = (((int64_t)H + tile - 1) / tile) * (((int64_t)W + tile - 1) / tile);
   if (nchips > (int64_t)INT32_MAX - 8) return SIL_EUNSUPPORTED;
-  a.nchips = (int32_t)nchips;
-  a.per_xcd = (int32_t)((nchips + 7) / 8);
-
-  int cls[256];
-  v_class_table(p, cls);
-  a.t1 = 256;
-  a.t2 = 256;
-  for (int v = 255; v >= 0; --v) {
-    if (cls[v] >= 1) a.t1 = (uint32_t)v;
-    if (cls[v] >= 2) a.t2 = (uint32_t)v;
-  }
-
-  RescaleConst rcst;
-  const size_t esize = p->dtype == SIL_U16 ? 2 : 1;
-  if (p->dtype == SIL_U16) {
-    if (!derive_rescale(p->refl_max, &rcst)) return SIL_EUNSUPPORTED;
-    a.x_sat = rcst.x_sat;
-    a.half = rcst.half;
-    a.magic = rcst.magic;
-    a.shift = rcst.shift;
-    // raw-value boundaries for filter = 0
-    a.X1 = 65536;
-    a.X2 = 65536;
-    for (uint32_t x = 65536; x-- > 0;) {
-      uint32_t v = host_rescale(x, p->refl_max);
-      if (v >= a.t1) a.X1 = x;
-      if (v >= a.t2) a.X2 = x;
-    }
-  } else {
-    a.X1 = a.t1;
-    a.X2 = a.t2;
-  }
+  Shared sh;
+  bool fast24;
+  if (!derive_shared(p, tile, &sh, &fast24)) return SIL_EUNSUPPORTED;
+  Scene sc;
+  fill_scene(scene, sel, H, W, pitch, p, labels, label_pitch, hist, chips, tile, &sc);
 
   // how the per-patch counts are produced
   bool zero_hist;
-  if (p->filter == 1 && a.ph == tile && a.pw == tile) {
-    a.count_mode = CM_HIST_STORE;
+  if (p->filter == 1 && sh.ph == tile && sh.pw == tile) {
+    sh.count_mode = CM_HIST_STORE;
     zero_hist = false;
-  } else if (p->filter == 1 && a.ph % tile == 0 && a.pw % tile == 0) {
-    a.count_mode = CM_HIST_ATOMIC;
+  } else if (p->filter == 1 && sh.ph % tile == 0 && sh.pw % tile == 0) {
+    sh.count_mode = CM_HIST_ATOMIC;
     zero_hist = true;
   } else {
-    a.npy_l = (tile - 1) / a.ph + 2;
-    a.npx_l = (tile - 1) / a.pw + 2;
-    if ((int64_t)a.npy_l * a.npx_l <= kMaxPatchSlots) {
-      a.count_mode = CM_PIX_LDS;
-      a.pix_store = (tile % a.ph == 0 && tile % a.pw == 0) ? 1u : 0u;
-      zero_hist = a.pix_store == 0;
+    sh.npy_l = (tile - 1) / sh.ph + 2;
+    sh.npx_l = (tile - 1) / sh.pw + 2;
+    if ((int64_t)sh.npy_l * sh.npx_l <= kMaxPatchSlots) {
+      sh.count_mode = CM_PIX_LDS;
+      sh.pix_store = (tile % sh.ph == 0 && tile % sh.pw == 0) ? 1u : 0u;
+      zero_hist = sh.pix_store == 0;
     } else {
-      a.count_mode = CM_PIX_GLOBAL;
+      sh.count_mode = CM_PIX_GLOBAL;
       zero_hist = true;
     }
   }
 
-  // vector paths need aligned rows and chip origins
-  const uintptr_t vbytes = 4 * esize;
-  const bool vec = ((uintptr_t)scene % vbytes == 0) && ((pitch * esize) % vbytes == 0) &&
-                   (tile % 4 == 0);
-  a.label_vec = ((uintptr_t)labels % 4 == 0) && (label_pitch % 4 == 0) && (tile % 4 == 0);
-
   hipStream_t st = (hipStream_t)stream;
   (void)hipGetLastError();
   if (zero_hist) {
-    int64_t n = (int64_t)a.ny * a.nx * 3;
+    int64_t n = (int64_t)sc.ny * sc.nx * 3;
     int g = (int)((n + 255) / 256);
     if (g > 4096) g = 4096;
     hipLaunchKernelGGL(k_fill_u32, dim3(g), dim3(256), 0, st, hist, n, 0u);
   }
-  const int grid = a.per_xcd * 8;
+  const int per_xcd = (int)((nchips + 7) / 8);
   if (p->dtype == SIL_U16)
-    launch_typed<uint16_t>(a, vec, rcst.fast24, (int)p->filter, grid, st);
+    launch_single<uint16_t>(sh, sc, fast24, (int)p->filter, per_xcd, st);
   else
-    launch_typed<uint8_t>(a, vec, false, (int)p->filter, grid, st);
+    launch_single<uint8_t>(sh, sc, false, (int)p->filter, per_xcd, st);
+  if (hipGetLastError() != hipSuccess) return SIL_EDEVICE;
+  return SIL_OK;
+}
+
+int sil_label_batch(const sil_job* jobs, int32_t njobs, const sil_params* p, void* stream) {
+  if (!jobs || njobs < 1 || njobs > SIL_BATCH_MAX_JOBS) return SIL_EINVAL;
+  int rc = validate_params(p);
+  if (rc != SIL_OK) return rc;
+  if (p->filter != 1 || p->patch_h != p->chip || p->patch_w != p->chip) return SIL_EUNSUPPORTED;
+  const int32_t tile = (int32_t)p->chip;
+  Shared sh;
+  bool fast24;
+  if (!derive_shared(p, tile, &sh, &fast24)) return SIL_EUNSUPPORTED;
+  sh.count_mode = CM_HIST_STORE;
+
+  Batch bt;
+  memset(&bt, 0, sizeof(bt));
+  int64_t total = 0;
+  for (int32_t j = 0; j < njobs; ++j) {
+    const sil_job& jb = jobs[j];
+    if (!jb.scene || !jb.labels || !jb.hist) return SIL_EINVAL;
+    rc = validate(jb.nbands, jb.sel, jb.H, jb.W, jb.pitch, jb.label_pitch, p);
+    if (rc != SIL_OK) return rc;
+    fill_scene(jb.scene, jb.sel, jb.H, jb.W, jb.pitch, p, jb.labels, jb.label_pitch, jb.hist,
+               jb.chips, tile, &bt.sc[j]);
+    if (jb.chip_begin < 0 || jb.chip_count < 1 ||
+        (int64_t)jb.chip_begin + jb.chip_count > bt.sc[j].nchips)
+      return SIL_EINVAL;
+    bt.sc[j].chip_begin = jb.chip_begin;
+    bt.prefix[j] = (int32_t)total;
+    total += jb.chip_count;
+    if (total > (int64_t)INT32_MAX - 8) return SIL_EUNSUPPORTED;
+  }
+  bt.prefix[njobs] = (int32_t)total;
+  bt.n = njobs;
+  bt.per_xcd = (int32_t)((total + 7) / 8);
+
+  hipStream_t st = (hipStream_t)stream;
+  (void)hipGetLastError();
+  if (p->dtype == SIL_U16)
+    launch_batch<uint16_t>(sh, bt, fast24, st);
+  else
+    launch_batch<uint8_t>(sh, bt, false, st);
   if (hipGetLastError() != hipSuccess) return SIL_EDEVICE;
   return SIL_OK;
 }

@@ -45,6 +45,24 @@ class _Params(ctypes.Structure):
 
 
 CHIP_INFO_BYTES = 12  # sil_chip_info: int32 t; u8 lo, hi, gate, stretch; u16 a1, a2
+BATCH_MAX_JOBS = 24
+
+
+class _Job(ctypes.Structure):
+    _fields_ = [
+        ("scene", ctypes.c_void_p),
+        ("nbands", ctypes.c_int32),
+        ("sel", ctypes.c_int32 * 3),
+        ("H", ctypes.c_int32),
+        ("W", ctypes.c_int32),
+        ("pitch", ctypes.c_int64),
+        ("labels", ctypes.c_void_p),
+        ("label_pitch", ctypes.c_int64),
+        ("hist", ctypes.c_void_p),
+        ("chips", ctypes.c_void_p),
+        ("chip_begin", ctypes.c_int32),
+        ("chip_count", ctypes.c_int32),
+    ]
 
 _lib = None
 
@@ -73,6 +91,11 @@ def lib() -> ctypes.CDLL:
                                 ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                 ctypes.c_void_p, ctypes.c_void_p]
         L.sil_label.restype = ctypes.c_int
+        L.sil_chip_count.argtypes = [ctypes.c_int32, ctypes.c_int32, P(_Params),
+                                     P(ctypes.c_int32)]
+        L.sil_chip_count.restype = ctypes.c_int
+        L.sil_label_batch.argtypes = [P(_Job), ctypes.c_int32, P(_Params), ctypes.c_void_p]
+        L.sil_label_batch.restype = ctypes.c_int
         L.sil_strerror.argtypes = [ctypes.c_int]
         L.sil_strerror.restype = ctypes.c_char_p
         if L.sil_abi_version() != ABI_VERSION:
@@ -200,3 +223,56 @@ def decode_chip_info(raw) -> list:
                    ("stretch", "u1"), ("a1", "<u2"), ("a2", "<u2")])
     arr = np.ascontiguousarray(np.asarray(raw, dtype=np.uint8))
     return arr.reshape(-1).view(dt).reshape(arr.shape[:-1])
+
+
+def chip_count(H: int, W: int, params: Params) -> int:
+    n = ctypes.c_int32()
+    p = params.to_c()
+    _check(lib().sil_chip_count(H, W, ctypes.byref(p), ctypes.byref(n)))
+    return n.value
+
+
+@dataclass
+class Job:
+    """One scene's share of a batched launch (``sil_job``).  ``scene`` is a
+    [nbands, H, pitch] GPU tensor; ``labels`` [H, >=W] uint8 and ``hist``
+    [ny, nx, 3] int32 are the scene's full output buffers; chips
+    [chip_begin, chip_begin + chip_count) are labelled by the call."""
+    scene: torch.Tensor
+    labels: torch.Tensor
+    hist: torch.Tensor
+    chip_begin: int
+    chip_count: int
+    W: Optional[int] = None
+    sel: Tuple[int, int, int] = (0, 1, 2)
+    chips: Optional[torch.Tensor] = None
+
+
+def make_job_struct(job: Job) -> _Job:
+    nb, H, pitch = job.scene.shape
+    j = _Job()
+    j.scene = job.scene.data_ptr()
+    j.nbands = nb
+    for i in range(3):
+        j.sel[i] = int(job.sel[i])
+    j.H = H
+    j.W = pitch if job.W is None else int(job.W)
+    j.pitch = pitch
+    j.labels = job.labels.data_ptr()
+    j.label_pitch = job.labels.stride(0)
+    j.hist = job.hist.data_ptr()
+    j.chips = job.chips.data_ptr() if job.chips is not None else None
+    j.chip_begin = int(job.chip_begin)
+    j.chip_count = int(job.chip_count)
+    return j
+
+
+def label_batch(jobs: Sequence[Job], params: Params,
+                stream: Optional[torch.cuda.Stream] = None) -> None:
+    """One ``sil_label_batch`` launch over the jobs' chip ranges (asynchronous)."""
+    if not jobs or len(jobs) > BATCH_MAX_JOBS:
+        raise ValueError(f"1..{BATCH_MAX_JOBS} jobs per batch")
+    arr = (_Job * len(jobs))(*[make_job_struct(j) for j in jobs])
+    s = stream if stream is not None else torch.cuda.current_stream(jobs[0].scene.device)
+    p = params.to_c()
+    _check(lib().sil_label_batch(arr, len(jobs), ctypes.byref(p), ctypes.c_void_p(s.cuda_stream)))

@@ -268,3 +268,58 @@ def test_errors_raise_before_launch(sil):
     assert e.value.code == sil.EUNSUPPORTED
     with pytest.raises(ValueError):
         sil.label(s, sil.Params(dtype=sil.U16))
+
+
+def test_batched_launches_equal_single_scene(sil):
+    """Chip ranges of several scenes labelled by sil_label_batch, split at
+    arbitrary chip boundaries over several launches, give exactly the
+    single-scene result (and so the oracle's)."""
+    rng = np.random.default_rng(21)
+    p = sil.Params(dtype=sil.U16)
+    scenes, refs, outs = [], [], []
+    for (H, W) in [(512, 512), (300, 1100), (1031, 777), (2048, 2048), (64, 64), (257, 513)]:
+        s16 = _rand_scene(rng, H, W, "u16", W)
+        dev = _to_dev(s16)
+        lab, hist = sil.label(dev, p)
+        ny, nx = hist.shape[:2]
+        refs.append((lab.clone(), hist.clone()))
+        outs.append((torch.full((H, W), 0xEE, dtype=torch.uint8, device="cuda"),
+                     torch.full((ny, nx, 3), -1, dtype=torch.int32, device="cuda")))
+        scenes.append(dev)
+    torch.cuda.synchronize()
+    # label every scene's chips in uneven pieces, interleaving scenes per launch
+    pending = [[0, sil.chip_count(s.shape[1], s.shape[2], p)] for s in scenes]
+    launches = 0
+    while any(b < n for b, n in pending):
+        jobs = []
+        for i, (b, n) in enumerate(pending):
+            if b < n and rng.random() < 0.8:
+                cnt = int(min(n - b, rng.integers(1, 40)))
+                jobs.append(sil.Job(scenes[i], outs[i][0], outs[i][1], b, cnt))
+                pending[i][0] += cnt
+        if jobs:
+            _say(f"case batch launch {launches}: {[(j.chip_begin, j.chip_count) for j in jobs]}")
+            sil.label_batch(jobs, p)
+            launches += 1
+    torch.cuda.synchronize()
+    assert launches > 3
+    for (rl, rh), (ol, oh) in zip(refs, outs):
+        assert torch.equal(rl, ol) and torch.equal(rh, oh)
+    # and the scenes agree with the oracle
+    s_np = scenes[2].cpu().numpy().view(np.uint16)
+    ol, oh = R.label(s_np, R.make_params(dtype=R.U16))
+    assert (outs[2][0].cpu().numpy() == ol).all() and (outs[2][1].cpu().numpy() == oh).all()
+
+
+def test_batch_rejects_bad_jobs(sil):
+    s = torch.zeros((3, 300, 300), dtype=torch.int16, device="cuda")
+    lab = torch.empty((300, 300), dtype=torch.uint8, device="cuda")
+    hist = torch.empty((2, 2, 3), dtype=torch.int32, device="cuda")
+    p = sil.Params(dtype=sil.U16)
+    with pytest.raises(sil.SilError) as e:
+        sil.label_batch([sil.Job(s, lab, hist, 3, 2)], p)  # chips 3..4 of 4
+    assert e.value.code == sil.EINVAL
+    with pytest.raises(sil.SilError) as e:
+        sil.label_batch([sil.Job(s, lab, hist, 0, 1)], sil.Params(dtype=sil.U16, patch_h=64,
+                                                                   patch_w=64))
+    assert e.value.code == sil.EUNSUPPORTED
