@@ -83,6 +83,71 @@ def calib_copy(nbytes=1 << 30, reps=3):
                       "ms": ms, "gbs": 2 * nbytes / ms / 1e6}), flush=True)
 
 
+def run_serving(n_requests, chips_per_launch, seeds_per_size=2):
+    """Continuous-batching server on the mixed-size request trace: capacity
+    (all requests arriving at once), p50/p99 latency under Poisson arrivals at
+    0.5 and 0.8 of capacity, and a bit-exactness pass in which every result
+    is compared with its scene's solo sil_label output."""
+    import numpy as np
+    import torch
+    from paper_2403_13135_amd import serve, sil
+
+    p = sil.Params(dtype=sil.U16)
+    pool = serve.make_pool(seeds_per_size=seeds_per_size)
+    refs = {}
+    for size, items in pool.items():
+        for i, (_, t) in enumerate(items):
+            lab, hist = sil.label(t, p)
+            refs[(size, i)] = (lab, hist)
+    torch.cuda.synchronize()
+    out = {"requests": n_requests, "sizes": list(serve.SIZES), "dtype": "u16",
+           "scenes_per_size": seeds_per_size, "chips_per_launch": chips_per_launch}
+
+    def play(rate, release, arena):
+        arr, picks = serve.make_trace(n_requests, rate, pool, seed=11)
+        scenes = [pool[sz][k][1] for sz, k in picks]
+        srv = serve.Server(p, arena_bytes=arena, max_chips_per_launch=chips_per_launch,
+                           max_inflight=4, nstreams=2)
+        comps, start = srv.run(scenes, arr, release=release)
+        st = srv.stats()
+        return srv, comps, start, arr, picks, st
+
+    px = lambda picks: sum(sz * sz for sz, _ in picks)
+    # capacity: every request present at t = 0
+    srv, comps, start, arr, picks, st = play(0.0, True, 8 << 30)
+    span = max(c.t_done_ms for c in comps) - start
+    cap_gpx = px(picks) / (span * 1e-3) / 1e9
+    cap_req_per_ms = n_requests / span
+    out["capacity"] = {"gpx_s": cap_gpx, "requests_per_s": cap_req_per_ms * 1e3,
+                       "span_ms": span, "launches": st["launches"]}
+    srv.close()
+    for rho in (0.5, 0.8):
+        srv, comps, start, arr, picks, st = play(rho * cap_req_per_ms, True, 8 << 30)
+        lat = np.array([c.t_done_ms - (start + a) for c, a in zip(comps, arr)])
+        span = max(c.t_done_ms for c in comps) - start
+        by_size = {}
+        for (sz, _), l in zip(picks, lat):
+            by_size.setdefault(sz, []).append(l)
+        out[f"rho_{rho}"] = {
+            "arrival_rate_per_s": rho * cap_req_per_ms * 1e3,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "throughput_gpx_s": px(picks) / (span * 1e-3) / 1e9, "launches": st["launches"],
+            "arena_peak_bytes": st["arena_peak"],
+            "p99_ms_by_size": {str(k): float(np.percentile(v, 99)) for k, v in by_size.items()}}
+        srv.close()
+    # bit-exactness: the burst again with every output kept, each compared
+    srv, comps, start, arr, picks, st = play(0.0, False, 80 << 30)
+    torch.cuda.synchronize()
+    exact = 0
+    for c, (sz, k) in zip(comps, picks):
+        lab, hist = refs[(sz, k)]
+        exact += int(torch.equal(c.labels(), lab) and torch.equal(c.hist(), hist))
+        srv.release(c.tag)
+    out["bit_exact"] = f"{exact}/{n_requests} results equal their scene's solo run"
+    srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +157,9 @@ def main():
     ap.add_argument("--pitch", type=int, default=PITCH)
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a 1 GiB device copy (for counter scaling)")
+    ap.add_argument("--skip-serving", action="store_true", help="omit the serving section")
+    ap.add_argument("--serving-requests", type=int, default=2000)
+    ap.add_argument("--chips-per-launch", type=int, default=1024)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -207,6 +275,12 @@ def main():
                "sample": f"the full {H}x{W} uint16 tile, one single-threaded run "
                          f"({dt:.1f} s); GPU output bit-identical: {ok}"}
 
+    serving = None
+    if not args.skip_serving:
+        del scene, labels, hist, labels0, hist0
+        torch.cuda.empty_cache()
+        serving = run_serving(args.serving_requests, args.chips_per_launch)
+
     out = {
         "metric": "auto-labelled Gpixel/s",
         "value": gpx_s,
@@ -238,6 +312,7 @@ def main():
             "thresholds_only_gpx_s": npx / (f0_ms / 1e3) / 1e9,
             "wall_s_timed_region": wall,
         },
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

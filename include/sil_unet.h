@@ -1,0 +1,142 @@
+/*
+ * sil_unet.h -- gfx950 kernels of the U-Net trained on the auto-labels
+ * (arXiv 2403.13135, section III-C "U-Net Model for Sea-Ice Classification":
+ * two 3x3 convolutions with ReLU per level, 2x2 max pooling with stride 2,
+ * 2x2 up-convolutions that halve the channels, concatenation with the skip
+ * map, a 1x1 convolution to the 3 classes; "U-Net Training": categorical
+ * cross-entropy and the Adam optimizer).  This build adds batch
+ * normalisation after each 3x3 convolution and uses "same" padding.
+ *
+ * Conventions:
+ *   - Activations are bf16, NHWC, contiguous ([N][H][W][C]); a "pixel" is one
+ *     (n, h, w); P = N*H*W.  Weights used by the convolutions are bf16; master
+ *     weights, gradients, statistics and the loss are fp32.
+ *   - 3x3 and up-convolutions run on MFMA (v_mfma_f32_16x16x32_bf16) with fp32
+ *     accumulation; all other steps are plain HIP kernels.
+ *   - Channel counts must be multiples of 8 (pad the 3-channel input to 8
+ *     with zeros); batch-norm and head channel counts must divide 256.
+ *     Violations: SIL_EINVAL.
+ *   - Every call is asynchronous on `stream` (hipStream_t or NULL), allocates
+ *     nothing and validates its sizes before enqueueing.  Outputs marked
+ *     "accumulate" are ADDED to (zero them first, e.g. sil_unet_fill_f32).
+ *   - Returns SIL_OK, SIL_EINVAL (NULL pointer, non-positive or unsupported
+ *     size) or SIL_EDEVICE (launch failure).
+ */
+#ifndef SIL_UNET_H
+#define SIL_UNET_H
+
+#include <stdint.h>
+
+#include "sil.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* 3x3 convolution, stride 1, zero padding 1, no bias.  The input is the
+ * channel concatenation of x0 [N][H][W][c0] and x1 [N][H][W][c1] (x1 NULL and
+ * c1 = 0 for a single input).  w: [cout][3][3][c0+c1].  y: [N][H][W][cout].
+ * stats (nullable, fp32 [2][cout], accumulate): per-channel sum and sum of
+ * squares of the fp32 outputs before rounding to bf16. */
+int sil_unet_conv3x3(const void* x0, int32_t c0, const void* x1, int32_t c1, const void* w,
+                     void* y, float* stats, int32_t N, int32_t H, int32_t W, int32_t cout,
+                     void* stream);
+
+/* Input gradient of sil_unet_conv3x3: dx = conv3x3(dy, wt) with wt the
+ * flipped, transposed weights [c0+c1][3][3][cout] (sil_unet_flip3x3).  The
+ * result is split by channel into dx0 [N][H][W][c0] and dx1 [..][c1]
+ * (dx1 NULL when c1 = 0). */
+int sil_unet_conv3x3_dgrad(const void* dy, int32_t cout, const void* wt, void* dx0, int32_t c0,
+                           void* dx1, int32_t c1, int32_t N, int32_t H, int32_t W, void* stream);
+
+/* Weight gradient of sil_unet_conv3x3 (accumulate): dw [cout][3][3][c0+c1] fp32
+ * += sum over pixels of dy (x) im2col(concat(x0, x1)). */
+int sil_unet_conv3x3_wgrad(const void* dy, int32_t cout, const void* x0, int32_t c0,
+                           const void* x1, int32_t c1, float* dw, int32_t N, int32_t H,
+                           int32_t W, void* stream);
+
+/* wt[ci][r][s][co] = w[co][2-r][2-s][ci] (bf16). */
+int sil_unet_flip3x3(const void* w, void* wt, int32_t cout, int32_t cin, void* stream);
+
+/* 2x2 up-convolution, stride 2 (transposed convolution): y[n][2h+i][2w+j][co]
+ * = b[co] + sum_ci x[n][h][w][ci] * w[i][j][co][ci].  x [N][H][W][cin],
+ * w bf16 [2][2][cout][cin], b fp32 [cout], y [N][2H][2W][cout]. */
+int sil_unet_upconv(const void* x, const void* w, const float* b, void* y, int32_t N, int32_t H,
+                    int32_t W, int32_t cin, int32_t cout, void* stream);
+
+/* Input gradient: dx[n][h][w][ci] = sum_{i,j,co} dy[n][2h+i][2w+j][co] *
+ * w[i][j][co][ci], with wt = the weights as [ci][2][2][co] (sil_unet_up_t). */
+int sil_unet_upconv_dgrad(const void* dy, const void* wt, void* dx, int32_t N, int32_t H,
+                          int32_t W, int32_t cin, int32_t cout, void* stream);
+
+/* Weight and bias gradients (accumulate): dw fp32 [2][2][cout][cin],
+ * db fp32 [cout]. */
+int sil_unet_upconv_wgrad(const void* x, const void* dy, float* dw, float* db, int32_t N,
+                          int32_t H, int32_t W, int32_t cin, int32_t cout, void* stream);
+
+/* wt[ci][i][j][co] = w[i][j][co][ci] (bf16). */
+int sil_unet_up_t(const void* w, void* wt, int32_t cin, int32_t cout, void* stream);
+
+/* Batch normalisation with batch statistics and ReLU:
+ * out = max(0, (z - mean) * rstd * gamma + beta), mean and biased variance from
+ * stats ([2][C]: sums over `count` values), rstd = 1/sqrt(var + eps).  Writes
+ * mr [2][C] = (mean, rstd) for the backward pass. */
+int sil_unet_bn_relu(const void* z, const float* stats, const float* gamma, const float* beta,
+                     float eps, int64_t count, void* out, float* mr, int64_t P, int32_t C,
+                     void* stream);
+
+/* Backward of sil_unet_bn_relu.  dout, z: [P][C] bf16; writes dz [P][C] bf16;
+ * dgamma, dbeta fp32 [C] (accumulate).  red: caller-provided fp32 [2][C]
+ * scratch, zeroed by the call. */
+int sil_unet_bn_relu_bwd(const void* dout, const void* z, const float* mr, const float* gamma,
+                         const float* beta, void* dz, float* dgamma, float* dbeta, float* red,
+                         int64_t P, int32_t C, void* stream);
+
+/* 2x2 max pooling, stride 2 (H, W even).  idx [N][H/2][W/2][C] u8 records
+ * the winning position (first maximum in row-major window order). */
+int sil_unet_maxpool(const void* x, void* y, uint8_t* idx, int32_t N, int32_t H, int32_t W,
+                     int32_t C, void* stream);
+int sil_unet_maxpool_bwd(const void* dy, const uint8_t* idx, void* dx, int32_t N, int32_t H,
+                         int32_t W, int32_t C, void* stream);
+
+/* 1x1 head: logits[p][k] = b[k] + sum_c x[p][c] w[k][c], k < 3 (fp32 out). */
+int sil_unet_head(const void* x, const float* w, const float* b, float* logits, int64_t P,
+                  int32_t C, void* stream);
+
+/* Softmax cross-entropy over 3 classes: loss[0] += sum_p -log softmax(l_p)[y_p]
+ * (accumulate); dlogits[p] = (softmax(l_p) - onehot(y_p)) * scale.
+ * labels: u8 [P] in 0..2; dlogits nullable. */
+int sil_unet_softmax_xent(const float* logits, const uint8_t* labels, float* loss,
+                          float* dlogits, float scale, int64_t P, void* stream);
+
+/* Head backward: dx [P][C] bf16 = dlogits w; dw fp32 [3][C] += sum_p dlogits x;
+ * db fp32 [3] += sum_p dlogits. */
+int sil_unet_head_bwd(const void* x, const float* w, const float* dlogits, void* dx, float* dw,
+                      float* db, int64_t P, int32_t C, void* stream);
+
+/* Class map: labels[p] = argmax_k logits[p][k] (first maximum). */
+int sil_unet_argmax(const float* logits, uint8_t* labels, int64_t P, void* stream);
+
+/* Network input from a planar 16-bit scene [3][H][pitch] (bands B2, B3, B4):
+ * for chip n with origin (y0, x0) = (origins[2n], origins[2n+1]) (device int32),
+ * out[n][h][w][c] = bf16(scene[c][y0+h][x0+w] * inv_refl) for c < 3 and 0 for
+ * c in 3..7; pixels outside the scene are 0.  out: [n_chips][chip][chip][8]. */
+int sil_unet_chips_input(const uint16_t* scene, int32_t H, int32_t W, int64_t pitch,
+                         const int32_t* origins, int32_t n_chips, int32_t chip, float inv_refl,
+                         void* out, void* stream);
+
+/* Adam (Kingma & Ba) with bias correction on fp32 master weights; writes the
+ * bf16 copy when wbf is non-NULL.  m, v: fp32 moments. */
+int sil_unet_adam(float* w, const float* g, float* m, float* v, void* wbf, int64_t n, float lr,
+                  float beta1, float beta2, float eps, int32_t step, void* stream);
+
+/* fp32 -> bf16 (round to nearest even). */
+int sil_unet_to_bf16(const float* x, void* y, int64_t n, void* stream);
+
+/* x[i] = v for i < n (fp32 fill, e.g. to zero accumulators). */
+int sil_unet_fill_f32(float* x, int64_t n, float v, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -49,7 +49,13 @@ constexpr int kRowsPerWave = 32;
 constexpr int kTile = kWaves * kRowsPerWave;  // 256: chip side handled per workgroup
 constexpr int kCopies = 32;                   // LDS histogram copies
 constexpr int kMaxPatchSlots = 1024;          // LDS per-patch counters per workgroup
-constexpr int kPrefetch = 3;                  // rows of loads in flight per wave
+#ifndef SIL_PREFETCH
+#define SIL_PREFETCH 3
+#endif
+#ifndef SIL_WAVES_PER_EU
+#define SIL_WAVES_PER_EU 4
+#endif
+constexpr int kPrefetch = SIL_PREFETCH;       // rows of loads in flight per wave
 constexpr int kMaxBatch = SIL_BATCH_MAX_JOBS; // scenes per batched launch
 
 enum CountMode : uint32_t {
@@ -628,7 +634,7 @@ __device__ __forceinline__ void filter_chip(const Shared& sh, const Scene& sc, i
 }
 
 template <typename T, bool FAST24>
-__global__ __launch_bounds__(kThreads, 4) void k_filter(Shared sh, Scene sc, int per_xcd) {
+__global__ __launch_bounds__(kThreads, SIL_WAVES_PER_EU) void k_filter(Shared sh, Scene sc, int per_xcd) {
   __shared__ FilterLds s;
   const int chip_id = xcd_work_index(per_xcd);
   if (chip_id >= sc.nchips) return;
@@ -638,7 +644,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_filter(Shared sh, Scene sc, int
 // Chips of up to kMaxBatch scenes in one launch: scene j contributes chips
 // [chip_begin, chip_begin + prefix[j+1] - prefix[j]).
 template <typename T, bool FAST24>
-__global__ __launch_bounds__(kThreads, 4) void k_filter_batch(Shared sh, Batch bt) {
+__global__ __launch_bounds__(kThreads, SIL_WAVES_PER_EU) void k_filter_batch(Shared sh, Batch bt) {
   __shared__ FilterLds s;
   const int i = xcd_work_index(bt.per_xcd);
   if (i >= bt.prefix[bt.n]) return;
@@ -865,14 +871,21 @@ bool derive_shared(const sil_params* p, int32_t tile, Shared* sh, bool* fast24) 
     sh->magic = rc.magic;
     sh->shift = rc.shift;
     *fast24 = rc.fast24;
-    // raw-value boundaries for filter = 0
-    sh->X1 = 65536;
-    sh->X2 = 65536;
-    for (uint32_t x = 65536; x-- > 0;) {
-      uint32_t v = host_rescale(x, p->refl_max);
-      if (v >= sh->t1) sh->X1 = x;
-      if (v >= sh->t2) sh->X2 = x;
-    }
+    // raw-value boundaries for filter = 0: the first x whose rescaled value
+    // reaches t (the rescale is non-decreasing), 65536 if none
+    auto first_reaching = [&](uint32_t t) {
+      uint32_t lo = 0, hi = 65536;
+      while (lo < hi) {
+        uint32_t mid = (lo + hi) / 2;
+        if (host_rescale(mid, p->refl_max) >= t)
+          hi = mid;
+        else
+          lo = mid + 1;
+      }
+      return lo;
+    };
+    sh->X1 = first_reaching(sh->t1);
+    sh->X2 = first_reaching(sh->t2);
   } else {
     sh->X1 = sh->t1;
     sh->X2 = sh->t2;

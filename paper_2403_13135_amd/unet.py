@@ -1,0 +1,331 @@
+"""U-Net trained on the auto-labels (arXiv 2403.13135, section III-C), on the
+gfx950 kernels of ``include/sil_unet.h``.
+
+Every layer is a ``torch.autograd.Function`` whose forward and backward call
+the library's kernels (BF16 MFMA convolutions with fp32 accumulation, fp32
+batch-norm statistics, softmax and loss); torch only holds the tensors and
+records the graph.  Activations are bf16 NHWC; master weights are fp32.
+
+Network (widths e.g. 32, 64, 128, 256): per encoder level two 3x3 conv +
+batch norm + ReLU and a 2x2 max pool; a bottleneck of two such convolutions;
+per decoder level a 2x2 up-convolution (stride 2) halving the channels,
+concatenation with the skip map and two 3x3 conv + BN + ReLU; a 1x1 head to
+3 classes and softmax cross-entropy.  The 3 input bands are padded to 8
+channels with zeros.
+"""
+import ctypes
+import math
+from typing import Dict, Sequence
+
+import torch
+
+from . import sil
+
+IN_CH = 8  # input channels after zero padding of the 3 bands
+BN_EPS = 1e-5
+
+_bound = False
+
+
+def _lib():
+    global _bound
+    L = sil.lib()
+    if not _bound:
+        vp, i32, i64, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+        sig = {
+            "sil_unet_conv3x3": [vp, i32, vp, i32, vp, vp, vp, i32, i32, i32, i32, vp],
+            "sil_unet_conv3x3_dgrad": [vp, i32, vp, vp, i32, vp, i32, i32, i32, i32, vp],
+            "sil_unet_conv3x3_wgrad": [vp, i32, vp, i32, vp, i32, vp, i32, i32, i32, vp],
+            "sil_unet_flip3x3": [vp, vp, i32, i32, vp],
+            "sil_unet_upconv": [vp, vp, vp, vp, i32, i32, i32, i32, i32, vp],
+            "sil_unet_upconv_dgrad": [vp, vp, vp, i32, i32, i32, i32, i32, vp],
+            "sil_unet_upconv_wgrad": [vp, vp, vp, vp, i32, i32, i32, i32, i32, vp],
+            "sil_unet_up_t": [vp, vp, i32, i32, vp],
+            "sil_unet_bn_relu": [vp, vp, vp, vp, f32, i64, vp, vp, i64, i32, vp],
+            "sil_unet_bn_relu_bwd": [vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, i32, vp],
+            "sil_unet_maxpool": [vp, vp, vp, i32, i32, i32, i32, vp],
+            "sil_unet_maxpool_bwd": [vp, vp, vp, i32, i32, i32, i32, vp],
+            "sil_unet_head": [vp, vp, vp, vp, i64, i32, vp],
+            "sil_unet_softmax_xent": [vp, vp, vp, vp, f32, i64, vp],
+            "sil_unet_head_bwd": [vp, vp, vp, vp, vp, vp, i64, i32, vp],
+            "sil_unet_argmax": [vp, vp, i64, vp],
+            "sil_unet_chips_input": [vp, i32, i32, i64, vp, i32, i32, f32, vp, vp],
+            "sil_unet_adam": [vp, vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp],
+            "sil_unet_to_bf16": [vp, vp, i64, vp],
+            "sil_unet_fill_f32": [vp, i64, f32, vp],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        _bound = True
+    return L
+
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _s():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _call(name, *args):
+    rc = getattr(_lib(), name)(*args)
+    if rc != sil.OK:
+        raise sil.SilError(rc, f"{name}: {sil.strerror(rc)}")
+
+
+def _bf16(w: torch.Tensor) -> torch.Tensor:
+    out = torch.empty(w.shape, dtype=torch.bfloat16, device=w.device)
+    _call("sil_unet_to_bf16", _p(w.contiguous()), _p(out), w.numel(), _s())
+    return out
+
+
+def _zeros(shape, device):
+    t = torch.empty(shape, dtype=torch.float32, device=device)
+    _call("sil_unet_fill_f32", _p(t), t.numel(), ctypes.c_float(0.0), _s())
+    return t
+
+
+class Conv3x3BNReLU(torch.autograd.Function):
+    """relu(batchnorm(conv3x3(concat(x0, x1)))) with batch statistics."""
+
+    @staticmethod
+    def forward(ctx, x0, x1, w, gamma, beta):
+        N, H, W, c0 = x0.shape
+        c1 = 0 if x1 is None else x1.shape[3]
+        cout = w.shape[0]
+        wb = _bf16(w)
+        z = torch.empty((N, H, W, cout), dtype=torch.bfloat16, device=x0.device)
+        stats = _zeros((2, cout), x0.device)
+        _call("sil_unet_conv3x3", _p(x0), c0, _p(x1), c1, _p(wb), _p(z), _p(stats), N, H, W,
+              cout, _s())
+        out = torch.empty_like(z)
+        mr = torch.empty((2, cout), dtype=torch.float32, device=x0.device)
+        P = N * H * W
+        _call("sil_unet_bn_relu", _p(z), _p(stats), _p(gamma), _p(beta), ctypes.c_float(BN_EPS),
+              P, _p(out), _p(mr), P, cout, _s())
+        ctx.save_for_backward(x0, x1 if x1 is not None else torch.empty(0), wb, z, mr, gamma, beta)
+        ctx.has_x1 = x1 is not None
+        return out
+
+    @staticmethod
+    def backward(ctx, dout):
+        x0, x1, wb, z, mr, gamma, beta = ctx.saved_tensors
+        x1 = x1 if ctx.has_x1 else None
+        dout = dout.contiguous()
+        N, H, W, c0 = x0.shape
+        c1 = 0 if x1 is None else x1.shape[3]
+        cout = wb.shape[0]
+        P = N * H * W
+        dz = torch.empty_like(z)
+        dgamma = _zeros((cout,), z.device)
+        dbeta = _zeros((cout,), z.device)
+        red = torch.empty((2, cout), dtype=torch.float32, device=z.device)
+        _call("sil_unet_bn_relu_bwd", _p(dout), _p(z), _p(mr), _p(gamma), _p(beta), _p(dz),
+              _p(dgamma), _p(dbeta), _p(red), P, cout, _s())
+        dw = _zeros(wb.shape, z.device)
+        _call("sil_unet_conv3x3_wgrad", _p(dz), cout, _p(x0), c0, _p(x1), c1, _p(dw), N, H, W,
+              _s())
+        dx0 = dx1 = None
+        if ctx.needs_input_grad[0] or (x1 is not None and ctx.needs_input_grad[1]):
+            wt = torch.empty((c0 + c1, 3, 3, cout), dtype=torch.bfloat16, device=z.device)
+            _call("sil_unet_flip3x3", _p(wb), _p(wt), cout, c0 + c1, _s())
+            dx0 = torch.empty_like(x0)
+            dx1 = torch.empty_like(x1) if x1 is not None else None
+            _call("sil_unet_conv3x3_dgrad", _p(dz), cout, _p(wt), _p(dx0), c0, _p(dx1), c1, N, H,
+                  W, _s())
+        return dx0, dx1, dw, dgamma, dbeta
+
+
+class MaxPool2(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x):
+        N, H, W, C = x.shape
+        y = torch.empty((N, H // 2, W // 2, C), dtype=x.dtype, device=x.device)
+        idx = torch.empty((N, H // 2, W // 2, C), dtype=torch.uint8, device=x.device)
+        _call("sil_unet_maxpool", _p(x), _p(y), _p(idx), N, H, W, C, _s())
+        ctx.save_for_backward(idx)
+        ctx.shape = x.shape
+        return y
+
+    @staticmethod
+    def backward(ctx, dy):
+        (idx,) = ctx.saved_tensors
+        N, H, W, C = ctx.shape
+        dx = torch.empty(ctx.shape, dtype=dy.dtype, device=dy.device)
+        _call("sil_unet_maxpool_bwd", _p(dy.contiguous()), _p(idx), _p(dx), N, H, W, C, _s())
+        return dx
+
+
+class UpConv2(torch.autograd.Function):
+    """2x2 transposed convolution, stride 2, with bias; w: [2, 2, cout, cin]."""
+
+    @staticmethod
+    def forward(ctx, x, w, b):
+        N, H, W, cin = x.shape
+        cout = w.shape[2]
+        wb = _bf16(w)
+        y = torch.empty((N, 2 * H, 2 * W, cout), dtype=torch.bfloat16, device=x.device)
+        _call("sil_unet_upconv", _p(x), _p(wb), _p(b), _p(y), N, H, W, cin, cout, _s())
+        ctx.save_for_backward(x, wb)
+        return y
+
+    @staticmethod
+    def backward(ctx, dy):
+        x, wb = ctx.saved_tensors
+        dy = dy.contiguous()
+        N, H, W, cin = x.shape
+        cout = wb.shape[2]
+        dw = _zeros(wb.shape, x.device)
+        db = _zeros((cout,), x.device)
+        _call("sil_unet_upconv_wgrad", _p(x), _p(dy), _p(dw), _p(db), N, H, W, cin, cout, _s())
+        wt = torch.empty((cin, 2, 2, cout), dtype=torch.bfloat16, device=x.device)
+        _call("sil_unet_up_t", _p(wb), _p(wt), cin, cout, _s())
+        dx = torch.empty_like(x)
+        _call("sil_unet_upconv_dgrad", _p(dy), _p(wt), _p(dx), N, H, W, cin, cout, _s())
+        return dx, dw, db
+
+
+class HeadXent(torch.autograd.Function):
+    """Mean softmax cross-entropy of the 1x1 head; returns (loss, logits)."""
+
+    @staticmethod
+    def forward(ctx, x, w, b, labels):
+        N, H, W, C = x.shape
+        P = N * H * W
+        logits = torch.empty((P, 3), dtype=torch.float32, device=x.device)
+        _call("sil_unet_head", _p(x), _p(w), _p(b), _p(logits), P, C, _s())
+        loss = _zeros((1,), x.device)
+        dlogits = torch.empty_like(logits)
+        _call("sil_unet_softmax_xent", _p(logits), _p(labels), _p(loss), _p(dlogits),
+              ctypes.c_float(1.0 / P), P, _s())
+        ctx.save_for_backward(x, w, dlogits)
+        ctx.mark_non_differentiable(logits)
+        return loss[0] / P, logits.view(N, H, W, 3)
+
+    @staticmethod
+    def backward(ctx, dloss, _dlogits):
+        x, w, dlogits = ctx.saved_tensors
+        N, H, W, C = x.shape
+        P = N * H * W
+        # dlogits already carries the 1/P of the mean; scale by the incoming grad
+        dl = dlogits * dloss if float(dloss) != 1.0 else dlogits
+        dx = torch.empty_like(x)
+        dw = _zeros((3, C), x.device)
+        db = _zeros((3,), x.device)
+        _call("sil_unet_head_bwd", _p(x), _p(w), _p(dl), _p(dx), _p(dw), _p(db), P, C, _s())
+        return dx, dw, db, None
+
+
+def layer_specs(widths: Sequence[int], in_ch: int = IN_CH):
+    specs = []
+    c = in_ch
+    for i, w in enumerate(widths):
+        name = f"enc{i}" if i < len(widths) - 1 else "mid"
+        specs.append((f"{name}.conv0", "conv3", c, w))
+        specs.append((f"{name}.conv1", "conv3", w, w))
+        c = w
+    for i in reversed(range(len(widths) - 1)):
+        w = widths[i]
+        specs.append((f"dec{i}.up", "up2", c, w))
+        specs.append((f"dec{i}.conv0", "conv3", 2 * w, w))
+        specs.append((f"dec{i}.conv1", "conv3", w, w))
+        c = w
+    specs.append(("head", "conv1", c, 3))
+    return specs
+
+
+class UNet:
+    """Parameters (fp32 master copies, GPU) and the forward pass."""
+
+    def __init__(self, widths: Sequence[int], device="cuda", seed: int = 0):
+        self.widths = tuple(widths)
+        g = torch.Generator().manual_seed(seed)
+        P: Dict[str, torch.Tensor] = {}
+        for name, kind, cin, cout in layer_specs(widths):
+            if kind == "conv3":
+                fan = 9 * (3 if name == "enc0.conv0" else cin)
+                w = torch.randn(cout, 3, 3, cin, generator=g) * math.sqrt(2.0 / fan)
+                if name == "enc0.conv0":
+                    w[..., 3:] = 0.0  # padding channels
+                P[name + ".w"] = w
+                P[name + ".gamma"] = torch.ones(cout)
+                P[name + ".beta"] = torch.zeros(cout)
+            elif kind == "up2":
+                P[name + ".w"] = torch.randn(2, 2, cout, cin, generator=g) * math.sqrt(2.0 / cin)
+                P[name + ".b"] = torch.zeros(cout)
+            else:
+                P[name + ".w"] = torch.randn(cout, cin, generator=g) * math.sqrt(2.0 / cin)
+                P[name + ".b"] = torch.zeros(cout)
+        self.params = {k: v.to(device).float().requires_grad_(True) for k, v in P.items()}
+
+    def forward(self, x: torch.Tensor, labels: torch.Tensor):
+        """x: bf16 [N, H, W, 8]; labels: uint8 [N, H, W].  Returns (loss, logits)."""
+        P = self.params
+        skips = []
+        h = x
+        L = len(self.widths)
+        for i in range(L):
+            name = f"enc{i}" if i < L - 1 else "mid"
+            for k in ("conv0", "conv1"):
+                n = f"{name}.{k}"
+                h = Conv3x3BNReLU.apply(h, None, P[n + ".w"], P[n + ".gamma"], P[n + ".beta"])
+            if i < L - 1:
+                skips.append(h)
+                h = MaxPool2.apply(h)
+        for i in reversed(range(L - 1)):
+            up = UpConv2.apply(h, P[f"dec{i}.up.w"], P[f"dec{i}.up.b"])
+            n = f"dec{i}.conv0"
+            h = Conv3x3BNReLU.apply(up, skips[i], P[n + ".w"], P[n + ".gamma"], P[n + ".beta"])
+            n = f"dec{i}.conv1"
+            h = Conv3x3BNReLU.apply(h, None, P[n + ".w"], P[n + ".gamma"], P[n + ".beta"])
+        return HeadXent.apply(h, P["head.w"], P["head.b"], labels)
+
+    def predict(self, x: torch.Tensor) -> torch.Tensor:
+        """Class map [N, H, W] (uint8).  Uses batch statistics of `x`, as in training."""
+        N, H, W, _ = x.shape
+        dummy = torch.zeros((N, H, W), dtype=torch.uint8, device=x.device)
+        with torch.no_grad():
+            _, logits = self.forward(x, dummy)
+        out = torch.empty((N, H, W), dtype=torch.uint8, device=x.device)
+        _call("sil_unet_argmax", _p(logits.contiguous()), _p(out), N * H * W, _s())
+        return out
+
+
+class Adam:
+    """Adam on the model's fp32 master weights (one fused kernel per tensor)."""
+
+    def __init__(self, params: Dict[str, torch.Tensor], lr=1e-3, betas=(0.9, 0.999), eps=1e-8):
+        self.params = params
+        self.lr, self.b1, self.b2, self.eps = lr, betas[0], betas[1], eps
+        self.m = {k: torch.zeros_like(v) for k, v in params.items()}
+        self.v = {k: torch.zeros_like(v) for k, v in params.items()}
+        self.t = 0
+
+    @torch.no_grad()
+    def step(self):
+        self.t += 1
+        for k, p in self.params.items():
+            if p.grad is None:
+                continue
+            _call("sil_unet_adam", _p(p), _p(p.grad.contiguous()), _p(self.m[k]), _p(self.v[k]),
+                  None, p.numel(), ctypes.c_float(self.lr), ctypes.c_float(self.b1),
+                  ctypes.c_float(self.b2), ctypes.c_float(self.eps), self.t, _s())
+
+    def zero_grad(self):
+        for p in self.params.values():
+            p.grad = None
+
+
+def chips_input(scene: torch.Tensor, origins: torch.Tensor, chip: int = 256,
+                refl_max: float = 10000.0) -> torch.Tensor:
+    """bf16 [n, chip, chip, 8] network input from a [3, H, pitch] int16/uint16
+    scene for the chip origins [n, 2] (int32, device)."""
+    _, H, pitch = scene.shape
+    n = origins.shape[0]
+    out = torch.empty((n, chip, chip, IN_CH), dtype=torch.bfloat16, device=scene.device)
+    _call("sil_unet_chips_input", _p(scene), H, pitch, pitch, _p(origins.contiguous()), n, chip,
+          ctypes.c_float(1.0 / refl_max), _p(out), _s())
+    return out

@@ -12,8 +12,8 @@ Recipes:
   * ``config_tile()``: 10980x10980 uint16 reflectance, 4 haze blobs covering
     ~10 % and 2 shadow blobs covering ~5 % (sigma ~832 px), seed 2.
 """
-from .synth import (Blob, SceneSpec, coverage, config_small, config_tile, generate,
-                    generate_u8, to_u16)
+from .synth import (Blob, SceneSpec, blobs_for_coverage, coverage, config_small, config_tile,
+                    generate, generate_u8, to_u16)
 
-__all__ = ["Blob", "SceneSpec", "coverage", "config_small", "config_tile", "generate",
-           "generate_u8", "to_u16"]
+__all__ = ["Blob", "SceneSpec", "blobs_for_coverage", "coverage", "config_small", "config_tile",
+           "generate", "generate_u8", "to_u16"]

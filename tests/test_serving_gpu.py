@@ -1,0 +1,130 @@
+"""GPU tests of the continuous-batching server: every result is the same
+alone and in the mix (bit for bit), admission respects the HBM arena, and
+argument errors are rejected."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import sil_ref as R
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_13135_amd import serve, sil
+    sil.lib()
+    rng = np.random.default_rng(77)
+    shapes = [(512, 512), (300, 1100), (1031, 777), (2048, 2048), (64, 64), (257, 513),
+              (1500, 2600)]
+    p = sil.Params(dtype=sil.U16)
+    pool = []
+    for i, (H, W) in enumerate(shapes):
+        spec = synth.SceneSpec(H, W, 500 + i, "u16",
+                               synth.blobs_for_coverage(H, W, 500 + i, 1, 1, 0.1),
+                               synth.blobs_for_coverage(H, W, 500 + i, 2, 1, 0.05))
+        s_np = synth.generate(spec)
+        dev = torch.from_numpy(s_np.view(np.int16)).cuda()
+        lab, hist = sil.label(dev, p)
+        torch.cuda.synchronize()
+        if i < 3:  # the single-scene path itself against the oracle
+            ol, oh = R.label(s_np, R.make_params(dtype=R.U16))
+            assert (lab.cpu().numpy() == ol).all() and (hist.cpu().numpy() == oh).all()
+        pool.append((dev, lab, hist))
+    return serve, sil, p, pool, rng
+
+
+def _check(c, ref):
+    lab, hist = ref[1], ref[2]
+    return torch.equal(c.labels(), lab) and torch.equal(c.hist(), hist)
+
+
+def test_mixed_burst_equals_alone(env):
+    serve, sil, p, pool, rng = env
+    srv = serve.Server(p, arena_bytes=2 << 30, max_chips_per_launch=150, max_inflight=3,
+                       nstreams=2)
+    picks = [int(rng.integers(0, len(pool))) for _ in range(80)]
+    _say("case burst of 80 mixed requests, 150 chips per launch")
+    comps, _ = srv.run([pool[k][0] for k in picks], [0.0] * len(picks), release=False)
+    torch.cuda.synchronize()
+    st = srv.stats()
+    assert st["completed"] == len(picks)
+    assert st["launches"] > 10
+    assert max(c.launches for c in comps) > 1  # big scenes were split over launches
+    for c, k in zip(comps, picks):
+        assert _check(c, pool[k]), f"request {c.tag} (scene {k}) differs from its solo run"
+        srv.release(c.tag)
+    assert srv.stats()["arena_used"] == 0
+    srv.close()
+
+
+def test_poisson_trace_with_tight_arena(env):
+    """An arena that holds only a few requests' outputs: admission waits for
+    releases, every request still completes, and the peak stays in bounds."""
+    serve, sil, p, pool, rng = env
+    arena = 24 << 20
+    srv = serve.Server(p, arena_bytes=arena, max_chips_per_launch=64, max_inflight=2)
+    picks = [int(rng.integers(0, len(pool))) for _ in range(40)]
+    arrivals = np.cumsum(rng.exponential(0.05, len(picks))).tolist()
+    _say("case poisson trace, 24 MiB arena")
+    comps, start = srv.run([pool[k][0] for k in picks], arrivals, release=True)
+    st = srv.stats()
+    assert st["completed"] == st["released"] == len(picks)
+    assert st["arena_peak"] <= arena and st["arena_used"] == 0
+    for c, a in zip(comps, arrivals):
+        assert c.t_done_ms >= c.t_admit_ms >= c.t_submit_ms - 1e-3
+        assert c.t_submit_ms >= start + a - 1e-3
+    srv.close()
+
+
+def test_manual_loop_verifies_before_release(env):
+    serve, sil, p, pool, rng = env
+    srv = serve.Server(p, arena_bytes=64 << 20, max_chips_per_launch=100, max_inflight=2)
+    todo = [int(rng.integers(0, len(pool))) for _ in range(30)]
+    tag_scene = {}
+    nxt, done = 0, 0
+    while done < len(todo):
+        while nxt < len(todo) and nxt - done < 8:
+            srv.submit(pool[todo[nxt]][0], tag=1000 + nxt)
+            tag_scene[1000 + nxt] = todo[nxt]
+            nxt += 1
+        srv.pump()
+        for c in srv.poll():
+            assert _check(c, pool[tag_scene[c.tag]])
+            srv.release(c.tag)
+            done += 1
+    srv.close()
+
+
+def test_server_argument_errors(env):
+    serve, sil, p, pool, rng = env
+    with pytest.raises(sil.SilError) as e:
+        serve.Server(sil.Params(dtype=sil.U16, patch_h=64, patch_w=64))
+    assert e.value.code == sil.EUNSUPPORTED
+    srv = serve.Server(p, arena_bytes=1 << 20)
+    big = pool[3][0]  # 2048x2048: 4 MiB of labels > 1 MiB arena
+    with pytest.raises(sil.SilError) as e:
+        srv.submit(big, tag=1)
+    assert e.value.code == sil.EINVAL
+    srv.submit(pool[4][0], tag=2)
+    with pytest.raises(sil.SilError) as e:
+        srv.submit(pool[4][0], tag=2)  # duplicate live tag
+    assert e.value.code == sil.EINVAL
+    with pytest.raises(sil.SilError):
+        srv.release(2)  # not completed yet
+    srv.pump()
+    srv.drain()
+    got = srv.poll()
+    assert [c.tag for c in got] == [2]
+    srv.release(2)
+    srv.close()
