@@ -148,6 +148,53 @@ def run_serving(n_requests, chips_per_launch, seeds_per_size=2):
     return out
 
 
+def run_learned(steps, n_fallback):
+    """U-Net (32-64-128-256) trained on GPU auto-labels at batch 32 of 256^2
+    chips: step time and MFMA throughput, held-out accuracy against the
+    synthetic truth beside the labeller, and serving with the labeller as
+    fallback on mixed-size scenes."""
+    import numpy as np
+    import torch
+    from paper_2403_13135_amd import learn, serve, sil, unet
+
+    widths = (32, 64, 128, 256)
+    train_sc = learn.make_scenes(12, 2048, seed0=3000)
+    test_sc = learn.make_scenes(3, 2048, seed0=4000)
+    X, Y = learn.build_training_set(train_sc)
+    model = unet.UNet(widths, seed=0)
+    losses, sec = learn.train(model, X, Y, steps=steps, batch=32, lr=1e-3)
+    flops_step = 3 * learn.unet_flops_per_image(widths) * 32
+    ev = learn.evaluate(model, test_sc)
+    out = {"widths": list(widths), "batch": 32, "train_chips": int(X.shape[0]), "steps": steps,
+           "step_ms": sec * 1e3, "images_per_s": 32 / sec,
+           "tflops": flops_step / sec / 1e12,
+           "mfma_frac_of_bf16_dense_peak": flops_step / sec / 2.5e15,
+           "loss_first_last": [losses[0], float(np.mean(losses[-10:]))], "held_out": ev}
+    del X, Y, train_sc
+    torch.cuda.empty_cache()
+    # serving with fallback: mixed sizes as in the serving trace
+    rng = np.random.default_rng(5)
+    import synth
+    scenes = []
+    for i in range(n_fallback):
+        n = serve.SIZES[int(rng.integers(0, len(serve.SIZES)))]
+        spec = synth.SceneSpec(n, n, 6000 + i, "u16",
+                               synth.blobs_for_coverage(n, n, 6000 + i, 1, 1, 0.10),
+                               synth.blobs_for_coverage(n, n, 6000 + i, 2, 1, 0.05))
+        scenes.append(torch.from_numpy(synth.generate(spec).view(np.int16)).cuda())
+    torch.cuda.synchronize()
+    recs = learn.serve_with_fallback(model, scenes, threshold=0.02)
+    ms = np.array([r["ms"] for r in recs])
+    px = sum(r["H"] * r["W"] for r in recs)
+    out["serving_with_fallback"] = {
+        "requests": n_fallback, "gpx_s": px / (ms.sum() * 1e-3) / 1e9,
+        "p50_ms": float(np.percentile(ms, 50)), "p99_ms": float(np.percentile(ms, 99)),
+        "mean_mismatch_vs_labeller": float(np.mean([r["disagreement"] for r in recs])),
+        "fallback_rate": float(np.mean([r["fallback"] for r in recs])),
+        "threshold": 0.02, "sequential": True}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +207,9 @@ def main():
     ap.add_argument("--skip-serving", action="store_true", help="omit the serving section")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--chips-per-launch", type=int, default=1024)
+    ap.add_argument("--skip-learned", action="store_true", help="omit the U-Net section")
+    ap.add_argument("--unet-steps", type=int, default=120)
+    ap.add_argument("--fallback-requests", type=int, default=12)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -280,6 +330,10 @@ def main():
         del scene, labels, hist, labels0, hist0
         torch.cuda.empty_cache()
         serving = run_serving(args.serving_requests, args.chips_per_launch)
+    learned = None
+    if not args.skip_learned:
+        torch.cuda.empty_cache()
+        learned = run_learned(args.unet_steps, args.fallback_requests)
 
     out = {
         "metric": "auto-labelled Gpixel/s",
@@ -313,6 +367,7 @@ def main():
             "wall_s_timed_region": wall,
         },
         "serving": serving,
+        "learned": learned,
     }
     print(json.dumps(out), flush=True)
 

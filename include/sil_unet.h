@@ -85,6 +85,13 @@ int sil_unet_bn_relu(const void* z, const float* stats, const float* gamma, cons
                      float eps, int64_t count, void* out, float* mr, int64_t P, int32_t C,
                      void* stream);
 
+/* Inference-mode batch normalisation and ReLU with fixed per-channel scale and
+ * shift (scale = gamma/sqrt(running_var + eps), shift = beta - running_mean *
+ * scale): out = max(0, z * scale + shift).  Each pixel's result depends only on
+ * that pixel, so outputs do not depend on what else is in the batch. */
+int sil_unet_affine_relu(const void* z, const float* scale, const float* shift, void* out,
+                         int64_t P, int32_t C, void* stream);
+
 /* Backward of sil_unet_bn_relu.  dout, z: [P][C] bf16; writes dz [P][C] bf16;
  * dgamma, dbeta fp32 [C] (accumulate).  red: caller-provided fp32 [2][C]
  * scratch, zeroed by the call. */
@@ -116,6 +123,14 @@ int sil_unet_head_bwd(const void* x, const float* w, const float* dlogits, void*
 
 /* Class map: labels[p] = argmax_k logits[p][k] (first maximum). */
 int sil_unet_argmax(const float* logits, uint8_t* labels, int64_t P, void* stream);
+
+/* Write the class map of chips back into a scene label plane: for chip n with
+ * origin (origins[2n], origins[2n+1]), labels[y0+h][x0+w] = argmax_k
+ * logits[n][h][w][k] for pixels inside the H x W scene.  logits fp32
+ * [n_chips][chip][chip][3]; labels [H][lpitch]. */
+int sil_unet_scatter_argmax(const float* logits, const int32_t* origins, int32_t n_chips,
+                            int32_t chip, uint8_t* labels, int32_t H, int32_t W, int64_t lpitch,
+                            void* stream);
 
 /* Network input from a planar 16-bit scene [3][H][pitch] (bands B2, B3, B4):
  * for chip n with origin (y0, x0) = (origins[2n], origins[2n+1]) (device int32),

@@ -428,6 +428,39 @@ __global__ void k_bn_bwd_apply(const u16* dout, const u16* z, const float* mr, c
   }
 }
 
+__global__ void k_affine_relu(const u16* z, const float* scale, const float* shift, u16* out,
+                              int64_t n, int32_t C) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t c = (int32_t)(i % C);
+    const float v = bf2f(z[i]) * scale[c] + shift[c];
+    out[i] = f2bf(v > 0.f ? v : 0.f);
+  }
+}
+
+__global__ void k_scatter_argmax(const float* logits, const int32_t* origins, int32_t n_chips,
+                                 int32_t chip, uint8_t* labels, int32_t H, int32_t W,
+                                 int64_t lpitch) {
+  const int64_t n = (int64_t)n_chips * chip * chip;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t w = (int32_t)(i % chip);
+    const int32_t h = (int32_t)((i / chip) % chip);
+    const int32_t k = (int32_t)(i / ((int64_t)chip * chip));
+    const int32_t y = origins[2 * k] + h, x = origins[2 * k + 1] + w;
+    if (y < 0 || y >= H || x < 0 || x >= W) continue;
+    const float a = logits[3 * i], b = logits[3 * i + 1], c = logits[3 * i + 2];
+    uint8_t cls = 0;
+    float m = a;
+    if (b > m) {
+      m = b;
+      cls = 1;
+    }
+    if (c > m) cls = 2;
+    labels[(int64_t)y * lpitch + x] = cls;
+  }
+}
+
 __global__ void k_add_vec(float* dst, const float* src, int32_t n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] += src[i];
@@ -862,6 +895,29 @@ int sil_unet_bn_relu(const void* z, const float* stats, const float* gamma, cons
   const int64_t n = P * C;
   hipLaunchKernelGGL(k_bn_relu, dim3(grid_for(n)), dim3(256), 0, st, (const u16*)z, mr, gamma,
                      beta, (u16*)out, n, C);
+  return done();
+}
+
+int sil_unet_affine_relu(const void* z, const float* scale, const float* shift, void* out,
+                         int64_t P, int32_t C, void* stream) {
+  if (!z || !scale || !shift || !out || P <= 0 || C <= 0) return SIL_EINVAL;
+  (void)hipGetLastError();
+  const int64_t n = P * C;
+  hipLaunchKernelGGL(k_affine_relu, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream,
+                     (const u16*)z, scale, shift, (u16*)out, n, C);
+  return done();
+}
+
+int sil_unet_scatter_argmax(const float* logits, const int32_t* origins, int32_t n_chips,
+                            int32_t chip, uint8_t* labels, int32_t H, int32_t W, int64_t lpitch,
+                            void* stream) {
+  if (!logits || !origins || !labels || n_chips <= 0 || chip <= 0 || H <= 0 || W <= 0 ||
+      lpitch < W)
+    return SIL_EINVAL;
+  (void)hipGetLastError();
+  const int64_t n = (int64_t)n_chips * chip * chip;
+  hipLaunchKernelGGL(k_scatter_argmax, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream,
+                     logits, origins, n_chips, chip, labels, H, W, lpitch);
   return done();
 }
 

@@ -1,0 +1,176 @@
+"""Training the U-Net on the GPU auto-labels and serving it with the labeller
+as fallback (arXiv 2403.13135, section III-C and Fig. "Workflow for Sea Ice
+Classification employing cloud-shadow filter and U-net model Inferencing").
+
+* Training data: seeded synthetic scenes (``synth``), auto-labelled by the
+  GPU labeller (``sil.label``, filter on), cut into 256 x 256 chips as the
+  paper cuts its 2048 x 2048 scenes into 64 chips of 256 x 256.
+* The trained network's class maps are compared with the labeller's (pixel
+  disagreement) and, since the synthetic scenes carry their class truth, both
+  are scored against that truth; so is the unfiltered threshold labelling.
+* Serving with fallback: a scene's U-Net class map is used unless it
+  disagrees with the labeller on more than a set fraction of pixels, in
+  which case the labeller's map is returned.
+"""
+import time
+from dataclasses import dataclass
+from typing import List
+
+import numpy as np
+import torch
+
+from . import sil, unet
+
+CHIP = 256
+
+
+def unet_flops_per_image(widths, H=CHIP, W=CHIP) -> float:
+    """2 x multiply-adds of one forward pass at H x W: 3x3 convolutions at
+    their level's resolution and 2x2 up-convolutions from the level below (the
+    1x1 head and element-wise work are not counted)."""
+    L = len(widths)
+    macs = 0
+    for name, kind, cin, cout in unet.layer_specs(widths, in_ch=3):
+        if kind == "conv1":
+            continue
+        # level index of the layer: "enc<i>", "dec<i>", or the bottleneck
+        lvl = L - 1 if name.startswith("mid") else int(name.split(".")[0][3:])
+        hh, ww = H >> lvl, W >> lvl
+        if kind == "conv3":
+            macs += 9 * cin * cout * hh * ww
+        elif kind == "up2":
+            macs += 4 * cin * cout * (hh // 2) * (ww // 2)
+    return 2.0 * macs
+
+
+@dataclass
+class Scene:
+    scene: torch.Tensor    # [3, H, W] int16 (uint16 reflectance bits), device
+    truth: torch.Tensor    # [H, W] uint8, device
+    labels: torch.Tensor   # [H, W] uint8 auto-labels (filter on), device
+    labels0: torch.Tensor  # [H, W] uint8 thresholds only, device
+
+
+def make_scenes(n: int, size: int, seed0: int, device="cuda") -> List[Scene]:
+    import synth
+    out = []
+    p1 = sil.Params(dtype=sil.U16)
+    p0 = sil.Params(dtype=sil.U16, filter=0)
+    for i in range(n):
+        seed = seed0 + i
+        spec = synth.SceneSpec(size, size, seed, "u16",
+                               synth.blobs_for_coverage(size, size, seed, 1, 2, 0.10),
+                               synth.blobs_for_coverage(size, size, seed, 2, 1, 0.05))
+        s, truth = synth.generate(spec, want_truth=True)
+        dev = torch.from_numpy(s.view(np.int16)).to(device)
+        lab, _ = sil.label(dev, p1)
+        lab0, _ = sil.label(dev, p0)
+        out.append(Scene(dev, torch.from_numpy(truth).to(device), lab, lab0))
+    torch.cuda.synchronize()
+    return out
+
+
+def interior_origins(H: int, W: int, chip: int = CHIP) -> np.ndarray:
+    return np.array([(y, x) for y in range(0, H - chip + 1, chip)
+                     for x in range(0, W - chip + 1, chip)], dtype=np.int32)
+
+
+def all_origins(H: int, W: int, chip: int = CHIP) -> np.ndarray:
+    return np.array([(y, x) for y in range(0, H, chip) for x in range(0, W, chip)],
+                    dtype=np.int32)
+
+
+def build_training_set(scenes: List[Scene]):
+    """bf16 inputs [n, 256, 256, 8] and uint8 auto-label chips [n, 256, 256]."""
+    xs, ys = [], []
+    for sc in scenes:
+        H, W = sc.labels.shape
+        org = interior_origins(H, W)
+        o = torch.from_numpy(org).to(sc.scene.device)
+        xs.append(unet.chips_input(sc.scene, o))
+        lab = sc.labels.unfold(0, CHIP, CHIP).unfold(1, CHIP, CHIP)  # [ny, nx, 256, 256]
+        ys.append(lab.reshape(-1, CHIP, CHIP).contiguous())
+    return torch.cat(xs), torch.cat(ys)
+
+
+def train(model: unet.UNet, X: torch.Tensor, Y: torch.Tensor, steps: int, batch: int = 32,
+          lr: float = 1e-3, seed: int = 0, log_every: int = 0):
+    """Adam on random batches; returns (losses, seconds per step after warm-up)."""
+    opt = unet.Adam(model.params, lr=lr)
+    g = torch.Generator().manual_seed(seed)
+    losses, t_steps = [], []
+    for step in range(steps):
+        idx = torch.randint(0, X.shape[0], (batch,), generator=g).to(X.device)
+        xb, yb = X.index_select(0, idx), Y.index_select(0, idx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        opt.zero_grad()
+        loss, _ = model.forward(xb, yb)
+        loss.backward()
+        opt.step()
+        model.update_running_stats()
+        torch.cuda.synchronize()
+        t_steps.append(time.perf_counter() - t0)
+        losses.append(loss.item())
+        if log_every and step % log_every == 0:
+            print(f"step {step} loss {losses[-1]:.4f} {t_steps[-1] * 1e3:.1f} ms", flush=True)
+    warm = t_steps[min(5, len(t_steps) - 1):]
+    return losses, float(np.median(warm))
+
+
+@torch.no_grad()
+def predict_scene(model: unet.UNet, scene: torch.Tensor, batch: int = 64) -> torch.Tensor:
+    """U-Net class map [H, W] of a whole scene (edge chips zero-padded)."""
+    _, H, W = scene.shape
+    org = torch.from_numpy(all_origins(H, W)).to(scene.device)
+    out = torch.empty((H, W), dtype=torch.uint8, device=scene.device)
+    for i in range(0, org.shape[0], batch):
+        o = org[i:i + batch]
+        x = unet.chips_input(scene, o)
+        logits = model.infer_logits(x)
+        unet.scatter_argmax(logits, o, out, H, W)
+    return out
+
+
+def accuracy(a: torch.Tensor, b: torch.Tensor) -> float:
+    return (a == b).float().mean().item()
+
+
+def evaluate(model: unet.UNet, scenes: List[Scene]) -> dict:
+    acc_u, acc_l, acc_0, dis = [], [], [], []
+    for sc in scenes:
+        pred = predict_scene(model, sc.scene)
+        acc_u.append(accuracy(pred, sc.truth))
+        acc_l.append(accuracy(sc.labels, sc.truth))
+        acc_0.append(accuracy(sc.labels0, sc.truth))
+        dis.append(1.0 - accuracy(pred, sc.labels))
+    return {"unet_vs_truth": float(np.mean(acc_u)), "labeller_vs_truth": float(np.mean(acc_l)),
+            "thresholds_only_vs_truth": float(np.mean(acc_0)),
+            "unet_labeller_disagreement": float(np.mean(dis))}
+
+
+@torch.no_grad()
+def serve_with_fallback(model: unet.UNet, scenes: List[torch.Tensor], threshold: float = 0.02,
+                        batch: int = 64, outputs: list = None):
+    """Each scene: labeller and U-Net on the same GPU; the U-Net map is kept
+    unless it disagrees with the labeller on more than `threshold` of the
+    pixels.  Returns per-request records (latency ms, disagreement, fallback);
+    the served class maps are appended to `outputs` when given."""
+    p = sil.Params(dtype=sil.U16)
+    recs = []
+    for s in scenes:
+        _, H, W = s.shape
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        lab, hist = sil.label(s, p)
+        pred = predict_scene(model, s, batch=batch)
+        mism = (pred != lab).sum()
+        e1.record()
+        e1.synchronize()
+        d = mism.item() / (H * W)
+        recs.append({"H": H, "W": W, "ms": e0.elapsed_time(e1), "disagreement": d,
+                     "fallback": d > threshold})
+        if outputs is not None:
+            outputs.append(lab if d > threshold else pred)
+    return recs

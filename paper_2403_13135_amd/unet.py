@@ -43,6 +43,8 @@ def _lib():
             "sil_unet_up_t": [vp, vp, i32, i32, vp],
             "sil_unet_bn_relu": [vp, vp, vp, vp, f32, i64, vp, vp, i64, i32, vp],
             "sil_unet_bn_relu_bwd": [vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, i32, vp],
+            "sil_unet_affine_relu": [vp, vp, vp, vp, i64, i32, vp],
+            "sil_unet_scatter_argmax": [vp, vp, i32, i32, vp, i32, i32, i64, vp],
             "sil_unet_maxpool": [vp, vp, vp, i32, i32, i32, i32, vp],
             "sil_unet_maxpool_bwd": [vp, vp, vp, i32, i32, i32, i32, vp],
             "sil_unet_head": [vp, vp, vp, vp, i64, i32, vp],
@@ -92,7 +94,8 @@ class Conv3x3BNReLU(torch.autograd.Function):
     """relu(batchnorm(conv3x3(concat(x0, x1)))) with batch statistics."""
 
     @staticmethod
-    def forward(ctx, x0, x1, w, gamma, beta):
+    def forward(ctx, x0, x1, w, gamma, beta, mr=None):
+        """mr (optional [2, cout] fp32) receives the batch (mean, rstd)."""
         N, H, W, c0 = x0.shape
         c1 = 0 if x1 is None else x1.shape[3]
         cout = w.shape[0]
@@ -102,7 +105,8 @@ class Conv3x3BNReLU(torch.autograd.Function):
         _call("sil_unet_conv3x3", _p(x0), c0, _p(x1), c1, _p(wb), _p(z), _p(stats), N, H, W,
               cout, _s())
         out = torch.empty_like(z)
-        mr = torch.empty((2, cout), dtype=torch.float32, device=x0.device)
+        if mr is None:
+            mr = torch.empty((2, cout), dtype=torch.float32, device=x0.device)
         P = N * H * W
         _call("sil_unet_bn_relu", _p(z), _p(stats), _p(gamma), _p(beta), ctypes.c_float(BN_EPS),
               P, _p(out), _p(mr), P, cout, _s())
@@ -136,7 +140,7 @@ class Conv3x3BNReLU(torch.autograd.Function):
             dx1 = torch.empty_like(x1) if x1 is not None else None
             _call("sil_unet_conv3x3_dgrad", _p(dz), cout, _p(wt), _p(dx0), c0, _p(dx1), c1, N, H,
                   W, _s())
-        return dx0, dx1, dw, dgamma, dbeta
+        return dx0, dx1, dw, dgamma, dbeta, None
 
 
 class MaxPool2(torch.autograd.Function):
@@ -260,6 +264,14 @@ class UNet:
                 P[name + ".w"] = torch.randn(cout, cin, generator=g) * math.sqrt(2.0 / cin)
                 P[name + ".b"] = torch.zeros(cout)
         self.params = {k: v.to(device).float().requires_grad_(True) for k, v in P.items()}
+        # running batch-norm statistics for inference, and the last batch's (mean, rstd)
+        self.bn_names = [n for n, kind, _, _ in layer_specs(widths) if kind == "conv3"]
+        self.running = {n: (torch.zeros(P[n + ".gamma"].numel(), device=device),
+                            torch.ones(P[n + ".gamma"].numel(), device=device))
+                        for n in self.bn_names}
+        self.batch_mr = {n: torch.empty((2, P[n + ".gamma"].numel()), device=device)
+                         for n in self.bn_names}
+        self.momentum = 0.1
 
     def forward(self, x: torch.Tensor, labels: torch.Tensor):
         """x: bf16 [N, H, W, 8]; labels: uint8 [N, H, W].  Returns (loss, logits)."""
@@ -267,21 +279,73 @@ class UNet:
         skips = []
         h = x
         L = len(self.widths)
+
+        def cbr(h, skip, n):
+            return Conv3x3BNReLU.apply(h, skip, P[n + ".w"], P[n + ".gamma"], P[n + ".beta"],
+                                       self.batch_mr[n])
+
         for i in range(L):
             name = f"enc{i}" if i < L - 1 else "mid"
-            for k in ("conv0", "conv1"):
-                n = f"{name}.{k}"
-                h = Conv3x3BNReLU.apply(h, None, P[n + ".w"], P[n + ".gamma"], P[n + ".beta"])
+            h = cbr(cbr(h, None, name + ".conv0"), None, name + ".conv1")
             if i < L - 1:
                 skips.append(h)
                 h = MaxPool2.apply(h)
         for i in reversed(range(L - 1)):
             up = UpConv2.apply(h, P[f"dec{i}.up.w"], P[f"dec{i}.up.b"])
-            n = f"dec{i}.conv0"
-            h = Conv3x3BNReLU.apply(up, skips[i], P[n + ".w"], P[n + ".gamma"], P[n + ".beta"])
-            n = f"dec{i}.conv1"
-            h = Conv3x3BNReLU.apply(h, None, P[n + ".w"], P[n + ".gamma"], P[n + ".beta"])
+            h = cbr(cbr(up, skips[i], f"dec{i}.conv0"), None, f"dec{i}.conv1")
         return HeadXent.apply(h, P["head.w"], P["head.b"], labels)
+
+    @torch.no_grad()
+    def update_running_stats(self):
+        """Exponential moving average of the last batch's statistics."""
+        m = self.momentum
+        for n in self.bn_names:
+            mean, rstd = self.batch_mr[n][0], self.batch_mr[n][1]
+            var = 1.0 / (rstd * rstd) - BN_EPS
+            rm, rv = self.running[n]
+            rm.mul_(1 - m).add_(mean, alpha=m)
+            rv.mul_(1 - m).add_(var, alpha=m)
+
+    @torch.no_grad()
+    def infer_logits(self, x: torch.Tensor) -> torch.Tensor:
+        """Inference with the running statistics: fp32 logits [N, H, W, 3].  Every
+        kernel treats pixels independently of the batch, so a chip's logits do
+        not depend on the other chips of the batch."""
+        P = self.params
+        N, H, W, _ = x.shape
+        dev = x.device
+
+        def cbr(h, skip, n):
+            Nn, Hh, Ww, c0 = h.shape
+            c1 = 0 if skip is None else skip.shape[3]
+            wb = _bf16(P[n + ".w"])
+            cout = wb.shape[0]
+            z = torch.empty((Nn, Hh, Ww, cout), dtype=torch.bfloat16, device=dev)
+            _call("sil_unet_conv3x3", _p(h), c0, _p(skip), c1, _p(wb), _p(z), None, Nn, Hh, Ww,
+                  cout, _s())
+            rm, rv = self.running[n]
+            scale = P[n + ".gamma"] / torch.sqrt(rv + BN_EPS)
+            shift = P[n + ".beta"] - rm * scale
+            out = torch.empty_like(z)
+            _call("sil_unet_affine_relu", _p(z), _p(scale.contiguous()), _p(shift.contiguous()),
+                  _p(out), Nn * Hh * Ww, cout, _s())
+            return out
+
+        skips, h, L = [], x, len(self.widths)
+        for i in range(L):
+            name = f"enc{i}" if i < L - 1 else "mid"
+            h = cbr(cbr(h, None, name + ".conv0"), None, name + ".conv1")
+            if i < L - 1:
+                skips.append(h)
+                h = MaxPool2.apply(h)
+        for i in reversed(range(L - 1)):
+            up = UpConv2.apply(h, P[f"dec{i}.up.w"], P[f"dec{i}.up.b"])
+            h = cbr(cbr(up, skips[i], f"dec{i}.conv0"), None, f"dec{i}.conv1")
+        C = h.shape[3]
+        logits = torch.empty((N, H, W, 3), dtype=torch.float32, device=dev)
+        _call("sil_unet_head", _p(h), _p(P["head.w"]), _p(P["head.b"]), _p(logits), N * H * W, C,
+              _s())
+        return logits
 
     def predict(self, x: torch.Tensor) -> torch.Tensor:
         """Class map [N, H, W] (uint8).  Uses batch statistics of `x`, as in training."""
@@ -329,3 +393,11 @@ def chips_input(scene: torch.Tensor, origins: torch.Tensor, chip: int = 256,
     _call("sil_unet_chips_input", _p(scene), H, pitch, pitch, _p(origins.contiguous()), n, chip,
           ctypes.c_float(1.0 / refl_max), _p(out), _s())
     return out
+
+
+def scatter_argmax(logits: torch.Tensor, origins: torch.Tensor, labels: torch.Tensor, H: int,
+                   W: int):
+    """Class map of chips written into a scene label plane [H, >=W] (uint8)."""
+    n, chip = logits.shape[0], logits.shape[1]
+    _call("sil_unet_scatter_argmax", _p(logits.contiguous()), _p(origins.contiguous()), n, chip,
+          _p(labels), H, W, labels.stride(0), _s())

@@ -1,0 +1,82 @@
+"""GPU tests of the learned part: U-Net inference is the same for a chip
+alone and in a batch; a short training on the GPU auto-labels learns the
+labeller's classes and is scored against the synthetic truth beside the
+labeller; the labeller takes over when the U-Net disagrees with it."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mods():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_13135_amd import learn, sil, unet
+    sil.lib()
+    unet._lib()
+    return learn, sil, unet
+
+
+@pytest.fixture(scope="module")
+def trained(mods):
+    learn, sil, unet = mods
+    train_sc = learn.make_scenes(6, 1024, seed0=7100)
+    test_sc = learn.make_scenes(2, 1024, seed0=7200)
+    X, Y = learn.build_training_set(train_sc)
+    model = unet.UNet((16, 32, 32, 64), seed=3)
+    _say(f"case training on {X.shape[0]} auto-labelled chips")
+    losses, sec = learn.train(model, X, Y, steps=150, batch=16, lr=2e-3)
+    _say(f"loss {losses[0]:.3f} -> {np.mean(losses[-10:]):.3f}, {sec * 1e3:.1f} ms/step")
+    return model, losses, test_sc
+
+
+def test_inference_is_batch_invariant(mods, trained):
+    learn, sil, unet = mods
+    model, _, test_sc = trained
+    sc = test_sc[0].scene
+    org = torch.from_numpy(learn.all_origins(1024, 1024)).cuda()
+    x = unet.chips_input(sc, org)
+    full = model.infer_logits(x)
+    for k in (0, 5, 15):
+        alone = model.infer_logits(x[k:k + 1].contiguous())
+        assert torch.equal(alone[0], full[k]), f"chip {k} differs alone vs in the batch"
+    pair = model.infer_logits(x[[3, 9]].contiguous())
+    assert torch.equal(pair[0], full[3]) and torch.equal(pair[1], full[9])
+
+
+def test_training_learns_the_auto_labels(mods, trained):
+    learn, sil, unet = mods
+    model, losses, test_sc = trained
+    assert np.mean(losses[-10:]) < 0.5 * losses[0]
+    ev = learn.evaluate(model, test_sc)
+    _say(f"held-out: {ev}")
+    # the network reproduces the labeller it was trained on...
+    assert ev["unet_labeller_disagreement"] < 0.10
+    # ...and, like the labeller, beats the unfiltered thresholds against the truth
+    assert ev["unet_vs_truth"] > ev["thresholds_only_vs_truth"]
+
+
+def test_fallback_to_the_labeller(mods, trained):
+    learn, sil, unet = mods
+    model, _, test_sc = trained
+    scenes = [sc.scene for sc in test_sc]
+    recs = learn.serve_with_fallback(model, scenes, threshold=0.02)
+    assert all(r["ms"] > 0 for r in recs)
+    # a corrupted network (head biases forcing one class) must fall back
+    saved = model.params["head.b"].detach().clone()
+    with torch.no_grad():
+        model.params["head.b"].copy_(torch.tensor([50.0, 0.0, 0.0], device="cuda"))
+    bad = learn.serve_with_fallback(model, scenes, threshold=0.02)
+    with torch.no_grad():
+        model.params["head.b"].copy_(saved)
+    assert all(r["fallback"] for r in bad)
+    assert all(r["disagreement"] > 0.02 for r in bad)

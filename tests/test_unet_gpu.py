@@ -11,6 +11,7 @@ import torch
 import torch.nn.functional as F
 
 from oracle import unet_ref as U
+from tests import unet_bf16
 
 pytestmark = pytest.mark.gpu
 
@@ -151,16 +152,30 @@ def test_unet_matches_float64_oracle(un):
     lo, logo, go, _ = U.loss_and_grads(P, xo, labels.long(), widths)
     assert abs(loss.item() - lo.item()) < 0.02 * lo.item()
     assert _rel(logits.permute(0, 3, 1, 2), logo) < 0.05
-    worst = {}
+    # bf16 storage alone (float64 arithmetic, bf16 rounding at the GPU's storage
+    # points) moves the gradients by `emul`; the GPU may not do worse than about
+    # twice that, layers next to the loss must be tight, and the gradient as a
+    # whole must point the same way
+    ge = unet_bf16.grads(P, xo, labels, widths)
+    flat_g, flat_o = [], []
+    bad = {}
     for k, v in model.params.items():
         gg = v.grad.detach().cpu().double()
         if k == "enc0.conv0.w":
             gg = gg[..., :3]
         elif k.endswith(".up.w"):
             gg = gg.permute(0, 1, 3, 2)
-        worst[k] = _rel(gg, go[k])
-    bad = {k: e for k, e in worst.items() if e > 0.1}
+        err, emul = _rel(gg, go[k]), _rel(ge[k], go[k])
+        if err > max(0.05, 2.0 * emul):
+            bad[k] = (round(err, 4), round(emul, 4))
+        flat_g.append(gg.reshape(-1))
+        flat_o.append(go[k].reshape(-1))
     assert not bad, bad
+    for k in ("head.w", "head.b", "dec0.conv1.gamma", "dec0.conv1.beta"):
+        gg = model.params[k].grad.detach().cpu().double()
+        assert _rel(gg, go[k]) < 0.02, k
+    cos = F.cosine_similarity(torch.cat(flat_g), torch.cat(flat_o), dim=0).item()
+    assert cos > 0.9, cos
 
 
 def test_training_steps_reduce_loss(un):
