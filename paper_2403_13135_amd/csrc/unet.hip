@@ -5,14 +5,17 @@
 //   * k_gemm_nt: C[m][n] = sum_k A[m][k] * B[n][k], B K-contiguous (weights).
 //     A is read as plain rows, as the 3x3 im2col of one or two NHWC tensors
 //     (channel concatenation of the decoder's up-sampled and skip maps), or as
-//     the 2x2 gather of an up-sampled gradient.  Tiles 128 x BN x 32, 4 waves
-//     of 64 x BN/2, operands double-buffered in LDS (rows padded to 80 bytes).
-//     Epilogues: bf16 store with per-channel sum / sum of squares for batch
-//     normalisation, a channel split into two tensors, or the up-convolution
-//     scatter with bias.
+//     the 2x2 gather of an up-sampled gradient.  Tiles of 4 waves, each wave
+//     64 rows x 16*NJ columns (128 x 128, 128 x 64, or 256 x 32 for narrow
+//     outputs), K steps of 32, operands double-buffered in LDS (rows padded to
+//     80 bytes); a block walks several M tiles.  Epilogues: bf16 store with
+//     per-channel sum / sum of squares for batch normalisation (reduced in LDS,
+//     one atomic per column per block), a channel split into two tensors, or
+//     the up-convolution scatter with bias.
 //   * k_gemm_tn: weight gradients C[m][n] = sum_p A[p][m] * B[p][n] over pixel
 //     ranges (split-K across workgroups, fp32 atomics), both operands
-//     transposed into LDS so MFMA reads stay 16-byte contiguous along p.
+//     transposed into LDS (pixel pairs packed into 4-byte writes) so MFMA reads
+//     stay 16-byte contiguous along p; tiles 32*MI x 32*NJ.
 // Forward conv:  M = pixels, N = cout, K = 9*cin.
 // Input grad:    the same kernel on dy with flipped, transposed weights.
 // Weight grad:   M = cout, N = 9*cin, reduction over pixels.
@@ -20,6 +23,11 @@
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <utility>
 
 #include "sil_unet.h"
 
@@ -30,7 +38,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kGT = 256;      // GEMM threads (4 waves)
-constexpr int kBM = 128;      // GEMM tile rows
 constexpr int kBK = 32;       // reduction step (one MFMA K)
 constexpr int kLdsRow = 40;   // u16 per LDS row: 32 + 8 padding (80 bytes)
 
@@ -42,7 +49,10 @@ __device__ __forceinline__ u16 f2bf(float f) {
   return (u16)(u >> 16);
 }
 
-enum AMode : int { A_ROWS = 0, A_IM2COL = 1, A_UPGATHER = 2 };
+// A_IM2COL32: the im2col of A_IM2COL when c0 + c1 is a multiple of 32, so a
+// 32-wide reduction step lies inside one tap: the tap and channel offset are
+// block-uniform counters and each row's shifted address is one add.
+enum AMode : int { A_ROWS = 0, A_IM2COL = 1, A_UPGATHER = 2, A_IM2COL32 = 3 };
 enum EMode : int { E_STORE = 0, E_SPLIT = 1, E_UPSCATTER = 2 };
 
 struct GemmNT {
@@ -82,124 +92,184 @@ __device__ __forceinline__ uint4 load_a(const GemmNT& g, int32_t m, int32_t img,
   }
 }
 
-template <int AM, int EM, int BN>
+// Tile: WM x WN waves (4 in all), each wave 64 rows x 16*NJ columns, so
+// BM = 64*WM and BN = 16*NJ*WN.  Narrow outputs (32 channels) stack the waves
+// along M (4 x 1) so each im2col tile feeds twice the MFMA work.  A block
+// walks M tiles blockIdx.x, blockIdx.x + gridDim.x, ... (the grid holds about
+// one resident wave of blocks), so the batch-norm sums it adds up are
+// reduced in LDS and reach global memory with one atomic per column per
+// block instead of one per column per tile.
+template <int AM, int EM, int WM, int WN, int NJ>
 __global__ __launch_bounds__(kGT) void k_gemm_nt(GemmNT g) {
-  __shared__ u16 As[2][kBM][kLdsRow];
+  constexpr int BM = 64 * WM, BN = 16 * NJ * WN;
+  static_assert(WM * WN == 4, "four waves");
+  __shared__ u16 As[2][BM][kLdsRow];
   __shared__ u16 Bs[2][BN][kLdsRow];
+  __shared__ float red[WM][2][BN];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int32_t m0 = blockIdx.x * kBM, n0 = blockIdx.y * BN;
-  constexpr int NJ = BN / 32;  // 16-column MFMA blocks per wave
-  constexpr int BCH = BN * 4;  // B chunks per step
-
-  // this thread's A rows (two) and chunk column
+  const int wm = wave / WN, wn = wave % WN;
+  const int32_t n0 = blockIdx.y * BN;
+  const int32_t mtiles = (g.M + BM - 1) / BM;
+  constexpr int BCH = BN * 4;               // B chunks per step
+  constexpr int BR = (BCH + kGT - 1) / kGT;  // B chunks per thread
   const int kq = tid & 3;
-  int32_t am[2], aimg[2], ah[2], aw[2];
-#pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    am[r] = m0 + (tid >> 2) + 64 * r;
-    const int32_t mm = min(am[r], g.M - 1);
-    aimg[r] = mm / (g.H * g.W);
-    const int32_t rem = mm - aimg[r] * g.H * g.W;
-    ah[r] = rem / g.W;
-    aw[r] = rem - ah[r] * g.W;
-  }
-  uint4 ra[2], rb[2];
-  auto gload = [&](int32_t k0) {
-#pragma unroll
-    for (int r = 0; r < 2; ++r) ra[r] = load_a<AM>(g, am[r], aimg[r], ah[r], aw[r], k0 + 8 * kq);
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int c = tid + kGT * r;
-      rb[r] = make_uint4(0, 0, 0, 0);
-      if (c < BCH) {
-        const int32_t n = n0 + (c >> 2), k = k0 + 8 * (c & 3);
-        if (n < g.N && k < g.K) rb[r] = *(const uint4*)(g.b + (int64_t)n * g.K + k);
-      }
-    }
-  };
-  auto lstore = [&](int buf) {
-#pragma unroll
-    for (int r = 0; r < 2; ++r) *(uint4*)&As[buf][(tid >> 2) + 64 * r][8 * kq] = ra[r];
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int c = tid + kGT * r;
-      if (c < BCH) *(uint4*)&Bs[buf][c >> 2][8 * (c & 3)] = rb[r];
-    }
-  };
-
-  f32x4 acc[4][NJ];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-
   const int nk = (g.K + kBK - 1) / kBK;
-  gload(0);
-  lstore(0);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) gload((kt + 1) * kBK);
-    bf16x8 a[4], b[NJ];
+
+  float s1[NJ], s2[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) s1[j] = s2[j] = 0.f;
+
+  for (int32_t mt = blockIdx.x; mt < mtiles; mt += gridDim.x) {
+    const int32_t m0 = mt * BM;
+    // this thread's A rows (WM of them) and chunk column
+    int32_t am[WM], aimg[WM], ah[WM], aw[WM];
+#pragma unroll
+    for (int r = 0; r < WM; ++r) {
+      am[r] = m0 + (tid >> 2) + 64 * r;
+      const int32_t mm = min(am[r], g.M - 1);
+      aimg[r] = mm / (g.H * g.W);
+      const int32_t rem = mm - aimg[r] * g.H * g.W;
+      ah[r] = rem / g.W;
+      aw[r] = rem - ah[r] * g.W;
+    }
+    uint4 ra[WM], rb[BR];
+    int32_t nth = 0, ntw = 0, ncc = 0;  // A_IM2COL32: tap row, column and channel of the next load
+    auto gload = [&](int32_t k0) {
+      if constexpr (AM == A_IM2COL32) {
+        const int32_t ci = ncc + 8 * kq;
+        const bool first = ci < g.c0;
+        const u16* src = first ? g.a0 : g.a1;
+        const int32_t ld = first ? g.c0 : g.c1, off = first ? ci : ci - g.c0;
+        const int32_t dh = nth - 1, dw = ntw - 1;
+#pragma unroll
+        for (int r = 0; r < WM; ++r) {
+          const int32_t hh = ah[r] + dh, ww = aw[r] + dw;
+          ra[r] = make_uint4(0, 0, 0, 0);
+          if (am[r] < g.M && (uint32_t)hh < (uint32_t)g.H && (uint32_t)ww < (uint32_t)g.W)
+            ra[r] = *(const uint4*)(src + (int64_t)(am[r] + dh * g.W + dw) * ld + off);
+        }
+        ncc += kBK;
+        if (ncc == g.c0 + g.c1) {
+          ncc = 0;
+          if (++ntw == 3) {
+            ntw = 0;
+            ++nth;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < WM; ++r)
+          ra[r] = load_a<AM>(g, am[r], aimg[r], ah[r], aw[r], k0 + 8 * kq);
+      }
+#pragma unroll
+      for (int r = 0; r < BR; ++r) {
+        const int c = tid + kGT * r;
+        rb[r] = make_uint4(0, 0, 0, 0);
+        if (c < BCH) {
+          const int32_t n = n0 + (c >> 2), k = k0 + 8 * (c & 3);
+          if (n < g.N && k < g.K) rb[r] = *(const uint4*)(g.b + (int64_t)n * g.K + k);
+        }
+      }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+      for (int r = 0; r < WM; ++r) *(uint4*)&As[buf][(tid >> 2) + 64 * r][8 * kq] = ra[r];
+#pragma unroll
+      for (int r = 0; r < BR; ++r) {
+        const int c = tid + kGT * r;
+        if (c < BCH) *(uint4*)&Bs[buf][c >> 2][8 * (c & 3)] = rb[r];
+      }
+    };
+
+    f32x4 acc[4][NJ];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-      a[i] = __builtin_bit_cast(bf16x8,
-                                *(const uint4*)&As[buf][wm * 64 + 16 * i + (lane & 15)][8 * (lane >> 4)]);
 #pragma unroll
-    for (int j = 0; j < NJ; ++j)
-      b[j] = __builtin_bit_cast(
-          bf16x8, *(const uint4*)&Bs[buf][wn * (BN / 2) + 16 * j + (lane & 15)][8 * (lane >> 4)]);
+      for (int j = 0; j < NJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    // both LDS buffers are free here: the previous tile's last step ended in a barrier
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+      const int buf = kt & 1;
+      if (kt + 1 < nk) gload((kt + 1) * kBK);
+      bf16x8 a[4], b[NJ];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 4; ++i)
+        a[i] = __builtin_bit_cast(
+            bf16x8, *(const uint4*)&As[buf][wm * 64 + 16 * i + (lane & 15)][8 * (lane >> 4)]);
 #pragma unroll
       for (int j = 0; j < NJ; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-    if (kt + 1 < nk) lstore(buf ^ 1);
-    __syncthreads();
+        b[j] = __builtin_bit_cast(
+            bf16x8, *(const uint4*)&Bs[buf][wn * 16 * NJ + 16 * j + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+      if (kt + 1 < nk) lstore(buf ^ 1);
+      __syncthreads();
+    }
+
+    // epilogue: acc[i][j][t] is C[row][col], row = wave rows + 16i + 4*(lane/16) + t,
+    // col = wave cols + 16j + lane%16
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int32_t col = n0 + wn * 16 * NJ + 16 * j + (lane & 15);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int32_t row = m0 + wm * 64 + 16 * i + 4 * (lane >> 4) + t;
+          const float v = acc[i][j][t];
+          if (row >= g.M || col >= g.N) continue;
+          if constexpr (EM == E_STORE) {
+            g.y0[(int64_t)row * g.N + col] = f2bf(v);
+            s1[j] += v;
+            s2[j] += v * v;
+          } else if constexpr (EM == E_SPLIT) {
+            if (col < g.split)
+              g.y0[(int64_t)row * g.split + col] = f2bf(v);
+            else
+              g.y1[(int64_t)row * (g.N - g.split) + (col - g.split)] = f2bf(v);
+          } else {
+            const int32_t q = col / g.up_cout, co = col - q * g.up_cout;
+            const int32_t img = row / (g.H * g.W), rem = row - img * g.H * g.W;
+            const int32_t h = rem / g.W, w = rem - h * g.W;
+            const int64_t pix =
+                ((int64_t)img * 2 * g.H + 2 * h + (q >> 1)) * (2 * g.W) + 2 * w + (q & 1);
+            g.y0[pix * g.up_cout + co] = f2bf(v + g.bias[co]);
+          }
+        }
+    }
   }
 
-  // epilogue: acc[i][j][t] is C[row][col], row = wave rows + 16i + 4*(lane/16) + t,
-  // col = wave cols + 16j + lane%16
+  if constexpr (EM == E_STORE) {
+    if (g.stats) {
+      // lanes l and l ^ 16, l ^ 32 hold the same column: fold them, then the WM
+      // waves that share columns meet in LDS
 #pragma unroll
-  for (int j = 0; j < NJ; ++j) {
-    const int32_t col = n0 + wn * (BN / 2) + 16 * j + (lane & 15);
-    float s1 = 0.f, s2 = 0.f;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int32_t row = m0 + wm * 64 + 16 * i + 4 * (lane >> 4) + t;
-        const float v = acc[i][j][t];
-        if (row >= g.M || col >= g.N) continue;
-        if constexpr (EM == E_STORE) {
-          g.y0[(int64_t)row * g.N + col] = f2bf(v);
-          s1 += v;
-          s2 += v * v;
-        } else if constexpr (EM == E_SPLIT) {
-          if (col < g.split)
-            g.y0[(int64_t)row * g.split + col] = f2bf(v);
-          else
-            g.y1[(int64_t)row * (g.N - g.split) + (col - g.split)] = f2bf(v);
-        } else {
-          const int32_t q = col / g.up_cout, co = col - q * g.up_cout;
-          const int32_t img = row / (g.H * g.W), rem = row - img * g.H * g.W;
-          const int32_t h = rem / g.W, w = rem - h * g.W;
-          const int64_t pix =
-              ((int64_t)img * 2 * g.H + 2 * h + (q >> 1)) * (2 * g.W) + 2 * w + (q & 1);
-          g.y0[pix * g.up_cout + co] = f2bf(v + g.bias[co]);
+      for (int j = 0; j < NJ; ++j) {
+        s1[j] += __shfl_xor(s1[j], 16);
+        s1[j] += __shfl_xor(s1[j], 32);
+        s2[j] += __shfl_xor(s2[j], 16);
+        s2[j] += __shfl_xor(s2[j], 32);
+        if (lane < 16) {
+          red[wm][0][wn * 16 * NJ + 16 * j + lane] = s1[j];
+          red[wm][1][wn * 16 * NJ + 16 * j + lane] = s2[j];
         }
       }
-    if constexpr (EM == E_STORE) {
-      if (g.stats) {
-        s1 += __shfl_xor(s1, 16);
-        s1 += __shfl_xor(s1, 32);
-        s2 += __shfl_xor(s2, 16);
-        s2 += __shfl_xor(s2, 32);
-        if (lane < 16 && col < g.N) {
-          atomicAdd(&g.stats[col], s1);
-          atomicAdd(&g.stats[g.N + col], s2);
+      __syncthreads();
+      if (tid < BN && n0 + tid < g.N) {
+        float t1 = 0.f, t2 = 0.f;
+#pragma unroll
+        for (int r = 0; r < WM; ++r) {
+          t1 += red[r][0][tid];
+          t2 += red[r][1][tid];
         }
+        atomicAdd(&g.stats[n0 + tid], t1);
+        atomicAdd(&g.stats[g.N + n0 + tid], t2);
       }
     }
   }
@@ -223,46 +293,151 @@ struct GemmTN {
   float* c;
 };
 
-template <int MODE>
-__device__ __forceinline__ uint4 load_tn(const GemmTN& g, const u16* base, int32_t ld, int64_t p,
-                                         int32_t idx, bool is_b) {
-  const uint4 zero = make_uint4(0, 0, 0, 0);
-  if (p >= g.P) return zero;
-  if constexpr (MODE == T_PLAIN) {
-    return *(const uint4*)(base + p * ld + idx);
-  } else {
-    const int32_t img = (int32_t)(p / ((int64_t)g.H * g.W));
-    const int32_t rem = (int32_t)(p - (int64_t)img * g.H * g.W);
-    const int32_t h = rem / g.W, w = rem - h * g.W;
-    if constexpr (MODE == T_IM2COL) {
-      const int32_t ct = g.c0 + g.c1;
-      const int32_t tap = idx / ct, ci = idx - tap * ct;
-      const int32_t hh = h + tap / 3 - 1, ww = w + tap % 3 - 1;
-      if (hh < 0 || hh >= g.H || ww < 0 || ww >= g.W) return zero;
-      const int64_t pix = ((int64_t)img * g.H + hh) * g.W + ww;
-      if (ci < g.c0) return *(const uint4*)(g.b0 + pix * g.c0 + ci);
-      return *(const uint4*)(g.b1 + pix * g.c1 + (ci - g.c0));
-    } else {
-      const int32_t cout = g.M / 4;
-      const int32_t q = idx / cout, co = idx - q * cout;
-      const int64_t pix = ((int64_t)img * 2 * g.H + 2 * h + (q >> 1)) * (2 * g.W) + 2 * w + (q & 1);
-      return *(const uint4*)(g.a + pix * cout + co);
+// Pixel coordinates of a running pixel index, advanced without divisions.
+struct Pix {
+  int32_t img, h, w;
+};
+
+__device__ __forceinline__ Pix pix_of(int64_t p, int32_t H, int32_t W) {
+  const int64_t hw = (int64_t)H * W;
+  Pix r;
+  r.img = (int32_t)(p / hw);
+  const int32_t rem = (int32_t)(p - (int64_t)r.img * hw);
+  r.h = rem / W;
+  r.w = rem - r.h * W;
+  return r;
+}
+
+__device__ __forceinline__ void pix_adv(Pix& q, int32_t d, int32_t H, int32_t W) {
+  q.w += d;
+  while (q.w >= W) {
+    q.w -= W;
+    if (++q.h == H) {
+      q.h = 0;
+      ++q.img;
     }
   }
 }
 
-// AM: mode of A (T_PLAIN or T_UPGATHER); BMD: mode of B (T_PLAIN or T_IM2COL).
-template <int AM, int BMD, int BM, int BN>
+// Where one staged 16-byte chunk (8 consecutive m or n at one pixel) comes
+// from; fixed for the whole pixel walk of a block.
+struct TnSrc {
+  const u16* base;
+  int32_t ld, off;  // element = base[pixel * ld + off]
+  int32_t dh, dw;   // pixel shift: 3x3 tap (-1..1) or, when up, 2x2 sub-pixel (0..1)
+  bool ok, up;
+};
+
+__device__ __forceinline__ TnSrc tn_src(const GemmTN& g, int mode, bool is_a, int32_t idx,
+                                        bool ok) {
+  TnSrc s{};
+  s.ok = ok;
+  s.up = mode == T_UPGATHER;
+  if (mode == T_PLAIN) {
+    s.base = is_a ? g.a : g.b0;
+    s.ld = is_a ? g.M : g.N;
+    s.off = idx;
+  } else if (mode == T_IM2COL) {
+    const int32_t ct = g.c0 + g.c1;
+    const int32_t tap = idx / ct, ci = idx - tap * ct;
+    s.dh = tap / 3 - 1;
+    s.dw = tap % 3 - 1;
+    if (ci < g.c0) {
+      s.base = g.b0;
+      s.ld = g.c0;
+      s.off = ci;
+    } else {
+      s.base = g.b1;
+      s.ld = g.c1;
+      s.off = ci - g.c0;
+    }
+  } else {  // m = (i*2 + j)*cout + co over dy [img][2H][2W][cout]
+    const int32_t cout = g.M / 4;
+    const int32_t q = idx / cout;
+    s.base = g.a;
+    s.ld = cout;
+    s.off = idx - q * cout;
+    s.dh = q >> 1;
+    s.dw = q & 1;
+  }
+  return s;
+}
+
+__device__ __forceinline__ uint4 tn_load(const TnSrc& s, const Pix& q, int32_t H, int32_t W,
+                                         bool in_range) {
+  const uint4 zero = make_uint4(0, 0, 0, 0);
+  if (!s.ok || !in_range) return zero;
+  int64_t pix;
+  if (s.up) {
+    pix = ((int64_t)q.img * 2 * H + 2 * q.h + s.dh) * (2 * W) + 2 * q.w + s.dw;
+  } else {
+    const int32_t hh = q.h + s.dh, ww = q.w + s.dw;
+    if (hh < 0 || hh >= H || ww < 0 || ww >= W) return zero;
+    pix = ((int64_t)q.img * H + hh) * W + ww;
+  }
+  return *(const uint4*)(s.base + pix * s.ld + s.off);
+}
+
+// C[m][n] += sum_p A[p][m] B[p][n] over this block's pixel range.  A^T and B^T
+// are staged in one LDS array S (rows 0..BM-1 = m, BM.. = n; 32 pixels per row,
+// double-buffered).  Staging slot c (0 .. 2*(BM+BN)) covers LDS rows
+// 8*(c/16) .. +7 at the pixel pair 2*(c%16), 2*(c%16)+1: two 16-byte loads, then
+// eight 4-byte LDS writes of (pixel 2j, pixel 2j+1) pairs, which land in
+// consecutive banks across the 16 lanes of a row group.
+template <int AM, int BMD, int MI, int NJ>
 __global__ __launch_bounds__(kGT) void k_gemm_tn(GemmTN g) {
-  __shared__ u16 As[BM][kLdsRow];
-  __shared__ u16 Bs[BN][kLdsRow];
+  constexpr int BM = 32 * MI, BN = 32 * NJ;
+  constexpr int SLOTS = 2 * (BM + BN);
+  constexpr int SR = (SLOTS + kGT - 1) / kGT;
+  __shared__ u16 S[2][BM + BN][kLdsRow];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int32_t m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
-  constexpr int MI = BM / 32, NJ = BN / 32;
-  constexpr int ACH = kBK * BM / 8, BCH = kBK * BN / 8;  // 16-byte chunks per step
   const int64_t p_begin = (int64_t)blockIdx.z * g.p_per_split;
   const int64_t p_end = min(g.P, p_begin + g.p_per_split);
+  const int pj = tid & 15;
+
+  TnSrc src[SR];
+#pragma unroll
+  for (int r = 0; r < SR; ++r) {
+    const int c = tid + kGT * r;
+    const int row = 8 * (c >> 4);
+    if (c >= SLOTS) {
+      src[r] = TnSrc{};
+    } else if (row < BM) {
+      src[r] = tn_src(g, AM, true, m0 + row, m0 + row < g.M);
+    } else {
+      src[r] = tn_src(g, BMD, false, n0 + row - BM, n0 + row - BM < g.N);
+    }
+  }
+
+  Pix q = pix_of(p_begin + 2 * pj, g.H, g.W);
+  uint4 rv[SR][2];
+  auto gload = [&](int64_t p0) {
+    Pix q1 = q;
+    pix_adv(q1, 1, g.H, g.W);
+    const int64_t pa = p0 + 2 * pj;
+#pragma unroll
+    for (int r = 0; r < SR; ++r) {
+      rv[r][0] = tn_load(src[r], q, g.H, g.W, pa < p_end);
+      rv[r][1] = tn_load(src[r], q1, g.H, g.W, pa + 1 < p_end);
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < SR; ++r) {
+      const int c = tid + kGT * r;
+      if (c >= SLOTS) continue;
+      const int row = 8 * (c >> 4);
+      const uint32_t w0[4] = {rv[r][0].x, rv[r][0].y, rv[r][0].z, rv[r][0].w};
+      const uint32_t w1[4] = {rv[r][1].x, rv[r][1].y, rv[r][1].z, rv[r][1].w};
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        *(uint32_t*)&S[buf][row + 2 * t][2 * pj] = (w0[t] & 0xffffu) | (w1[t] << 16);
+        *(uint32_t*)&S[buf][row + 2 * t + 1][2 * pj] = (w0[t] >> 16) | (w1[t] & 0xffff0000u);
+      }
+    }
+  };
 
   f32x4 acc[MI][NJ];
 #pragma unroll
@@ -270,42 +445,34 @@ __global__ __launch_bounds__(kGT) void k_gemm_tn(GemmTN g) {
 #pragma unroll
     for (int j = 0; j < NJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+  gload(p_begin);
+  lstore(0);
+  __syncthreads();
+  int buf = 0;
   for (int64_t p0 = p_begin; p0 < p_end; p0 += kBK) {
-    // stage A^T and B^T: chunk c covers 8 consecutive m (or n) at one pixel
-    for (int c = tid; c < ACH; c += kGT) {
-      const int pl = c / (BM / 8), mc = 8 * (c % (BM / 8));
-      const int64_t p = p0 + pl;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (p < p_end && m0 + mc < g.M) v = load_tn<AM>(g, g.a, g.M, p, m0 + mc, false);
-      const u16* e = (const u16*)&v;
-#pragma unroll
-      for (int t = 0; t < 8; ++t) As[mc + t][pl] = e[t];
+    const bool more = p0 + kBK < p_end;
+    if (more) {
+      pix_adv(q, kBK, g.H, g.W);
+      gload(p0 + kBK);
     }
-    for (int c = tid; c < BCH; c += kGT) {
-      const int pl = c / (BN / 8), nc = 8 * (c % (BN / 8));
-      const int64_t p = p0 + pl;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (p < p_end && n0 + nc < g.N) v = load_tn<BMD>(g, g.b0, g.N, p, n0 + nc, true);
-      const u16* e = (const u16*)&v;
-#pragma unroll
-      for (int t = 0; t < 8; ++t) Bs[nc + t][pl] = e[t];
-    }
-    __syncthreads();
     bf16x8 a[MI], b[NJ];
 #pragma unroll
     for (int i = 0; i < MI; ++i)
       a[i] = __builtin_bit_cast(
-          bf16x8, *(const uint4*)&As[wm * (BM / 2) + 16 * i + (lane & 15)][8 * (lane >> 4)]);
+          bf16x8, *(const uint4*)&S[buf][wm * (BM / 2) + 16 * i + (lane & 15)][8 * (lane >> 4)]);
 #pragma unroll
     for (int j = 0; j < NJ; ++j)
       b[j] = __builtin_bit_cast(
-          bf16x8, *(const uint4*)&Bs[wn * (BN / 2) + 16 * j + (lane & 15)][8 * (lane >> 4)]);
+          bf16x8,
+          *(const uint4*)&S[buf][BM + wn * (BN / 2) + 16 * j + (lane & 15)][8 * (lane >> 4)]);
 #pragma unroll
     for (int i = 0; i < MI; ++i)
 #pragma unroll
       for (int j = 0; j < NJ; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    if (more) lstore(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
 #pragma unroll
   for (int i = 0; i < MI; ++i)
@@ -358,6 +525,22 @@ __global__ void k_up_t(const u16* w, u16* wt, int32_t cin, int32_t cout) {
   }
 }
 
+// 8 bf16 <-> 8 floats
+__device__ __forceinline__ void unpack8(uint4 v, float f[8]) {
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    f[2 * i] = __uint_as_float(w[i] << 16);
+    f[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+  }
+}
+__device__ __forceinline__ uint4 pack8(const float f[8]) {
+  uint32_t w[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) w[i] = (uint32_t)f2bf(f[2 * i]) | ((uint32_t)f2bf(f[2 * i + 1]) << 16);
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
 // per-channel (mean, rstd) from sums, in double
 __global__ void k_bn_stats(const float* stats, int32_t C, int64_t count, float eps, float* mr) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -369,72 +552,115 @@ __global__ void k_bn_stats(const float* stats, int32_t C, int64_t count, float e
   mr[C + c] = (float)(1.0 / sqrt(var + (double)eps));
 }
 
+// BN + ReLU, 8 channels per thread (C % 8 == 0)
 __global__ void k_bn_relu(const u16* z, const float* mr, const float* gamma, const float* beta,
                           u16* out, int64_t n, int32_t C) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+  const int64_t n8 = n / 8;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n8;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t c = (int32_t)(i % C);
-    const float v = (bf2f(z[i]) - mr[c]) * mr[C + c] * gamma[c] + beta[c];
-    out[i] = f2bf(v > 0.f ? v : 0.f);
+    const int32_t c0 = (int32_t)((i * 8) % C);
+    float f[8];
+    unpack8(((const uint4*)z)[i], f);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int c = c0 + j;
+      const float v = (f[j] - mr[c]) * mr[C + c] * gamma[c] + beta[c];
+      f[j] = v > 0.f ? v : 0.f;
+    }
+    ((uint4*)out)[i] = pack8(f);
   }
 }
 
-// Per-channel sums over [P][C] of f(p, c) with blocks of 256 threads; C <= 256
-// and 256 % C == 0.  Each block reduces its rows in LDS, then one atomic per
-// channel.
+// Per-channel sums over [P][C] for the BN backward: thread t owns channel
+// group g = t % (C/8) (8 channels, 16-byte loads) and rows t / (C/8) + k *
+// (256 / (C/8)) of its block's row range; C <= 256, 256 % (C/8) == 0.
+// Partial sums meet in LDS, then one atomic per channel per block.
 __global__ void k_bn_bwd_reduce(const u16* dout, const u16* z, const float* mr,
                                 const float* gamma, const float* beta, float* red, int64_t P,
                                 int32_t C) {
-  __shared__ float s1[256], s2[256];
-  const int t = threadIdx.x;
-  const int c = t % C, r0 = t / C, rstep = 256 / C;
-  float a1 = 0.f, a2 = 0.f;
+  __shared__ float s1[256 * 8], s2[256 * 8];
+  const int t = threadIdx.x, G = C / 8;
+  const int g = t % G, r0 = t / G, rstep = 256 / G;
+  const int c0 = 8 * g;
+  float a1[8], a2[8], mean[8], rstd[8], gm[8], bt[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    a1[j] = 0.f;
+    a2[j] = 0.f;
+    mean[j] = mr[c0 + j];
+    rstd[j] = mr[C + c0 + j];
+    gm[j] = gamma[c0 + j];
+    bt[j] = beta[c0 + j];
+  }
   const int64_t rows_per_block = (P + gridDim.x - 1) / gridDim.x;
   const int64_t rb = (int64_t)blockIdx.x * rows_per_block;
   const int64_t re = min(P, rb + rows_per_block);
   for (int64_t p = rb + r0; p < re; p += rstep) {
-    const int64_t i = p * C + c;
-    const float zh = (bf2f(z[i]) - mr[c]) * mr[C + c];
-    const float pre = zh * gamma[c] + beta[c];
-    const float d = pre > 0.f ? bf2f(dout[i]) : 0.f;
-    a1 += d;
-    a2 += d * zh;
+    const int64_t i = (p * C + c0) / 8;
+    float fz[8], fd[8];
+    unpack8(((const uint4*)z)[i], fz);
+    unpack8(((const uint4*)dout)[i], fd);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const float zh = (fz[j] - mean[j]) * rstd[j];
+      const float d = zh * gm[j] + bt[j] > 0.f ? fd[j] : 0.f;
+      a1[j] += d;
+      a2[j] += d * zh;
+    }
   }
-  s1[t] = a1;
-  s2[t] = a2;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    s1[j * 256 + t] = a1[j];
+    s2[j * 256 + t] = a2[j];
+  }
   __syncthreads();
   if (t < C) {
+    const int gg = t / 8, j = t % 8;
     float b1 = 0.f, b2 = 0.f;
-    for (int k = t; k < 256; k += C) {
-      b1 += s1[k];
-      b2 += s2[k];
+    for (int k = gg; k < 256; k += G) {
+      b1 += s1[j * 256 + k];
+      b2 += s2[j * 256 + k];
     }
-    atomicAdd(&red[c], b1);
-    atomicAdd(&red[C + c], b2);
+    atomicAdd(&red[t], b1);
+    atomicAdd(&red[C + t], b2);
   }
 }
 
 __global__ void k_bn_bwd_apply(const u16* dout, const u16* z, const float* mr, const float* gamma,
                                const float* beta, const float* red, u16* dz, int64_t n, int32_t C,
                                float inv_count) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+  const int64_t n8 = n / 8;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n8;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t c = (int32_t)(i % C);
-    const float zh = (bf2f(z[i]) - mr[c]) * mr[C + c];
-    const float pre = zh * gamma[c] + beta[c];
-    const float d = pre > 0.f ? bf2f(dout[i]) : 0.f;
-    const float g = gamma[c] * mr[C + c] * (d - (red[c] + zh * red[C + c]) * inv_count);
-    dz[i] = f2bf(g);
+    const int32_t c0 = (int32_t)((i * 8) % C);
+    float fz[8], fd[8], o[8];
+    unpack8(((const uint4*)z)[i], fz);
+    unpack8(((const uint4*)dout)[i], fd);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int c = c0 + j;
+      const float zh = (fz[j] - mr[c]) * mr[C + c];
+      const float d = zh * gamma[c] + beta[c] > 0.f ? fd[j] : 0.f;
+      o[j] = gamma[c] * mr[C + c] * (d - (red[c] + zh * red[C + c]) * inv_count);
+    }
+    ((uint4*)dz)[i] = pack8(o);
   }
 }
 
 __global__ void k_affine_relu(const u16* z, const float* scale, const float* shift, u16* out,
                               int64_t n, int32_t C) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+  const int64_t n8 = n / 8;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n8;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t c = (int32_t)(i % C);
-    const float v = bf2f(z[i]) * scale[c] + shift[c];
-    out[i] = f2bf(v > 0.f ? v : 0.f);
+    const int32_t c0 = (int32_t)((i * 8) % C);
+    float f[8];
+    unpack8(((const uint4*)z)[i], f);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const float v = f[j] * scale[c0 + j] + shift[c0 + j];
+      f[j] = v > 0.f ? v : 0.f;
+    }
+    ((uint4*)out)[i] = pack8(f);
   }
 }
 
@@ -466,47 +692,66 @@ __global__ void k_add_vec(float* dst, const float* src, int32_t n) {
   if (i < n) dst[i] += src[i];
 }
 
+// 2x2 max pool, 8 channels per thread
 __global__ void k_maxpool(const u16* x, u16* y, uint8_t* idx, int32_t N, int32_t H, int32_t W,
                           int32_t C) {
-  const int32_t Ho = H / 2, Wo = W / 2;
-  const int64_t n = (int64_t)N * Ho * Wo * C;
+  const int32_t Ho = H / 2, Wo = W / 2, G = C / 8;
+  const int64_t n = (int64_t)N * Ho * Wo * G;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t c = (int32_t)(i % C);
-    int64_t r = i / C;
+    const int32_t g = (int32_t)(i % G);
+    int64_t r = i / G;
     const int32_t wo = (int32_t)(r % Wo);
     r /= Wo;
     const int32_t ho = (int32_t)(r % Ho);
     const int32_t img = (int32_t)(r / Ho);
-    float best = 0.f;
-    int bi = 0;
+    float best[8], v[8];
+    uint32_t bi[8];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const float v = bf2f(x[(((int64_t)img * H + 2 * ho + (k >> 1)) * W + 2 * wo + (k & 1)) * C + c]);
-      if (k == 0 || v > best) {
-        best = v;
-        bi = k;
-      }
+      unpack8(*(const uint4*)(x + (((int64_t)img * H + 2 * ho + (k >> 1)) * W + 2 * wo + (k & 1)) *
+                                      C + 8 * g),
+              v);
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (k == 0 || v[j] > best[j]) {
+          best[j] = v[j];
+          bi[j] = (uint32_t)k;
+        }
     }
-    y[i] = f2bf(best);
-    idx[i] = (uint8_t)bi;
+    ((uint4*)y)[i] = pack8(best);
+    uint2 packed;
+    packed.x = bi[0] | (bi[1] << 8) | (bi[2] << 16) | (bi[3] << 24);
+    packed.y = bi[4] | (bi[5] << 8) | (bi[6] << 16) | (bi[7] << 24);
+    ((uint2*)idx)[i] = packed;
   }
 }
 
 __global__ void k_maxpool_bwd(const u16* dy, const uint8_t* idx, u16* dx, int32_t N, int32_t H,
                               int32_t W, int32_t C) {
-  const int64_t n = (int64_t)N * H * W * C;
+  const int32_t G = C / 8;
+  const int64_t n = (int64_t)N * H * W * G;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t c = (int32_t)(i % C);
-    int64_t r = i / C;
+    const int32_t g = (int32_t)(i % G);
+    int64_t r = i / G;
     const int32_t w = (int32_t)(r % W);
     r /= W;
     const int32_t h = (int32_t)(r % H);
     const int32_t img = (int32_t)(r / H);
-    const int64_t o = (((int64_t)img * (H / 2) + h / 2) * (W / 2) + w / 2) * C + c;
-    const int k = (h & 1) * 2 + (w & 1);
-    dx[i] = idx[o] == k ? dy[o] : (u16)0;
+    const int64_t o = (((int64_t)img * (H / 2) + h / 2) * (W / 2) + w / 2) * G + g;
+    const uint32_t k = (uint32_t)((h & 1) * 2 + (w & 1));
+    const uint4 d = ((const uint4*)dy)[o];
+    const uint2 ix = ((const uint2*)idx)[o];
+    const uint32_t dw[4] = {d.x, d.y, d.z, d.w};
+    uint32_t out[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t word = q < 2 ? ix.x : ix.y;
+      const uint32_t lo = (word >> (16 * (q & 1))) & 0xffu, hi = (word >> (16 * (q & 1) + 8)) & 0xffu;
+      out[q] = (lo == k ? (dw[q] & 0xffffu) : 0u) | (hi == k ? (dw[q] & 0xffff0000u) : 0u);
+    }
+    ((uint4*)dx)[i] = make_uint4(out[0], out[1], out[2], out[3]);
   }
 }
 
@@ -515,11 +760,15 @@ __global__ void k_head(const u16* x, const float* w, const float* b, float* logi
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P;
        p += (int64_t)gridDim.x * blockDim.x) {
     float l0 = b[0], l1 = b[1], l2 = b[2];
-    for (int32_t c = 0; c < C; ++c) {
-      const float v = bf2f(x[p * C + c]);
-      l0 += v * w[c];
-      l1 += v * w[C + c];
-      l2 += v * w[2 * C + c];
+    for (int32_t c0 = 0; c0 < C; c0 += 8) {
+      float f[8];
+      unpack8(*(const uint4*)(x + p * C + c0), f);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        l0 += f[j] * w[c0 + j];
+        l1 += f[j] * w[C + c0 + j];
+        l2 += f[j] * w[2 * C + c0 + j];
+      }
     }
     logits[3 * p] = l0;
     logits[3 * p + 1] = l1;
@@ -558,12 +807,17 @@ __global__ void k_softmax_xent(const float* logits, const uint8_t* labels, float
 
 // head backward, input gradient: one thread per (pixel, channel)
 __global__ void k_head_dx(const float* w, const float* dl, u16* dx, int64_t P, int32_t C) {
-  const int64_t n = P * C;
+  const int32_t G = C / 8;
+  const int64_t n = P * G;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t p = i / C;
-    const int32_t c = (int32_t)(i - p * C);
-    dx[i] = f2bf(dl[3 * p] * w[c] + dl[3 * p + 1] * w[C + c] + dl[3 * p + 2] * w[2 * C + c]);
+    const int64_t p = i / G;
+    const int32_t c0 = 8 * (int32_t)(i - p * G);
+    const float d0 = dl[3 * p], d1 = dl[3 * p + 1], d2 = dl[3 * p + 2];
+    float o[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) o[j] = d0 * w[c0 + j] + d1 * w[C + c0 + j] + d2 * w[2 * C + c0 + j];
+    ((uint4*)dx)[i] = pack8(o);
   }
 }
 
@@ -630,21 +884,30 @@ __global__ void k_argmax(const float* logits, uint8_t* labels, int64_t P) {
   }
 }
 
-// column sums of dy [P][C] into db (accumulate); blocks of 256, 256 % C == 0
+// column sums of dy [P][C] into db (accumulate); 8 channels per thread,
+// blocks of 256, 256 % (C/8) == 0
 __global__ void k_colsum(const u16* dy, float* db, int64_t P, int32_t C) {
-  __shared__ float s[256];
-  const int t = threadIdx.x, c = t % C, r0 = t / C, rstep = 256 / C;
-  float a = 0.f;
+  __shared__ float s[256 * 8];
+  const int t = threadIdx.x, G = C / 8;
+  const int g = t % G, r0 = t / G, rstep = 256 / G;
+  float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   const int64_t rows_per_block = (P + gridDim.x - 1) / gridDim.x;
   const int64_t rb = (int64_t)blockIdx.x * rows_per_block;
   const int64_t re = min(P, rb + rows_per_block);
-  for (int64_t p = rb + r0; p < re; p += rstep) a += bf2f(dy[p * C + c]);
-  s[t] = a;
+  for (int64_t p = rb + r0; p < re; p += rstep) {
+    float f[8];
+    unpack8(*(const uint4*)(dy + p * C + 8 * g), f);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a[j] += f[j];
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) s[j * 256 + t] = a[j];
   __syncthreads();
   if (t < C) {
+    const int gg = t / 8, j = t % 8;
     float b = 0.f;
-    for (int k = t; k < 256; k += C) b += s[k];
-    atomicAdd(&db[c], b);
+    for (int k = gg; k < 256; k += G) b += s[j * 256 + k];
+    atomicAdd(&db[t], b);
   }
 }
 
@@ -686,6 +949,10 @@ __global__ void k_adam(float* w, const float* g, float* m, float* v, u16* wbf, i
 
 // ---- host helpers ---------------------------------------------------------------
 
+// Reductions that end in global atomics run at most this many blocks: atomics
+// on one address serialise, so their count, not the bytes read, would bound them.
+constexpr int kRedBlocks = 1024;
+
 int grid_for(int64_t n, int block = 256) {
   int64_t g = (n + block - 1) / block;
   if (g > 8192) g = 8192;
@@ -695,25 +962,66 @@ int grid_for(int64_t n, int block = 256) {
 
 int done() { return hipGetLastError() == hipSuccess ? SIL_OK : SIL_EDEVICE; }
 
+// Blocks of `kernel` (256 threads) that fit on the current device at once.
+int resident_blocks(const void* kernel) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  std::lock_guard<std::mutex> lock(mu);
+  auto key = std::make_pair(dev, kernel);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kGT, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    cus = 256;
+  const int n = per_cu * cus;
+  cache[key] = n;
+  return n;
+}
+
+template <int AM, int EM, int WM, int WN, int NJ>
+void launch_nt_tile(const GemmNT& g, hipStream_t st) {
+  constexpr int BM = 64 * WM, BN = 16 * NJ * WN;
+  auto kern = k_gemm_nt<AM, EM, WM, WN, NJ>;
+  const int gy = (g.N + BN - 1) / BN;
+  const int mtiles = (g.M + BM - 1) / BM;
+  const int cap = std::max(1, resident_blocks((const void*)kern) / gy);
+  dim3 grid(std::min(mtiles, cap), gy);
+  hipLaunchKernelGGL(kern, grid, dim3(kGT), 0, st, g);
+}
+
 template <int AM, int EM>
 int launch_nt(const GemmNT& g, hipStream_t st) {
   (void)hipGetLastError();
-  const int bn = g.N % 128 == 0 ? 128 : (g.N % 64 == 0 ? 64 : 32);
-  dim3 grid((g.M + kBM - 1) / kBM, (g.N + bn - 1) / bn);
-  if (bn == 128)
-    hipLaunchKernelGGL((k_gemm_nt<AM, EM, 128>), grid, dim3(kGT), 0, st, g);
-  else if (bn == 64)
-    hipLaunchKernelGGL((k_gemm_nt<AM, EM, 64>), grid, dim3(kGT), 0, st, g);
-  else
-    hipLaunchKernelGGL((k_gemm_nt<AM, EM, 32>), grid, dim3(kGT), 0, st, g);
+  if (g.N % 128 == 0)
+    launch_nt_tile<AM, EM, 2, 2, 4>(g, st);
+  else if (g.N % 64 == 0)
+    launch_nt_tile<AM, EM, 2, 2, 2>(g, st);
+  else  // narrow outputs: 256 x 32 tiles, waves stacked along M
+    launch_nt_tile<AM, EM, 4, 1, 2>(g, st);
   return done();
 }
 
+// Weight-gradient tile (32*MI x 32*NJ): the widest N tile that divides N
+// (192, 128, 96, 64), else 96 for N <= 96, else 32.
 template <int AM, int BMD>
 int launch_tn(GemmTN g, hipStream_t st) {
   (void)hipGetLastError();
-  const int bm = g.M % 128 == 0 ? 128 : (g.M % 64 == 0 ? 64 : 32);
-  const int bn = g.N % 128 == 0 ? 128 : (g.N % 64 == 0 ? 64 : 32);
+  const int mi = g.M % 128 == 0 ? 4 : (g.M % 64 == 0 ? 2 : 1);
+  int nj;
+  if (mi == 4 && g.N % 128 == 0) nj = 4;
+  else if (g.N % 192 == 0) nj = 6;
+  else if (g.N % 128 == 0) nj = 4;
+  else if (g.N % 96 == 0) nj = 3;
+  else if (g.N % 64 == 0) nj = 2;
+  else if (g.N <= 96) nj = 3;
+  else nj = 1;
+  const int bm = 32 * mi, bn = 32 * nj;
   const int64_t tiles = (int64_t)((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn);
   // split the pixel reduction so that roughly 2048 workgroups run
   int64_t splits = (2048 + tiles - 1) / tiles;
@@ -723,19 +1031,16 @@ int launch_tn(GemmTN g, hipStream_t st) {
   g.p_per_split = ((g.P + splits - 1) / splits + kBK - 1) / kBK * kBK;
   splits = (g.P + g.p_per_split - 1) / g.p_per_split;
   dim3 grid((g.M + bm - 1) / bm, (g.N + bn - 1) / bn, (unsigned)splits);
-#define SIL_TN(BMv, BNv) \
-  hipLaunchKernelGGL((k_gemm_tn<AM, BMD, BMv, BNv>), grid, dim3(kGT), 0, st, g)
-  if (bm == 128 && bn == 128) SIL_TN(128, 128);
-  else if (bm == 128 && bn == 64) SIL_TN(128, 64);
-  else if (bm == 128) SIL_TN(128, 32);
-  else if (bm == 64 && bn == 128) SIL_TN(64, 128);
-  else if (bm == 64 && bn == 64) SIL_TN(64, 64);
-  else if (bm == 64) SIL_TN(64, 32);
-  else if (bn == 128) SIL_TN(32, 128);
-  else if (bn == 64) SIL_TN(32, 64);
-  else SIL_TN(32, 32);
+#define SIL_TN(MIv, NJv)                                                            \
+  if (mi == MIv && nj == NJv) {                                                     \
+    hipLaunchKernelGGL((k_gemm_tn<AM, BMD, MIv, NJv>), grid, dim3(kGT), 0, st, g); \
+    return done();                                                                  \
+  }
+  SIL_TN(4, 4) SIL_TN(4, 6) SIL_TN(4, 3) SIL_TN(4, 2) SIL_TN(4, 1)
+  SIL_TN(2, 6) SIL_TN(2, 4) SIL_TN(2, 3) SIL_TN(2, 2) SIL_TN(2, 1)
+  SIL_TN(1, 6) SIL_TN(1, 4) SIL_TN(1, 3) SIL_TN(1, 2) SIL_TN(1, 1)
 #undef SIL_TN
-  return done();
+  return SIL_EINVAL;
 }
 
 bool ok_dims(int32_t N, int32_t H, int32_t W) { return N > 0 && H > 0 && W > 0; }
@@ -762,6 +1067,7 @@ int sil_unet_conv3x3(const void* x0, int32_t c0, const void* x1, int32_t c1, con
   g.b = (const u16*)w;
   g.y0 = (u16*)y;
   g.stats = stats;
+  if ((c0 + c1) % kBK == 0) return launch_nt<A_IM2COL32, E_STORE>(g, (hipStream_t)stream);
   return launch_nt<A_IM2COL, E_STORE>(g, (hipStream_t)stream);
 }
 
@@ -782,8 +1088,10 @@ int sil_unet_conv3x3_dgrad(const void* dy, int32_t cout, const void* wt, void* d
   g.y0 = (u16*)dx0;
   g.y1 = (u16*)dx1;
   g.split = c1 > 0 ? c0 : c0 + c1;
-  if (c1 > 0) return launch_nt<A_IM2COL, E_SPLIT>(g, (hipStream_t)stream);
-  return launch_nt<A_IM2COL, E_STORE>(g, (hipStream_t)stream);
+  hipStream_t st = (hipStream_t)stream;
+  if (cout % kBK == 0)
+    return c1 > 0 ? launch_nt<A_IM2COL32, E_SPLIT>(g, st) : launch_nt<A_IM2COL32, E_STORE>(g, st);
+  return c1 > 0 ? launch_nt<A_IM2COL, E_SPLIT>(g, st) : launch_nt<A_IM2COL, E_STORE>(g, st);
 }
 
 int sil_unet_conv3x3_wgrad(const void* dy, int32_t cout, const void* x0, int32_t c0,
@@ -867,9 +1175,9 @@ int sil_unet_upconv_wgrad(const void* x, const void* dy, float* dw, float* db, i
   g.c = dw;
   int rc = launch_tn<T_UPGATHER, T_PLAIN>(g, (hipStream_t)stream);
   if (rc != SIL_OK) return rc;
-  if (256 % cout) return SIL_EINVAL;
+  if (cout > 256 || 256 % cout) return SIL_EINVAL;
   const int64_t Pout = (int64_t)N * 4 * H * W;
-  hipLaunchKernelGGL(k_colsum, dim3(grid_for(Pout / 64 + 1, 1)), dim3(256), 0,
+  hipLaunchKernelGGL(k_colsum, dim3(std::min(grid_for(Pout * (cout / 8) / 2048 + 1, 1), kRedBlocks)), dim3(256), 0,
                      (hipStream_t)stream, (const u16*)dy, db, Pout, cout);
   return done();
 }
@@ -886,24 +1194,24 @@ int sil_unet_up_t(const void* w, void* wt, int32_t cin, int32_t cout, void* stre
 int sil_unet_bn_relu(const void* z, const float* stats, const float* gamma, const float* beta,
                      float eps, int64_t count, void* out, float* mr, int64_t P, int32_t C,
                      void* stream) {
-  if (!z || !stats || !gamma || !beta || !out || !mr || count <= 0 || P <= 0 || C <= 0)
+  if (!z || !stats || !gamma || !beta || !out || !mr || count <= 0 || P <= 0 || C <= 0 || C % 8)
     return SIL_EINVAL;
   (void)hipGetLastError();
   hipStream_t st = (hipStream_t)stream;
   hipLaunchKernelGGL(k_bn_stats, dim3((C + 255) / 256), dim3(256), 0, st, stats, C, count, eps,
                      mr);
   const int64_t n = P * C;
-  hipLaunchKernelGGL(k_bn_relu, dim3(grid_for(n)), dim3(256), 0, st, (const u16*)z, mr, gamma,
+  hipLaunchKernelGGL(k_bn_relu, dim3(grid_for(n / 8)), dim3(256), 0, st, (const u16*)z, mr, gamma,
                      beta, (u16*)out, n, C);
   return done();
 }
 
 int sil_unet_affine_relu(const void* z, const float* scale, const float* shift, void* out,
                          int64_t P, int32_t C, void* stream) {
-  if (!z || !scale || !shift || !out || P <= 0 || C <= 0) return SIL_EINVAL;
+  if (!z || !scale || !shift || !out || P <= 0 || C <= 0 || C % 8) return SIL_EINVAL;
   (void)hipGetLastError();
   const int64_t n = P * C;
-  hipLaunchKernelGGL(k_affine_relu, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream,
+  hipLaunchKernelGGL(k_affine_relu, dim3(grid_for(n / 8)), dim3(256), 0, (hipStream_t)stream,
                      (const u16*)z, scale, shift, (u16*)out, n, C);
   return done();
 }
@@ -925,15 +1233,15 @@ int sil_unet_bn_relu_bwd(const void* dout, const void* z, const float* mr, const
                          const float* beta, void* dz, float* dgamma, float* dbeta, float* red,
                          int64_t P, int32_t C, void* stream) {
   if (!dout || !z || !mr || !gamma || !beta || !dz || !dgamma || !dbeta || !red || P <= 0 ||
-      C <= 0 || C > 256 || 256 % C)
+      C < 8 || C > 256 || 256 % C)
     return SIL_EINVAL;
   (void)hipGetLastError();
   hipStream_t st = (hipStream_t)stream;
   hipLaunchKernelGGL(k_fill, dim3(1), dim3(256), 0, st, red, (int64_t)2 * C, 0.f);
-  hipLaunchKernelGGL(k_bn_bwd_reduce, dim3(grid_for(P / 64 + 1, 1)), dim3(256), 0, st,
+  hipLaunchKernelGGL(k_bn_bwd_reduce, dim3(std::min(grid_for(P * (C / 8) / 2048 + 1, 1), kRedBlocks)), dim3(256), 0, st,
                      (const u16*)dout, (const u16*)z, mr, gamma, beta, red, P, C);
   const int64_t n = P * C;
-  hipLaunchKernelGGL(k_bn_bwd_apply, dim3(grid_for(n)), dim3(256), 0, st, (const u16*)dout,
+  hipLaunchKernelGGL(k_bn_bwd_apply, dim3(grid_for(n / 8)), dim3(256), 0, st, (const u16*)dout,
                      (const u16*)z, mr, gamma, beta, red, (u16*)dz, n, C, 1.f / (float)P);
   hipLaunchKernelGGL(k_add_vec, dim3((C + 255) / 256), dim3(256), 0, st, dbeta, red, C);
   hipLaunchKernelGGL(k_add_vec, dim3((C + 255) / 256), dim3(256), 0, st, dgamma, red + C, C);
@@ -942,9 +1250,10 @@ int sil_unet_bn_relu_bwd(const void* dout, const void* z, const float* mr, const
 
 int sil_unet_maxpool(const void* x, void* y, uint8_t* idx, int32_t N, int32_t H, int32_t W,
                      int32_t C, void* stream) {
-  if (!x || !y || !idx || !ok_dims(N, H, W) || H % 2 || W % 2 || C <= 0) return SIL_EINVAL;
+  if (!x || !y || !idx || !ok_dims(N, H, W) || H % 2 || W % 2 || C <= 0 || C % 8)
+    return SIL_EINVAL;
   (void)hipGetLastError();
-  const int64_t n = (int64_t)N * (H / 2) * (W / 2) * C;
+  const int64_t n = (int64_t)N * (H / 2) * (W / 2) * (C / 8);
   hipLaunchKernelGGL(k_maxpool, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream,
                      (const u16*)x, (u16*)y, idx, N, H, W, C);
   return done();
@@ -952,9 +1261,10 @@ int sil_unet_maxpool(const void* x, void* y, uint8_t* idx, int32_t N, int32_t H,
 
 int sil_unet_maxpool_bwd(const void* dy, const uint8_t* idx, void* dx, int32_t N, int32_t H,
                          int32_t W, int32_t C, void* stream) {
-  if (!dy || !idx || !dx || !ok_dims(N, H, W) || H % 2 || W % 2 || C <= 0) return SIL_EINVAL;
+  if (!dy || !idx || !dx || !ok_dims(N, H, W) || H % 2 || W % 2 || C <= 0 || C % 8)
+    return SIL_EINVAL;
   (void)hipGetLastError();
-  const int64_t n = (int64_t)N * H * W * C;
+  const int64_t n = (int64_t)N * H * W * (C / 8);
   hipLaunchKernelGGL(k_maxpool_bwd, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream,
                      (const u16*)dy, idx, (u16*)dx, N, H, W, C);
   return done();
@@ -962,7 +1272,7 @@ int sil_unet_maxpool_bwd(const void* dy, const uint8_t* idx, void* dx, int32_t N
 
 int sil_unet_head(const void* x, const float* w, const float* b, float* logits, int64_t P,
                   int32_t C, void* stream) {
-  if (!x || !w || !b || !logits || P <= 0 || C <= 0) return SIL_EINVAL;
+  if (!x || !w || !b || !logits || P <= 0 || C <= 0 || C % 8) return SIL_EINVAL;
   (void)hipGetLastError();
   hipLaunchKernelGGL(k_head, dim3(grid_for(P)), dim3(256), 0, (hipStream_t)stream,
                      (const u16*)x, w, b, logits, P, C);
@@ -973,20 +1283,20 @@ int sil_unet_softmax_xent(const float* logits, const uint8_t* labels, float* los
                           float* dlogits, float scale, int64_t P, void* stream) {
   if (!logits || !labels || !loss || P <= 0) return SIL_EINVAL;
   (void)hipGetLastError();
-  hipLaunchKernelGGL(k_softmax_xent, dim3(grid_for(P)), dim3(256), 0, (hipStream_t)stream,
+  hipLaunchKernelGGL(k_softmax_xent, dim3(std::min(grid_for(P), kRedBlocks)), dim3(256), 0, (hipStream_t)stream,
                      logits, labels, loss, dlogits, scale, P);
   return done();
 }
 
 int sil_unet_head_bwd(const void* x, const float* w, const float* dlogits, void* dx, float* dw,
                       float* db, int64_t P, int32_t C, void* stream) {
-  if (!x || !w || !dlogits || !dx || !dw || !db || P <= 0 || C <= 0 || C > 256 || 256 % C)
+  if (!x || !w || !dlogits || !dx || !dw || !db || P <= 0 || C < 8 || C > 256 || 256 % C)
     return SIL_EINVAL;
   (void)hipGetLastError();
   hipStream_t st = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_head_dx, dim3(grid_for(P * C)), dim3(256), 0, st, w, dlogits, (u16*)dx,
+  hipLaunchKernelGGL(k_head_dx, dim3(grid_for(P * C / 8)), dim3(256), 0, st, w, dlogits, (u16*)dx,
                      P, C);
-  hipLaunchKernelGGL(k_head_dw, dim3(grid_for(P / 64 + 1, 1)), dim3(256), 0, st, (const u16*)x,
+  hipLaunchKernelGGL(k_head_dw, dim3(std::min(grid_for(P / 64 + 1, 1), kRedBlocks)), dim3(256), 0, st, (const u16*)x,
                      dlogits, dw, db, P, C);
   return done();
 }

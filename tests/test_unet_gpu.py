@@ -40,9 +40,15 @@ def _rel(a, b):
     return (a - b).norm().item() / max(b.norm().item(), 1e-30)
 
 
+# Shapes reach every tile family: narrow (32-wide) and wide outputs, ragged
+# weight-gradient N tiles (9*cin = 72), N tiles of 96/192/128 with 32-, 64- and
+# 128-row M tiles, and a 256 x 256 batch whose M tiles outnumber the resident
+# blocks, so each block of the forward GEMM walks several tiles.
 @pytest.mark.parametrize("N,H,W,c0,c1,cout", [(2, 16, 16, 8, 0, 32), (1, 9, 13, 16, 16, 8),
                                               (2, 32, 32, 32, 0, 64), (1, 8, 8, 64, 64, 128),
-                                              (3, 4, 4, 128, 0, 256)])
+                                              (3, 4, 4, 128, 0, 256), (1, 16, 16, 32, 32, 32),
+                                              (2, 8, 8, 64, 0, 64), (1, 8, 8, 64, 0, 128),
+                                              (1, 8, 8, 32, 0, 128), (4, 256, 256, 32, 0, 32)])
 def test_conv3x3_forward_and_gradients(un, N, H, W, c0, c1, cout):
     _say(f"case conv3x3 {N, H, W, c0, c1, cout}")
     g = torch.Generator().manual_seed(N * 1000 + H * 10 + cout)
