@@ -166,6 +166,30 @@ static uint8_t filtered_value(uint8_t m, const sil_ref_chip_info* info) {
   return info->stretch ? sil_ref_stretch(m, info->lo, info->hi) : m;
 }
 
+/* 192-bit product of a 128-bit and a 64-bit unsigned integer, as three
+ * 64-bit limbs (least significant first), and their comparison: the exact
+ * Otsu and gate comparisons of chips beyond 256^2 pixels exceed 128 bits. */
+typedef struct {
+  uint64_t w[3];
+} u192;
+
+static u192 mul_128_64(u128 a, uint64_t b) {
+  u128 lo = (u128)(uint64_t)a * b;
+  u128 hi = (u128)(uint64_t)(a >> 64) * b;
+  u192 r;
+  r.w[0] = (uint64_t)lo;
+  u128 mid = (lo >> 64) + (u128)(uint64_t)hi;
+  r.w[1] = (uint64_t)mid;
+  r.w[2] = (uint64_t)(hi >> 64) + (uint64_t)(mid >> 64);
+  return r;
+}
+
+static int cmp_192(u192 a, u192 b) {
+  for (int i = 2; i >= 0; --i)
+    if (a.w[i] != b.w[i]) return a.w[i] > b.w[i] ? 1 : -1;
+  return 0;
+}
+
 void sil_ref_chip_stats(const uint32_t* h, const sil_ref_params* p,
                         sil_ref_chip_info* info) {
   uint64_t N = 0, S = 0, Q = 0;
@@ -178,7 +202,8 @@ void sil_ref_chip_stats(const uint32_t* h, const sil_ref_params* p,
   /* Otsu: maximise the between-class variance over splits {v <= t} |
    * {v > t}.  With class weights w0, w1 and sums S0, S1,
    *   sigma_B^2 * N^2 = (w1*S0 - w0*S1)^2 / (w0*w1),
-   * compared exactly as fractions num/den; the smallest t wins ties. */
+   * compared exactly as fractions num/den (192-bit cross products, so
+   * chips of up to 2^27 pixels compare exactly); the smallest t wins ties. */
   int32_t best_t = -1;
   u128 best_num = 0;
   uint64_t best_den = 1;
@@ -192,7 +217,7 @@ void sil_ref_chip_stats(const uint32_t* h, const sil_ref_params* p,
     u128 num = (u128)(diff < 0 ? -diff : diff);
     num *= num;
     uint64_t den = w0 * w1;
-    if (best_t < 0 || num * best_den > best_num * den) {
+    if (best_t < 0 || cmp_192(mul_128_64(num, best_den), mul_128_64(best_num, den)) > 0) {
       best_t = (int32_t)t;
       best_num = num;
       best_den = den;
@@ -205,7 +230,8 @@ void sil_ref_chip_stats(const uint32_t* h, const sil_ref_params* p,
   info->gate = 0;
   if (best_t >= 0) {
     u128 var = (u128)N * Q - (u128)S * S;
-    info->gate = (u128)p->eta_den * best_num >= (u128)p->eta_num * best_den * var;
+    info->gate = cmp_192(mul_128_64(best_num, p->eta_den),
+                         mul_128_64(var * best_den, p->eta_num)) >= 0;
   }
 
   /* Truncation levels: lo is the (k+1)-th smallest value, hi the (k+1)-th
@@ -310,5 +336,174 @@ int sil_ref_label(const void* scene, int32_t nbands, const int32_t* sel, int32_t
 
   free(V);
   free(Vc);
+  return SIL_REF_OK;
+}
+
+/* ---- general labeller: full HSV masks, any filter unit, filtered RGB ---- */
+
+void sil_ref_hsv8(uint8_t r, uint8_t g, uint8_t b, uint8_t* h, uint8_t* s, uint8_t* v) {
+  /* OpenCV's 8-bit HSV convention: V = max(R,G,B) in 0..255, S = 255*(V-min)/V
+   * in 0..255, H = hue in degrees / 2 in 0..179 (hexcone model: the hue
+   * angle is 60 degrees times the sector position).  Rounding is half up;
+   * when two channels tie for the maximum, red takes precedence over green
+   * and green over blue. */
+  int32_t V = r > g ? r : g;
+  V = V > b ? V : b;
+  int32_t m = r < g ? r : g;
+  m = m < b ? m : b;
+  int32_t d = V - m;
+  *v = (uint8_t)V;
+  *s = V == 0 ? 0 : (uint8_t)((510 * d + V) / (2 * V));
+  if (d == 0) {
+    *h = 0;
+    return;
+  }
+  /* sector position times d: red sector (g-b), green 2d + (b-r), blue 4d + (r-g) */
+  int32_t num;
+  if (V == r)
+    num = g - b;
+  else if (V == g)
+    num = 2 * d + (b - r);
+  else
+    num = 4 * d + (r - g);
+  /* hue / 2 = 30 * num / d, rounded half up: floor((60 num + d) / (2 d)) */
+  int32_t top = 60 * num + d, bot = 2 * d;
+  int32_t q = top >= 0 ? top / bot : -((-top + bot - 1) / bot);
+  if (q < 0) q += 180;
+  *h = (uint8_t)q;
+}
+
+void sil_ref_hsv8_many(const uint8_t* rgb, int64_t n, uint8_t* hsv) {
+  for (int64_t i = 0; i < n; ++i)
+    sil_ref_hsv8(rgb[3 * i], rgb[3 * i + 1], rgb[3 * i + 2], &hsv[3 * i], &hsv[3 * i + 1],
+                 &hsv[3 * i + 2]);
+}
+
+uint8_t sil_ref_filtered_band(uint8_t c, uint8_t v, uint8_t vc) {
+  /* scale the pixel's colour so that its brightness becomes vc:
+   * c' = c * vc / v, rounded half up; a black pixel stays black */
+  if (v == 0) return 0;
+  return (uint8_t)(((uint32_t)c * vc + v / 2u) / v);
+}
+
+int sil_ref_validate_ex(int32_t nbands, const int32_t* sel, int32_t H, int32_t W,
+                        int64_t pitch, int64_t mask_pitch, const sil_ref_params* p) {
+  if (!p || !sel) return SIL_REF_EINVAL;
+  if (p->abi != SIL_REF_ABI_VERSION) return SIL_REF_EINVAL;
+  if (p->dtype != SIL_REF_U8 && p->dtype != SIL_REF_U16) return SIL_REF_EINVAL;
+  if (p->dtype == SIL_REF_U16 && p->refl_max < 1) return SIL_REF_EINVAL;
+  if (p->filter > 1) return SIL_REF_EINVAL;
+  if (p->chip < 1 || p->clip_shift < 1 || p->clip_shift > 31) return SIL_REF_EINVAL;
+  if (p->eta_den < 1 || p->eta_num > p->eta_den) return SIL_REF_EINVAL;
+  if (p->patch_h < 1 || p->patch_w < 1) return SIL_REF_EINVAL;
+  if (H < 1 || W < 1 || pitch < W || mask_pitch < W || nbands < 1) return SIL_REF_EINVAL;
+  for (int i = 0; i < 3; ++i)
+    if (sel[i] < 0 || sel[i] >= nbands) return SIL_REF_EINVAL;
+  if (p->dtype == SIL_REF_U16 && p->refl_max > 65535) return SIL_REF_EUNSUPPORTED;
+  /* the exact statistics hold for chips of at most 2^27 pixels */
+  if (p->filter == 1) {
+    int64_t ch = (int64_t)p->chip < H ? (int64_t)p->chip : H;
+    int64_t cw = (int64_t)p->chip < W ? (int64_t)p->chip : W;
+    if (ch * cw > ((int64_t)1 << 27)) return SIL_REF_EUNSUPPORTED;
+  }
+  return SIL_REF_OK;
+}
+
+int sil_ref_label_ex(const void* scene, int32_t nbands, const int32_t* sel, int32_t H,
+                     int32_t W, int64_t pitch, const sil_ref_params* p, uint8_t* masks,
+                     int64_t mask_pitch, uint32_t* counts, uint8_t* rgb, int64_t rgb_pitch,
+                     sil_ref_chip_info* chips) {
+  if (!scene || !masks) return SIL_REF_EINVAL;
+  int rc = sil_ref_validate_ex(nbands, sel, H, W, pitch, mask_pitch, p);
+  if (rc != SIL_REF_OK) return rc;
+  if (rgb && rgb_pitch < W) return SIL_REF_EINVAL;
+  int32_t ny, nx;
+  sil_ref_hist_dims(H, W, p, &ny, &nx);
+
+  const int64_t npx = (int64_t)H * W;
+  const int64_t plane = (int64_t)H * pitch;
+  uint8_t* C8 = malloc((size_t)(3 * npx)); /* 8-bit blue, green, red planes */
+  uint8_t* V = malloc((size_t)npx);
+  uint8_t* Vc = malloc((size_t)npx);
+  uint8_t* Vm = p->filter ? malloc((size_t)npx) : NULL;
+  if (!C8 || !V || !Vc || (p->filter && !Vm)) {
+    free(C8);
+    free(V);
+    free(Vc);
+    free(Vm);
+    return SIL_REF_EINVAL;
+  }
+
+  /* 1. each band to 8 bit (16-bit input: the same rescale as V), and V */
+  for (int i = 0; i < 3; ++i)
+    for (int32_t y = 0; y < H; ++y)
+      for (int32_t x = 0; x < W; ++x) {
+        int64_t idx = sel[i] * plane + (int64_t)y * pitch + x;
+        uint32_t raw = p->dtype == SIL_REF_U8 ? ((const uint8_t*)scene)[idx]
+                                               : ((const uint16_t*)scene)[idx];
+        C8[i * npx + (int64_t)y * W + x] =
+            p->dtype == SIL_REF_U8 ? (uint8_t)raw : sil_ref_rescale(raw, p->refl_max);
+      }
+  for (int64_t k = 0; k < npx; ++k) {
+    uint8_t m = C8[k];
+    if (C8[npx + k] > m) m = C8[npx + k];
+    if (C8[2 * npx + k] > m) m = C8[2 * npx + k];
+    V[k] = m;
+  }
+
+  /* 2-4. filtered brightness, exactly as the fused labeller but for any chip */
+  if (p->filter == 0) {
+    memcpy(Vc, V, (size_t)npx);
+  } else {
+    sil_ref_median3x3(V, H, W, Vm);
+    const int64_t C = p->chip;
+    const int64_t ncy = (H + C - 1) / C, ncx = (W + C - 1) / C;
+    for (int64_t cy = 0; cy < ncy; ++cy)
+      for (int64_t cx = 0; cx < ncx; ++cx) {
+        int64_t y0 = cy * C, y1 = y0 + C < H ? y0 + C : H;
+        int64_t x0 = cx * C, x1 = x0 + C < W ? x0 + C : W;
+        uint32_t h[256] = {0};
+        for (int64_t y = y0; y < y1; ++y)
+          for (int64_t x = x0; x < x1; ++x) h[Vm[y * W + x]]++;
+        sil_ref_chip_info info;
+        sil_ref_chip_stats(h, p, &info);
+        if (chips) chips[cy * ncx + cx] = info;
+        for (int64_t y = y0; y < y1; ++y)
+          for (int64_t x = x0; x < x1; ++x) Vc[y * W + x] = filtered_value(Vm[y * W + x], &info);
+      }
+  }
+
+  /* 5. the three inRange masks on (H, S, Vc); H and S of the pixel's own
+   * 8-bit colour (blue = sel[0], green = sel[1], red = sel[2]) */
+  if (counts) memset(counts, 0, sizeof(uint32_t) * 3 * (size_t)ny * (size_t)nx);
+  for (int32_t y = 0; y < H; ++y)
+    for (int32_t x = 0; x < W; ++x) {
+      int64_t k = (int64_t)y * W + x;
+      uint8_t hh, ss, vv;
+      sil_ref_hsv8(C8[2 * npx + k], C8[npx + k], C8[k], &hh, &ss, &vv);
+      const uint8_t vc = Vc[k];
+      uint8_t bits = 0;
+      for (int c = 0; c < 3; ++c)
+        if (p->lo[c][0] <= hh && hh <= p->hi[c][0] && p->lo[c][1] <= ss && ss <= p->hi[c][1] &&
+            p->lo[c][2] <= vc && vc <= p->hi[c][2])
+          bits |= (uint8_t)(1u << c);
+      masks[(int64_t)y * mask_pitch + x] = bits;
+      /* 6. per-patch mask counts */
+      if (counts) {
+        int64_t py = y / (int64_t)p->patch_h, px = x / (int64_t)p->patch_w;
+        for (int c = 0; c < 3; ++c)
+          if (bits >> c & 1u) counts[(py * nx + px) * 3 + c]++;
+      }
+      /* filtered colour image */
+      if (rgb)
+        for (int i = 0; i < 3; ++i)
+          rgb[(int64_t)i * H * rgb_pitch + (int64_t)y * rgb_pitch + x] =
+              sil_ref_filtered_band(C8[i * npx + k], V[k], vc);
+    }
+
+  free(C8);
+  free(V);
+  free(Vc);
+  free(Vm);
   return SIL_REF_OK;
 }

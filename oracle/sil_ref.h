@@ -97,6 +97,34 @@ void sil_ref_chip_stats(const uint32_t* h, const sil_ref_params* p,
 uint8_t sil_ref_stretch(uint8_t m, uint8_t lo, uint8_t hi);
 int sil_ref_class_of(uint8_t vc, const sil_ref_params* p);
 
+/* General labeller (the variants of the method): three inRange masks on full
+ * HSV limits, a filter unit of any size up to a whole scene, and optionally
+ * the filtered colour image.
+ *   - H and S are those of the pixel's own 8-bit colour (OpenCV 8-bit
+ *     convention: H = hue/2 in 0..179, S in 0..255, rounded half up); V is
+ *     replaced by the filtered Vc.  Since H and S do not change when a colour
+ *     is scaled, this is inRange on the HSV of the filtered colour image up to
+ *     that image's rounding.
+ *   - masks: [H][mask_pitch] bytes, bit c set iff mask c (0 water, 1 thin,
+ *     2 thick) holds; limits are free (masks may overlap or leave pixels out).
+ *   - counts (nullable): [ny][nx][3], pixels with bit c set per patch.
+ *   - rgb (nullable): planar [3][H][rgb_pitch], plane i the filtered band
+ *     sel[i]: c' = c * Vc / V rounded half up (0 where V = 0), so its maximum
+ *     over the bands is exactly Vc.
+ *   - chips (nullable, filter = 1): per-chip statistics as sil_ref_label.
+ * Validation as sil_ref_label except: any H/S/V limits, any chip side (a
+ * chip of more than 2^27 pixels is SIL_REF_EUNSUPPORTED). */
+int sil_ref_validate_ex(int32_t nbands, const int32_t* sel, int32_t H, int32_t W,
+                        int64_t pitch, int64_t mask_pitch, const sil_ref_params* p);
+int sil_ref_label_ex(const void* scene, int32_t nbands, const int32_t* sel, int32_t H,
+                     int32_t W, int64_t pitch, const sil_ref_params* p, uint8_t* masks,
+                     int64_t mask_pitch, uint32_t* counts, uint8_t* rgb, int64_t rgb_pitch,
+                     sil_ref_chip_info* chips);
+void sil_ref_hsv8(uint8_t r, uint8_t g, uint8_t b, uint8_t* h, uint8_t* s, uint8_t* v);
+/* sil_ref_hsv8 over n interleaved (r, g, b) triples into (h, s, v) triples */
+void sil_ref_hsv8_many(const uint8_t* rgb, int64_t n, uint8_t* hsv);
+uint8_t sil_ref_filtered_band(uint8_t c, uint8_t v, uint8_t vc);
+
 #ifdef __cplusplus
 }
 #endif

@@ -86,6 +86,17 @@ def lib():
         L.sil_ref_stretch.restype = ctypes.c_uint8
         L.sil_ref_class_of.argtypes = [ctypes.c_uint8, P(Params)]
         L.sil_ref_class_of.restype = ctypes.c_int
+        L.sil_ref_validate_ex.argtypes = L.sil_ref_validate.argtypes
+        L.sil_ref_validate_ex.restype = ctypes.c_int
+        L.sil_ref_label_ex.argtypes = [ctypes.c_void_p, ctypes.c_int32, P(ctypes.c_int32),
+                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                       P(Params), ctypes.c_void_p, ctypes.c_int64,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                       ctypes.c_void_p]
+        L.sil_ref_label_ex.restype = ctypes.c_int
+        L.sil_ref_hsv8_many.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+        L.sil_ref_filtered_band.argtypes = [ctypes.c_uint8, ctypes.c_uint8, ctypes.c_uint8]
+        L.sil_ref_filtered_band.restype = ctypes.c_uint8
         L.sil_ref_strerror.argtypes = [ctypes.c_int]
         L.sil_ref_strerror.restype = ctypes.c_char_p
         _lib = L
@@ -205,3 +216,57 @@ def class_of(vc: int, params: Params = None) -> int:
     if params is None:
         params = make_params()
     return int(lib().sil_ref_class_of(vc, ctypes.byref(params)))
+
+
+# ---- the general labeller (variants) -----------------------------------------
+
+def validate_ex(nbands, sel, H, W, pitch, mask_pitch, params):
+    return lib().sil_ref_validate_ex(nbands, _sel_array(sel), H, W, pitch, mask_pitch,
+                                     ctypes.byref(params))
+
+
+def label_ex(scene: np.ndarray, params: Params = None, sel=(0, 1, 2), W: int = None,
+             want_rgb: bool = False, want_chips: bool = False):
+    """General labeller on ``scene`` [nbands, H, pitch]: returns a dict with
+    ``masks`` [H, W] (bit c = mask c), ``counts`` [ny, nx, 3], and, when asked,
+    ``rgb`` [3, H, W] (the filtered bands in ``sel`` order) and ``chips``."""
+    if params is None:
+        params = make_params()
+    scene = np.ascontiguousarray(scene)
+    nb, H, pitch = scene.shape
+    W = pitch if W is None else W
+    want = U8 if scene.dtype == np.uint8 else U16
+    if scene.dtype not in (np.uint8, np.uint16) or params.dtype != want:
+        raise ValueError("scene dtype does not match params.dtype")
+    ny, nx = hist_dims(H, W, params)
+    masks = np.full((H, W), 0xEE, dtype=np.uint8)
+    counts = np.zeros((ny, nx, 3), dtype=np.uint32)
+    rgb = np.full((3, H, W), 0xEE, dtype=np.uint8) if want_rgb else None
+    chips = None
+    if want_chips:
+        C = params.chip
+        chips = np.zeros(((H + C - 1) // C, (W + C - 1) // C), dtype=CHIP_DTYPE)
+    rc = lib().sil_ref_label_ex(scene.ctypes.data, nb, _sel_array(sel), H, W, pitch,
+                                ctypes.byref(params), masks.ctypes.data, W, counts.ctypes.data,
+                                rgb.ctypes.data if want_rgb else None, W,
+                                chips.ctypes.data if want_chips else None)
+    if rc:
+        raise OracleError(rc)
+    out = {"masks": masks, "counts": counts}
+    if want_rgb:
+        out["rgb"] = rgb
+    if want_chips:
+        out["chips"] = chips
+    return out
+
+
+def hsv8(rgb: np.ndarray) -> np.ndarray:
+    """OpenCV-convention 8-bit HSV of [..., 3] (r, g, b) uint8 triples."""
+    rgb = np.ascontiguousarray(rgb, dtype=np.uint8)
+    out = np.zeros_like(rgb)
+    lib().sil_ref_hsv8_many(rgb.ctypes.data, rgb.size // 3, out.ctypes.data)
+    return out
+
+
+def filtered_band(c: int, v: int, vc: int) -> int:
+    return int(lib().sil_ref_filtered_band(c, v, vc))

@@ -105,6 +105,62 @@ def stretch(m, lo, hi):
     return int(Fraction(c - lo) * 255 / (hi - lo) + Fraction(1, 2)) if hi > lo else m
 
 
+def filtered_v(scene, dtype="u8", refl_max=10000, filter=1, chip=256, clip_shift=8,
+               eta_num=3, eta_den=4, sel=(0, 1, 2)):
+    """The filtered brightness Vc [H, W] (int64) composed from the checkers
+    above, and the 8-bit (blue, green, red) planes it came from."""
+    s = np.asarray(scene)
+    planes = [s[i].astype(np.int64) for i in sel]
+    if dtype == "u16":
+        lut = {}
+        planes = [np.vectorize(lambda v: lut.setdefault(v, rescale_decimal(int(v), refl_max)))(
+            pl).astype(np.int64) for pl in planes]
+    V = np.maximum(np.maximum(planes[0], planes[1]), planes[2])
+    if filter == 0:
+        return V, planes
+    Hh, W = V.shape
+    Vm = median3x3(V)
+    Vc = Vm.copy()
+    for cy in range((Hh + chip - 1) // chip):
+        for cx in range((W + chip - 1) // chip):
+            blk = Vm[cy * chip:(cy + 1) * chip, cx * chip:(cx + 1) * chip]
+            px = blk.ravel().tolist()
+            t = otsu_within(px)
+            gate = t is not None and eta(px, t) >= Fraction(eta_num, eta_den)
+            rlo, rhi = ranks(px, clip_shift)
+            if gate and rhi > rlo:
+                Vc[cy * chip:(cy + 1) * chip, cx * chip:(cx + 1) * chip] = np.vectorize(
+                    lambda m: stretch(int(m), rlo, rhi))(blk)
+    return Vc, planes
+
+
+def otsu_hist_within(h):
+    """Otsu from a histogram with exact rationals, by the within-class form:
+    minimise sum over both classes of (sum v^2 h - (sum v h)^2 / weight), t =
+    0..254, both classes non-empty, smallest t on ties.  Returns (t or None,
+    eta = 1 - within / total as a Fraction or None)."""
+    h = [int(x) for x in h]
+    N = sum(h)
+    S = sum(v * h[v] for v in range(256))
+    Q = sum(v * v * h[v] for v in range(256))
+    total = Fraction(Q) - Fraction(S * S, N)
+    best_t, best = None, None
+    w0 = s0 = q0 = 0
+    for t in range(255):
+        w0 += h[t]
+        s0 += t * h[t]
+        q0 += t * t * h[t]
+        w1, s1, q1 = N - w0, S - s0, Q - q0
+        if w0 == 0 or w1 == 0:
+            continue
+        sw = Fraction(q0) - Fraction(s0 * s0, w0) + Fraction(q1) - Fraction(s1 * s1, w1)
+        if best is None or sw < best:
+            best, best_t = sw, t
+    if best_t is None:
+        return None, None
+    return best_t, 1 - best / total
+
+
 def label_scene(scene, dtype="u8", refl_max=10000, filter=1, chip=256, clip_shift=8,
                 eta_num=3, eta_den=4, patch_h=256, patch_w=256, sel=(0, 1, 2),
                 lo=PAPER_LO, hi=PAPER_HI):
