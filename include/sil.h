@@ -180,6 +180,63 @@ typedef struct sil_job {
  * is enqueued on error.  Allocates nothing; asynchronous on `stream`. */
 int sil_label_batch(const sil_job* jobs, int32_t njobs, const sil_params* p, void* stream);
 
+/* ---- General labeller: the variants of the method ------------------------
+ *
+ * sil_label_ex computes what sil_label does, generalised in the three ways
+ * the paper leaves open to the fused kernel:
+ *   - the three inRange masks of section III-B on FULL hue / saturation /
+ *     value limits.  H and S are those of the pixel's own 8-bit colour in
+ *     OpenCV's 8-bit convention (H = hue in degrees / 2, 0..179; S = 255 *
+ *     (max - min) / max, 0..255; both rounded half up; red wins a tie for the
+ *     maximum, then green); V is the filtered brightness Vc.  Scaling a colour
+ *     leaves H and S unchanged, so this is inRange on the HSV of the filtered
+ *     colour image up to that image's rounding.  Limits are free: masks may
+ *     overlap or leave pixels in no mask, so the output is a bit mask;
+ *   - a filter unit (p->chip) of any side, up to the whole scene (section
+ *     III-A filters whole scenes; section IV uses 256 x 256 chips);
+ *   - the filtered colour image, the U-Net's input in the inference workflow
+ *     (section III-C): c' = (c * Vc + V/2) div V per 8-bit band (0 where
+ *     V = 0), whose maximum over the bands is exactly Vc.
+ * The filter (median, per-chip Otsu gate, truncation and stretch) is the same
+ * definition as sil_label's; its exact comparisons are carried in 192 bits so
+ * that chips of up to 2^27 pixels stay exact.
+ *
+ *   scene, nbands, sel, H, W, pitch   as sil_label; 16-bit scenes must be
+ *                 2-byte aligned.
+ *   masks         device, [H][mask_pitch] bytes, mask_pitch >= W: bit c of
+ *                 pixel (y, x) is set iff mask c holds (c = 0 water, 1 thin
+ *                 ice, 2 thick ice, the paper's three ranges).
+ *   counts        device, nullable, uint32 [ny][nx][3] (sil_hist_dims), fully
+ *                 overwritten: pixels of patch (py, px) with bit c set.
+ *   rgb           device, nullable, planar [3][H][rgb_pitch] bytes, rgb_pitch
+ *                 >= W: plane i is the filtered band sel[i].
+ *   chips         device, nullable; with filter = 1 the per-chip statistics
+ *                 [ceil(H/chip)][ceil(W/chip)] (a1/a2 refer to the last
+ *                 V-interval holding the filtered value).
+ *   workspace     device, caller-owned scratch of at least
+ *                 sil_label_ex_workspace() bytes (0 when filter = 0, where it
+ *                 may be NULL); its contents are not kept between calls.
+ *   stream        hipStream_t or NULL.
+ *
+ * Errors: SIL_EINVAL for NULL scene/masks/sel/p, a too small or NULL
+ * workspace with filter = 1, rgb_pitch < W with rgb, a misaligned 16-bit
+ * scene, and sil_label's argument errors except those on H/S/V limits (any
+ * limits are accepted) and chip > 256; SIL_EUNSUPPORTED for a chip of more
+ * than 2^27 pixels (min(chip,H) * min(chip,W)), refl_max > 65535 or
+ * H*W >= 2^31; SIL_EDEVICE on a launch failure.  Allocates nothing;
+ * asynchronous on `stream`. */
+int sil_label_ex_validate(int32_t nbands, const int32_t sel[3], int32_t H, int32_t W,
+                          int64_t pitch, int64_t mask_pitch, const sil_params* p);
+
+/* Workspace bytes sil_label_ex needs for an H x W scene under p (0 when
+ * filter = 0).  SIL_EINVAL on NULL pointers, H or W < 1 or chip < 1. */
+int sil_label_ex_workspace(int32_t H, int32_t W, const sil_params* p, uint64_t* bytes);
+
+int sil_label_ex(const void* scene, int32_t nbands, const int32_t sel[3], int32_t H, int32_t W,
+                 int64_t pitch, const sil_params* p, uint8_t* masks, int64_t mask_pitch,
+                 uint32_t* counts, uint8_t* rgb, int64_t rgb_pitch, sil_chip_info* chips,
+                 void* workspace, uint64_t workspace_bytes, void* stream);
+
 /* Human-readable text of a return code (static storage). */
 const char* sil_strerror(int code);
 

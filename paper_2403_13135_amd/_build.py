@@ -5,7 +5,7 @@ import subprocess
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libsil.so")
-SOURCES = [os.path.join(PKG, "csrc", n) for n in ("sil.hip", "server.cpp", "unet.hip")]
+SOURCES = [os.path.join(PKG, "csrc", n) for n in ("sil.hip", "label_ex.hip", "server.cpp", "unet.hip")]
 INCLUDE = os.path.join(ROOT, "include")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1,0 +1,635 @@
+// label_ex.hip -- gfx950 kernels and C ABI of the general labeller: the
+// variants of the method of arXiv 2403.13135 that the fused labeller
+// (sil.hip) does not take.  The operation is stated in include/sil.h
+// (sil_label_ex):
+//   * the three inRange masks of section III-B on full hue / saturation /
+//     value limits (OpenCV 8-bit HSV), emitted as a per-pixel bit mask;
+//   * a filter unit of any size up to the whole scene (section III-A
+//     filters whole scenes as well as the 256 x 256 chips of section IV);
+//   * the filtered colour image c' = c * Vc / V, the U-Net's input in the
+//     inference workflow of section III-C.
+//
+// Three passes over HBM instead of the fused one, because a chip of
+// arbitrary size no longer fits one workgroup:
+//   A. k_ex_median (filter = 1): blocks own (chip, part) pairs and walk 16 x
+//      256 tiles of their chip; V = max(B,G,R) of the tile plus a one-pixel
+//      halo (clamped at the scene border) is staged in LDS, each thread takes
+//      one column and slides the 3x3 median down it (column sorts + median of
+//      three triples), writes the 8-bit median plane to the workspace and
+//      counts it in an 8-copy LDS histogram; one global atomic per nonzero
+//      bin and block.
+//   B. k_ex_stats: one wave per chip: exact Otsu with 192-bit cross-
+//      multiplied comparisons (chips up to 2^27 pixels), the eta gate, rank-k
+//      truncation levels and the stretch, written as a 256-entry table
+//      median -> filtered value.
+//   C. k_ex_apply: 8 x 256 tiles; per pixel the three 8-bit bands, V, the
+//      filtered Vc from the table, H and S, the masks, the filtered colour and
+//      per-patch mask counts (per-thread runs, wave-reduced when the wave
+//      shares a patch, LDS counters per tile, one global atomic per nonzero
+//      counter and tile).
+// Divisions by small run-time divisors use a float estimate corrected by one
+// integer step, which is exact for the operand ranges involved.
+
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "sil.h"
+
+namespace {
+
+constexpr int kTR = 16;           // pass A tile rows
+constexpr int kTC = 256;          // tile columns (= threads per block)
+constexpr int kTRC = 8;           // pass C tile rows
+constexpr int kMaxTilePatches = 128;
+constexpr int64_t kMaxChipPixels = int64_t(1) << 27;
+
+struct ExArgs {
+  const uint8_t* band[3];  // planes sel[0], sel[1], sel[2] (blue, green, red)
+  int64_t pitch_b;         // row pitch in bytes
+  int32_t H, W;
+  int32_t u16;
+  uint32_t refl_max;
+  double rinv;             // 1 / refl_max
+  int32_t filter;
+  int32_t chip, ncx, nchips;
+  int32_t ph, pw, nx;
+  int32_t cnt_lds;         // per-tile LDS counters (else per-pixel global atomics)
+  uint8_t lo[3][3], hi[3][3];
+  uint32_t clip_shift, eta_num, eta_den;
+  uint8_t* vm;             // workspace: [H][W] median plane
+  uint32_t* hist;          // workspace: [nchips][256]
+  uint8_t* lut;            // workspace: [nchips][256] median -> filtered value
+  uint8_t* masks;
+  int64_t mask_pitch;
+  uint32_t* counts;
+  uint8_t* rgb;
+  int64_t rgb_pitch;
+  sil_chip_info* chips;
+};
+
+// floor(n / d) for n < 2^18, 1 <= d <= 1024 (rd = 1.0f / d): the float
+// estimate is within one of the quotient, and one integer step corrects it.
+__device__ __forceinline__ uint32_t div_small(uint32_t n, uint32_t d, float rd) {
+  uint32_t q = (uint32_t)((float)n * rd);
+  const int32_t r = (int32_t)n - (int32_t)(q * d);
+  return r < 0 ? q - 1 : (r >= (int32_t)d ? q + 1 : q);
+}
+
+// 16-bit reflectance to 8 bit: round-half-up of x * 255 / refl_max,
+// saturating (double estimate within one of the quotient, then corrected).
+__device__ __forceinline__ uint32_t to8(uint32_t x, const ExArgs& a) {
+  if (!a.u16) return x;
+  const uint32_t n = x * 255u + a.refl_max / 2u;
+  uint32_t q = (uint32_t)((double)n * a.rinv);
+  const int64_t r = (int64_t)n - (int64_t)q * a.refl_max;
+  q = r < 0 ? q - 1 : (r >= (int64_t)a.refl_max ? q + 1 : q);
+  return q > 255u ? 255u : q;
+}
+
+__device__ __forceinline__ uint32_t raw_at(const ExArgs& a, int i, int32_t y, int32_t x) {
+  const uint8_t* row = a.band[i] + (int64_t)y * a.pitch_b;
+  return a.u16 ? (uint32_t)((const uint16_t*)row)[x] : (uint32_t)row[x];
+}
+
+// V = max over the bands (max commutes with the non-decreasing rescale)
+__device__ __forceinline__ uint32_t value_at(const ExArgs& a, int32_t y, int32_t x) {
+  const uint32_t m = max(max(raw_at(a, 0, y, x), raw_at(a, 1, y, x)), raw_at(a, 2, y, x));
+  return to8(m, a);
+}
+
+__device__ __forceinline__ uint32_t min3u(uint32_t a, uint32_t b, uint32_t c) {
+  return min(min(a, b), c);
+}
+__device__ __forceinline__ uint32_t max3u(uint32_t a, uint32_t b, uint32_t c) {
+  return max(max(a, b), c);
+}
+__device__ __forceinline__ uint32_t med3u(uint32_t a, uint32_t b, uint32_t c) {
+  return max(min(a, b), min(max(a, b), c));
+}
+
+// ---- pass A: median plane and per-chip histograms ------------------------------
+
+__global__ __launch_bounds__(kTC) void k_ex_median(ExArgs a, int32_t parts) {
+  __shared__ uint8_t sv[kTR + 2][kTC + 4];
+  __shared__ uint32_t sh[8][256];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < 8 * 256; i += kTC) (&sh[0][0])[i] = 0;
+  const int32_t chip_id = blockIdx.x / parts, part = blockIdx.x % parts;
+  const int32_t cy = chip_id / a.ncx, cx = chip_id - cy * a.ncx;
+  const int32_t y0 = (int32_t)((int64_t)cy * a.chip), x0 = (int32_t)((int64_t)cx * a.chip);
+  const int32_t ch = min(a.chip, a.H - y0), cw = min(a.chip, a.W - x0);
+  const int32_t nty = (ch + kTR - 1) / kTR, ntx = (cw + kTC - 1) / kTC;
+  uint32_t* hc = sh[tid & 7];
+  __syncthreads();
+  for (int32_t t = part; t < nty * ntx; t += parts) {
+    const int32_t ty = y0 + (t / ntx) * kTR, tx = x0 + (t % ntx) * kTC;
+    const int32_t rows = min(kTR, y0 + ch - ty), cols = min(kTC, x0 + cw - tx);
+    for (int r = 0; r < rows + 2; ++r) {
+      const int32_t y = min(max(ty - 1 + r, 0), a.H - 1);
+      for (int c = tid; c < cols + 2; c += kTC) {
+        const int32_t x = min(max(tx - 1 + c, 0), a.W - 1);
+        sv[r][c] = (uint8_t)value_at(a, y, x);
+      }
+    }
+    __syncthreads();
+    if (tid < cols) {
+      // sorted column triples of the three columns around pixel column tid
+      uint32_t p0[3], p1[3];  // rows r and r + 1 of columns tid .. tid + 2
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        p0[k] = sv[0][tid + k];
+        p1[k] = sv[1][tid + k];
+      }
+      uint8_t* out = a.vm + (int64_t)ty * a.W + tx + tid;
+      for (int r = 0; r < rows; ++r) {
+        uint32_t p2[3], lo3[3], md3[3], hi3[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          p2[k] = sv[r + 2][tid + k];
+          lo3[k] = min3u(p0[k], p1[k], p2[k]);
+          md3[k] = med3u(p0[k], p1[k], p2[k]);
+          hi3[k] = max3u(p0[k], p1[k], p2[k]);
+        }
+        const uint32_t m = med3u(max3u(lo3[0], lo3[1], lo3[2]), med3u(md3[0], md3[1], md3[2]),
+                                 min3u(hi3[0], hi3[1], hi3[2]));
+        out[(int64_t)r * a.W] = (uint8_t)m;
+        atomicAdd(&hc[m], 1u);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          p0[k] = p1[k];
+          p1[k] = p2[k];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) s += sh[k][tid];
+  if (s) atomicAdd(&a.hist[(int64_t)chip_id * 256 + tid], s);
+}
+
+// ---- pass B: per-chip statistics -------------------------------------------------
+
+typedef unsigned __int128 u128;
+
+struct U192 {
+  uint64_t w0, w1, w2;
+};
+
+__device__ __forceinline__ U192 mul_128_64(u128 a, uint64_t b) {
+  const u128 lo = (u128)(uint64_t)a * b;
+  const u128 hi = (u128)(uint64_t)(a >> 64) * b;
+  const u128 mid = (lo >> 64) + (u128)(uint64_t)hi;
+  return U192{(uint64_t)lo, (uint64_t)mid, (uint64_t)(hi >> 64) + (uint64_t)(mid >> 64)};
+}
+
+__device__ __forceinline__ int cmp192(const U192& a, const U192& b) {
+  if (a.w2 != b.w2) return a.w2 > b.w2 ? 1 : -1;
+  if (a.w1 != b.w1) return a.w1 > b.w1 ? 1 : -1;
+  if (a.w0 != b.w0) return a.w0 > b.w0 ? 1 : -1;
+  return 0;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_scan_incl(T v, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const T o = __shfl_up(v, d);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) v += __shfl_xor(v, d);
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) v = min(v, (uint32_t)__shfl_xor((int)v, d));
+  return v;
+}
+
+__device__ __forceinline__ int32_t wave_max(int32_t v) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) v = max(v, __shfl_xor(v, d));
+  return v;
+}
+
+__global__ __launch_bounds__(64) void k_ex_stats(ExArgs a) {
+  const int32_t chip = blockIdx.x;
+  const int lane = threadIdx.x;
+  const uint32_t* hg = a.hist + (int64_t)chip * 256;
+  uint32_t h[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) h[i] = hg[4 * lane + i];
+  const uint32_t cl = h[0] + h[1] + h[2] + h[3];
+  uint64_t sl = 0, ql = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint64_t v = 4 * lane + i;
+    sl += v * h[i];
+    ql += v * v * h[i];
+  }
+  const uint32_t c_inc = wave_scan_incl(cl, lane);
+  const uint64_t s_inc = wave_scan_incl(sl, lane);
+  const uint32_t N = __shfl(c_inc, 63);
+  const uint64_t S = __shfl(s_inc, 63);
+  const uint64_t Q = wave_sum(ql);
+
+  // Otsu over this lane's split points t = 4*lane + i (t <= 254):
+  // sigma_B^2 N^2 = D^2 / (w0 w1), D = N*S0 - w0*S
+  bool have = false;
+  u128 bnum = 0;
+  uint64_t bden = 1;
+  uint32_t bt = 0;
+  {
+    uint32_t w0 = c_inc - cl;
+    uint64_t s0 = s_inc - sl;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t t = 4 * lane + i;
+      w0 += h[i];
+      s0 += (uint64_t)t * h[i];
+      if (t < 255 && w0 > 0 && w0 < N) {
+        const int64_t D = (int64_t)((uint64_t)N * s0) - (int64_t)((uint64_t)w0 * S);
+        const uint64_t ad = (uint64_t)(D < 0 ? -D : D);
+        const u128 num = (u128)ad * ad;
+        const uint64_t den = (uint64_t)w0 * (N - w0);
+        if (!have || cmp192(mul_128_64(num, bden), mul_128_64(bnum, den)) > 0) {
+          have = true;
+          bnum = num;
+          bden = den;
+          bt = t;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t olo = __shfl_xor((uint64_t)bnum, d);
+    const uint64_t ohi = __shfl_xor((uint64_t)(bnum >> 64), d);
+    const uint64_t oden = __shfl_xor(bden, d);
+    const uint32_t ot = __shfl_xor(bt, d);
+    const int ohave = __shfl_xor((int)have, d);
+    const u128 onum = ((u128)ohi << 64) | olo;
+    bool take = false;
+    if (ohave) {
+      if (!have) {
+        take = true;
+      } else {
+        const int c = cmp192(mul_128_64(onum, bden), mul_128_64(bnum, oden));
+        take = c > 0 || (c == 0 && ot < bt);
+      }
+    }
+    if (take) {
+      have = true;
+      bnum = onum;
+      bden = oden;
+      bt = ot;
+    }
+  }
+
+  bool gate = false;
+  if (have) {
+    const u128 var = (u128)N * Q - (u128)S * S;
+    gate = cmp192(mul_128_64(bnum, a.eta_den), mul_128_64(var * bden, a.eta_num)) >= 0;
+  }
+
+  // truncation levels: (k+1)-th smallest and largest value, k = N >> clip_shift
+  const uint32_t kk = N >> a.clip_shift;
+  uint32_t lo_c = 256;
+  int32_t hi_c = -1;
+  {
+    uint32_t cum = c_inc - cl;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t v = 4 * lane + i;
+      const uint32_t before = cum;
+      cum += h[i];
+      if (cum > kk && lo_c == 256) lo_c = v;
+      if (N - before > kk) hi_c = (int32_t)v;
+    }
+  }
+  const uint32_t lo = wave_min(lo_c);
+  const uint32_t hi = (uint32_t)wave_max(hi_c);
+  const bool stretch = gate && hi > lo;
+
+  // table median -> filtered value; a1 / a2: smallest median whose filtered
+  // value falls (last matching V-interval) in class >= 1 / >= 2
+  uint32_t a1c = 256, a2c = 256;
+  uint32_t packed = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t m = 4 * lane + i;
+    uint32_t vc = m;
+    if (stretch) {
+      const uint32_t c = min(max(m, lo), hi);
+      vc = ((c - lo) * 255u + (hi - lo) / 2u) / (hi - lo);
+    }
+    packed |= vc << (8 * i);
+    int cls = -1;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      if (a.lo[k][2] <= vc && vc <= a.hi[k][2]) cls = k;
+    if (cls >= 1) a1c = min(a1c, m);
+    if (cls >= 2) a2c = min(a2c, m);
+  }
+  ((uint32_t*)(a.lut + (int64_t)chip * 256))[lane] = packed;
+  const uint32_t a1 = wave_min(a1c), a2 = wave_min(a2c);
+  if (lane == 0 && a.chips) {
+    sil_chip_info ci;
+    ci.t = have ? (int32_t)bt : -1;
+    ci.lo = (uint8_t)lo;
+    ci.hi = (uint8_t)hi;
+    ci.gate = gate;
+    ci.stretch = stretch;
+    ci.a1 = (uint16_t)a1;
+    ci.a2 = (uint16_t)a2;
+    a.chips[chip] = ci;
+  }
+}
+
+// ---- pass C: masks, filtered colour, counts --------------------------------------
+
+// 8-bit HSV hue (degrees / 2, 0..179) and saturation (0..255) of (r, g, b),
+// rounded half up; red wins a tie for the maximum, then green.
+__device__ __forceinline__ void hue_sat(uint32_t r, uint32_t g, uint32_t b, uint32_t& H,
+                                        uint32_t& S) {
+  const uint32_t V = max3u(r, g, b), mn = min3u(r, g, b), d = V - mn;
+  S = V == 0 ? 0u : div_small(510u * d + V, 2u * V, __builtin_amdgcn_rcpf((float)(2u * V)));
+  if (d == 0) {
+    H = 0;
+    return;
+  }
+  // sector position times d, shifted by 6d so it is never negative
+  int32_t num;
+  if (V == r)
+    num = (int32_t)g - (int32_t)b;
+  else if (V == g)
+    num = 2 * (int32_t)d + (int32_t)b - (int32_t)r;
+  else
+    num = 4 * (int32_t)d + (int32_t)r - (int32_t)g;
+  // hue / 2 = floor((60 num + d) / (2d)); adding 360 d to the numerator adds 180
+  const uint32_t top = (uint32_t)(60 * num + 361 * (int32_t)d);
+  const uint32_t q = div_small(top, 2u * d, __builtin_amdgcn_rcpf((float)(2u * d)));
+  H = q >= 360u ? q - 360u : (q >= 180u ? q - 180u : q);
+}
+
+__global__ __launch_bounds__(kTC) void k_ex_apply(ExArgs a, int32_t ntx, int64_t ntiles) {
+  __shared__ uint32_t scnt[kMaxTilePatches][3];
+  const int tid = threadIdx.x, lane = tid & 63;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int32_t ty = (int32_t)(tile / ntx) * kTRC, tx = (int32_t)(tile % ntx) * kTC;
+    const int32_t rows = min(kTRC, a.H - ty), cols = min(kTC, a.W - tx);
+    int32_t py0 = 0, px0 = 0, npx_t = 0;
+    if (a.counts && a.cnt_lds) {
+      py0 = ty / a.ph;
+      px0 = tx / a.pw;
+      npx_t = (tx + cols - 1) / a.pw - px0 + 1;
+      const int32_t np = ((ty + rows - 1) / a.ph - py0 + 1) * npx_t;
+      for (int i = tid; i < np * 3; i += kTC) (&scnt[0][0])[i] = 0;
+      __syncthreads();
+    }
+    const bool active = tid < cols;
+    const int32_t x = tx + tid;
+    const int32_t cxi = a.filter && active ? x / a.chip : 0;
+    const int32_t ppx = a.counts && active ? x / a.pw : 0;
+    int32_t run_key = -1;
+    uint32_t run[3] = {0, 0, 0};
+    auto flush = [&]() {
+      // the counts of this thread's current patch go to LDS; lanes of a wave
+      // that share the patch are summed first
+      const bool uni = __all(run_key == __shfl(run_key, 0));
+      if (uni) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) run[c] = wave_sum(run[c]);
+        if (lane == 0 && run_key >= 0)
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            if (run[c]) atomicAdd(&scnt[run_key][c], run[c]);
+      } else if (run_key >= 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          if (run[c]) atomicAdd(&scnt[run_key][c], run[c]);
+      }
+      run[0] = run[1] = run[2] = 0;
+    };
+    for (int r = 0; r < rows; ++r) {
+      const int32_t y = ty + r;
+      int32_t key = -1;
+      uint32_t bits = 0;
+      if (active) {
+        const uint32_t bl = to8(raw_at(a, 0, y, x), a), gr = to8(raw_at(a, 1, y, x), a),
+                       rd = to8(raw_at(a, 2, y, x), a);
+        const uint32_t V = max3u(bl, gr, rd);
+        uint32_t vc = V;
+        if (a.filter) {
+          const uint32_t m = a.vm[(int64_t)y * a.W + x];
+          const int32_t chip_id = (y / a.chip) * a.ncx + cxi;
+          vc = a.lut[(int64_t)chip_id * 256 + m];
+        }
+        uint32_t Hh, Ss;
+        hue_sat(rd, gr, bl, Hh, Ss);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          if (a.lo[c][0] <= Hh && Hh <= a.hi[c][0] && a.lo[c][1] <= Ss && Ss <= a.hi[c][1] &&
+              a.lo[c][2] <= vc && vc <= a.hi[c][2])
+            bits |= 1u << c;
+        a.masks[(int64_t)y * a.mask_pitch + x] = (uint8_t)bits;
+        if (a.rgb) {
+          const float rv = V ? __builtin_amdgcn_rcpf((float)V) : 0.f;
+          const uint32_t cband[3] = {bl, gr, rd};
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+            a.rgb[((int64_t)i * a.H + y) * a.rgb_pitch + x] =
+                V ? (uint8_t)div_small(cband[i] * vc + V / 2u, V, rv) : (uint8_t)0;
+        }
+        if (a.counts) {
+          if (a.cnt_lds) {
+            key = (y / a.ph - py0) * npx_t + (ppx - px0);
+          } else {
+            uint32_t* cp = a.counts + ((int64_t)(y / a.ph) * a.nx + ppx) * 3;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+              if (bits >> c & 1u) atomicAdd(&cp[c], 1u);
+          }
+        }
+      }
+      if (a.counts && a.cnt_lds) {
+        // wave-uniform test: every lane takes part in flush()
+        if (__any(key != run_key && run_key >= 0)) flush();
+        run_key = key;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) run[c] += bits >> c & 1u;
+      }
+    }
+    if (a.counts && a.cnt_lds) {
+      flush();
+      __syncthreads();
+      const int32_t np = ((ty + rows - 1) / a.ph - py0 + 1) * npx_t;
+      for (int i = tid; i < np * 3; i += kTC) {
+        const uint32_t v = (&scnt[0][0])[i];
+        if (v) {
+          const int32_t k = i / 3, c = i - k * 3;
+          const int32_t py = py0 + k / npx_t, px = px0 + k % npx_t;
+          atomicAdd(&a.counts[((int64_t)py * a.nx + px) * 3 + c], v);
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void k_ex_fill(uint32_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+// ---- host ---------------------------------------------------------------------------
+
+int64_t align256(int64_t v) { return (v + 255) & ~int64_t(255); }
+
+struct Layout {
+  int64_t nchips, vm, hist, lut, total;
+};
+
+Layout layout(int32_t H, int32_t W, const sil_params* p) {
+  Layout L{};
+  const int64_t C = p->chip;
+  L.nchips = ((H + C - 1) / C) * ((W + C - 1) / C);
+  if (!p->filter) return L;
+  L.vm = 0;
+  L.hist = align256((int64_t)H * W);
+  L.lut = align256(L.hist + L.nchips * 256 * 4);
+  L.total = L.lut + L.nchips * 256;
+  return L;
+}
+
+int validate_ex(int32_t nbands, const int32_t sel[3], int32_t H, int32_t W, int64_t pitch,
+                int64_t mask_pitch, const sil_params* p) {
+  if (!p || !sel) return SIL_EINVAL;
+  if (p->abi != SIL_ABI_VERSION) return SIL_EINVAL;
+  if (p->dtype != SIL_U8 && p->dtype != SIL_U16) return SIL_EINVAL;
+  if (p->dtype == SIL_U16 && p->refl_max < 1) return SIL_EINVAL;
+  if (p->filter > 1) return SIL_EINVAL;
+  if (p->chip < 1 || p->clip_shift < 1 || p->clip_shift > 31) return SIL_EINVAL;
+  if (p->eta_den < 1 || p->eta_num > p->eta_den) return SIL_EINVAL;
+  if (p->patch_h < 1 || p->patch_w < 1) return SIL_EINVAL;
+  if (H < 1 || W < 1 || pitch < W || mask_pitch < W || nbands < 1) return SIL_EINVAL;
+  for (int i = 0; i < 3; ++i)
+    if (sel[i] < 0 || sel[i] >= nbands) return SIL_EINVAL;
+  if (p->dtype == SIL_U16 && p->refl_max > 65535) return SIL_EUNSUPPORTED;
+  if (p->filter == 1) {
+    const int64_t ch = std::min<int64_t>(p->chip, H), cw = std::min<int64_t>(p->chip, W);
+    if (ch * cw > kMaxChipPixels) return SIL_EUNSUPPORTED;
+  }
+  // int32 pixel and chip arithmetic in the kernels
+  if ((int64_t)H * W > INT32_MAX || (int64_t)nbands * H * pitch > (INT64_MAX >> 2))
+    return SIL_EUNSUPPORTED;
+  return SIL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sil_label_ex_validate(int32_t nbands, const int32_t sel[3], int32_t H, int32_t W,
+                          int64_t pitch, int64_t mask_pitch, const sil_params* p) {
+  return validate_ex(nbands, sel, H, W, pitch, mask_pitch, p);
+}
+
+int sil_label_ex_workspace(int32_t H, int32_t W, const sil_params* p, uint64_t* bytes) {
+  if (!p || !bytes || H < 1 || W < 1 || p->chip < 1) return SIL_EINVAL;
+  *bytes = (uint64_t)layout(H, W, p).total;
+  return SIL_OK;
+}
+
+int sil_label_ex(const void* scene, int32_t nbands, const int32_t sel[3], int32_t H, int32_t W,
+                 int64_t pitch, const sil_params* p, uint8_t* masks, int64_t mask_pitch,
+                 uint32_t* counts, uint8_t* rgb, int64_t rgb_pitch, sil_chip_info* chips,
+                 void* workspace, uint64_t workspace_bytes, void* stream) {
+  if (!scene || !masks) return SIL_EINVAL;
+  int rc = validate_ex(nbands, sel, H, W, pitch, mask_pitch, p);
+  if (rc != SIL_OK) return rc;
+  if (rgb && rgb_pitch < W) return SIL_EINVAL;
+  const int64_t esz = p->dtype == SIL_U16 ? 2 : 1;
+  if (esz == 2 && ((uintptr_t)scene & 1)) return SIL_EINVAL;
+  const Layout L = layout(H, W, p);
+  if (p->filter && (!workspace || workspace_bytes < (uint64_t)L.total)) return SIL_EINVAL;
+  if (L.nchips > INT32_MAX - 4096) return SIL_EUNSUPPORTED;
+
+  ExArgs a{};
+  for (int i = 0; i < 3; ++i)
+    a.band[i] = (const uint8_t*)scene + (int64_t)sel[i] * H * pitch * esz;
+  a.pitch_b = pitch * esz;
+  a.H = H;
+  a.W = W;
+  a.u16 = esz == 2;
+  a.refl_max = p->refl_max;
+  a.rinv = 1.0 / (double)(p->refl_max ? p->refl_max : 1);
+  a.filter = (int32_t)p->filter;
+  a.chip = (int32_t)std::min<int64_t>(p->chip, std::max(H, W));
+  a.ncx = (int32_t)((W + (int64_t)p->chip - 1) / p->chip);
+  a.nchips = (int32_t)L.nchips;
+  a.ph = (int32_t)std::min<int64_t>(p->patch_h, H);
+  a.pw = (int32_t)std::min<int64_t>(p->patch_w, W);
+  a.nx = (int32_t)((W + (int64_t)p->patch_w - 1) / p->patch_w);
+  const int64_t ny = (H + (int64_t)p->patch_h - 1) / p->patch_h;
+  // patches a 8 x 256 tile can touch
+  const int64_t tp = (std::min<int64_t>(kTRC, H) - 1) / a.ph + 2;
+  const int64_t tq = (std::min<int64_t>(kTC, W) - 1) / a.pw + 2;
+  a.cnt_lds = tp * tq <= kMaxTilePatches;
+  memcpy(a.lo, p->lo, sizeof(a.lo));
+  memcpy(a.hi, p->hi, sizeof(a.hi));
+  a.clip_shift = p->clip_shift;
+  a.eta_num = p->eta_num;
+  a.eta_den = p->eta_den;
+  if (p->filter) {
+    a.vm = (uint8_t*)workspace + L.vm;
+    a.hist = (uint32_t*)((uint8_t*)workspace + L.hist);
+    a.lut = (uint8_t*)workspace + L.lut;
+  }
+  a.masks = masks;
+  a.mask_pitch = mask_pitch;
+  a.counts = counts;
+  a.rgb = rgb;
+  a.rgb_pitch = rgb_pitch;
+  a.chips = chips;
+
+  hipStream_t st = (hipStream_t)stream;
+  (void)hipGetLastError();
+  if (p->filter) {
+    const int64_t nh = L.nchips * 256;
+    hipLaunchKernelGGL(k_ex_fill, dim3((unsigned)std::min<int64_t>((nh + 255) / 256, 4096)),
+                       dim3(256), 0, st, a.hist, nh);
+    const int64_t tiles_per_chip = ((std::min<int64_t>(a.chip, H) + kTR - 1) / kTR) *
+                                   ((std::min<int64_t>(a.chip, W) + kTC - 1) / kTC);
+    const int32_t parts = (int32_t)std::max<int64_t>(
+        1, std::min<int64_t>((2048 + L.nchips - 1) / L.nchips, tiles_per_chip));
+    hipLaunchKernelGGL(k_ex_median, dim3((unsigned)(L.nchips * parts)), dim3(kTC), 0, st, a,
+                       parts);
+    hipLaunchKernelGGL(k_ex_stats, dim3((unsigned)L.nchips), dim3(64), 0, st, a);
+  }
+  if (counts) {
+    const int64_t nc = ny * a.nx * 3;
+    hipLaunchKernelGGL(k_ex_fill, dim3((unsigned)std::min<int64_t>((nc + 255) / 256, 4096)),
+                       dim3(256), 0, st, counts, nc);
+  }
+  const int32_t ntx = (W + kTC - 1) / kTC;
+  const int64_t ntiles = (int64_t)((H + kTRC - 1) / kTRC) * ntx;
+  hipLaunchKernelGGL(k_ex_apply, dim3((unsigned)std::min<int64_t>(ntiles, 8192)), dim3(kTC), 0,
+                     st, a, ntx, ntiles);
+  return hipGetLastError() == hipSuccess ? SIL_OK : SIL_EDEVICE;
+}
+
+}  // extern "C"

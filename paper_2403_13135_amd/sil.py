@@ -96,6 +96,17 @@ def lib() -> ctypes.CDLL:
         L.sil_chip_count.restype = ctypes.c_int
         L.sil_label_batch.argtypes = [P(_Job), ctypes.c_int32, P(_Params), ctypes.c_void_p]
         L.sil_label_batch.restype = ctypes.c_int
+        L.sil_label_ex_validate.argtypes = L.sil_validate.argtypes
+        L.sil_label_ex_validate.restype = ctypes.c_int
+        L.sil_label_ex_workspace.argtypes = [ctypes.c_int32, ctypes.c_int32, P(_Params),
+                                             P(ctypes.c_uint64)]
+        L.sil_label_ex_workspace.restype = ctypes.c_int
+        L.sil_label_ex.argtypes = [ctypes.c_void_p, ctypes.c_int32, P(ctypes.c_int32),
+                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, P(_Params),
+                                   ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
+        L.sil_label_ex.restype = ctypes.c_int
         L.sil_strerror.argtypes = [ctypes.c_int]
         L.sil_strerror.restype = ctypes.c_char_p
         if L.sil_abi_version() != ABI_VERSION:
@@ -276,3 +287,97 @@ def label_batch(jobs: Sequence[Job], params: Params,
     s = stream if stream is not None else torch.cuda.current_stream(jobs[0].scene.device)
     p = params.to_c()
     _check(lib().sil_label_batch(arr, len(jobs), ctypes.byref(p), ctypes.c_void_p(s.cuda_stream)))
+
+
+# ---- the general labeller (variants) -----------------------------------------
+
+def validate_ex(nbands: int, sel, H: int, W: int, pitch: int, mask_pitch: int,
+                params: Params) -> int:
+    s = (ctypes.c_int32 * 3)(*[int(v) for v in sel])
+    p = params.to_c()
+    return lib().sil_label_ex_validate(nbands, s, H, W, pitch, mask_pitch, ctypes.byref(p))
+
+
+def workspace_bytes(H: int, W: int, params: Params) -> int:
+    n = ctypes.c_uint64()
+    p = params.to_c()
+    _check(lib().sil_label_ex_workspace(H, W, ctypes.byref(p), ctypes.byref(n)))
+    return n.value
+
+
+def label_ex(scene: torch.Tensor, params: Optional[Params] = None, sel=(0, 1, 2),
+             W: Optional[int] = None, counts: bool = True, rgb: bool = False,
+             chips: bool = False, workspace: Optional[torch.Tensor] = None,
+             out: Optional[dict] = None, stream: Optional[torch.cuda.Stream] = None) -> dict:
+    """The general labeller ``sil_label_ex`` on ``scene`` ([nbands, H, pitch]
+    on the GPU): full-HSV masks, any filter unit, optional filtered colour.
+
+    Returns a dict with ``masks`` [H, W] uint8 (bit c = mask c), ``counts``
+    [ny, nx, 3] int32 (if asked), ``rgb`` [3, H, W] uint8 (if asked) and
+    ``chips`` (raw [ncy, ncx, 12] sil_chip_info bytes, if asked).  ``out`` may
+    hold preallocated tensors under the same keys; ``workspace`` a uint8 GPU
+    tensor of at least ``workspace_bytes`` bytes (allocated here if omitted).
+    Enqueued on ``stream`` (default: the current stream); not synchronised.
+    """
+    if params is None:
+        params = Params(dtype=U16 if scene.dtype in _SCENE_DTYPES[U16] else U8)
+    if scene.dim() != 3 or not scene.is_cuda or not scene.is_contiguous():
+        raise ValueError("scene must be a contiguous [nbands, H, pitch] GPU tensor")
+    if scene.dtype not in _SCENE_DTYPES[params.dtype]:
+        raise ValueError(f"scene dtype {scene.dtype} does not match params.dtype")
+    nb, H, pitch = scene.shape
+    W = pitch if W is None else int(W)
+    dev = scene.device
+    out = dict(out or {})
+    masks = out.get("masks")
+    if masks is None:
+        masks = out["masks"] = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    if masks.dtype != torch.uint8 or masks.dim() != 2 or masks.shape[0] != H \
+            or masks.shape[1] < W or masks.stride(1) != 1:
+        raise ValueError("masks must be uint8 [H, >=W] with unit column stride")
+    cnt = None
+    if counts:
+        ny, nx = hist_dims(H, W, params)
+        cnt = out.get("counts")
+        if cnt is None:
+            cnt = out["counts"] = torch.empty((ny, nx, 3), dtype=torch.int32, device=dev)
+        if cnt.shape != (ny, nx, 3) or cnt.dtype not in (torch.int32, torch.uint32) \
+                or not cnt.is_contiguous():
+            raise ValueError(f"counts must be contiguous int32 [{ny}, {nx}, 3]")
+    col = None
+    if rgb:
+        col = out.get("rgb")
+        if col is None:
+            col = out["rgb"] = torch.empty((3, H, W), dtype=torch.uint8, device=dev)
+        if col.dtype != torch.uint8 or col.dim() != 3 or col.shape[0] != 3 \
+                or col.shape[1] != H or col.shape[2] < W or col.stride(2) != 1 \
+                or col.stride(0) != H * col.stride(1):
+            raise ValueError("rgb must be planar uint8 [3, H, >=W]")
+    chip_t = None
+    if chips:
+        C = params.chip
+        chip_t = out.get("chips")
+        if chip_t is None:
+            chip_t = out["chips"] = torch.zeros(
+                ((H + C - 1) // C, (W + C - 1) // C, CHIP_INFO_BYTES), dtype=torch.uint8,
+                device=dev)
+    need = workspace_bytes(H, W, params)
+    if need and workspace is None:
+        workspace = torch.empty((need,), dtype=torch.uint8, device=dev)
+    if need and (workspace.dtype != torch.uint8 or workspace.numel() < need
+                 or not workspace.is_cuda):
+        raise ValueError(f"workspace must be a uint8 GPU tensor of >= {need} bytes")
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    sel_c = (ctypes.c_int32 * 3)(*[int(v) for v in sel])
+    p = params.to_c()
+    rc = lib().sil_label_ex(
+        ctypes.c_void_p(scene.data_ptr()), nb, sel_c, H, W, pitch, ctypes.byref(p),
+        ctypes.c_void_p(masks.data_ptr()), masks.stride(0),
+        ctypes.c_void_p(cnt.data_ptr()) if cnt is not None else None,
+        ctypes.c_void_p(col.data_ptr()) if col is not None else None,
+        col.stride(1) if col is not None else 0,
+        ctypes.c_void_p(chip_t.data_ptr()) if chip_t is not None else None,
+        ctypes.c_void_p(workspace.data_ptr()) if need else None, need,
+        ctypes.c_void_p(s.cuda_stream))
+    _check(rc)
+    return out
