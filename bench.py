@@ -83,6 +83,43 @@ def calib_copy(nbytes=1 << 30, reps=3):
                       "ms": ms, "gbs": 2 * nbytes / ms / 1e6}), flush=True)
 
 
+VARIANT_LIMITS = dict(lo=[[0, 40, 0], [20, 0, 60], [100, 10, 150]],
+                      hi=[[90, 255, 120], [179, 200, 220], [170, 255, 255]])
+
+
+def run_variants(sil, scene, H, W, stream, reps=20):
+    """The general labeller (sil_label_ex) on the resident full tile: full-HSV
+    limits with 256 x 256 chips, and the whole tile as one filter unit, with
+    and without the filtered colour image.  Algorithmic bytes per pixel:
+    pass A reads 6 and writes the 1-byte median, pass C reads 6 + 1 and
+    writes the 1-byte mask (+ 3 colour bytes)."""
+    import torch
+    out = {}
+    cases = [("full_hsv_chip256_rgb", dict(chip=256, **VARIANT_LIMITS), True),
+             ("scene_level_rgb", dict(chip=1 << 20), True),
+             ("scene_level_masks", dict(chip=1 << 20), False)]
+    for name, kw, rgb in cases:
+        p = sil.Params(dtype=sil.U16, **kw)
+        ws = torch.empty((sil.workspace_bytes(H, W, p),), dtype=torch.uint8, device=scene.device)
+        buf = sil.label_ex(scene, p, W=W, rgb=rgb, workspace=ws, stream=stream)
+        for _ in range(3):
+            sil.label_ex(scene, p, W=W, rgb=rgb, workspace=ws, out=buf, stream=stream)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            sil.label_ex(scene, p, W=W, rgb=rgb, workspace=ws, out=buf, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        bpp = 15 + (3 if rgb else 0)
+        out[name] = {"ms": ms, "gpx_s": H * W / (ms / 1e3) / 1e9,
+                     "algorithmic_bytes_per_px": bpp,
+                     "achieved_gbs": H * W * bpp / (ms / 1e3) / 1e9}
+        del ws, buf
+    return out
+
+
 def run_serving(n_requests, chips_per_launch, seeds_per_size=2):
     """Continuous-batching server on the mixed-size request trace: capacity
     (all requests arriving at once), p50/p99 latency under Poisson arrivals at
@@ -204,6 +241,8 @@ def main():
     ap.add_argument("--pitch", type=int, default=PITCH)
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a 1 GiB device copy (for counter scaling)")
+    ap.add_argument("--skip-variants", action="store_true",
+                    help="omit the general-labeller section")
     ap.add_argument("--skip-serving", action="store_true", help="omit the serving section")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--chips-per-launch", type=int, default=1024)
@@ -325,6 +364,10 @@ def main():
                "sample": f"the full {H}x{W} uint16 tile, one single-threaded run "
                          f"({dt:.1f} s); GPU output bit-identical: {ok}"}
 
+    variants = None
+    if not args.skip_variants:
+        variants = run_variants(sil, scene, H, W, stream)
+
     serving = None
     if not args.skip_serving:
         del scene, labels, hist, labels0, hist0
@@ -366,6 +409,7 @@ def main():
             "thresholds_only_gpx_s": npx / (f0_ms / 1e3) / 1e9,
             "wall_s_timed_region": wall,
         },
+        "variants": variants,
         "serving": serving,
         "learned": learned,
     }

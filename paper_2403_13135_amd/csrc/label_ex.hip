@@ -52,8 +52,8 @@ struct ExArgs {
   int64_t pitch_b;         // row pitch in bytes
   int32_t H, W;
   int32_t u16;
-  uint32_t refl_max;
-  double rinv;             // 1 / refl_max
+  uint32_t refl_max, half, sat_n;  // sat_n = 255 * refl_max: first saturating numerator
+  float rd;                // 1 / refl_max
   int32_t filter;
   int32_t chip, ncx, nchips;
   int32_t ph, pw, nx;
@@ -71,8 +71,9 @@ struct ExArgs {
   sil_chip_info* chips;
 };
 
-// floor(n / d) for n < 2^18, 1 <= d <= 1024 (rd = 1.0f / d): the float
-// estimate is within one of the quotient, and one integer step corrects it.
+// floor(n / d) for n < 2^24 and a quotient below 2^20 (rd ~ 1.0f / d to within
+// an ulp): the float estimate is within one of the quotient, and one integer
+// step corrects it.
 __device__ __forceinline__ uint32_t div_small(uint32_t n, uint32_t d, float rd) {
   uint32_t q = (uint32_t)((float)n * rd);
   const int32_t r = (int32_t)n - (int32_t)(q * d);
@@ -80,14 +81,11 @@ __device__ __forceinline__ uint32_t div_small(uint32_t n, uint32_t d, float rd) 
 }
 
 // 16-bit reflectance to 8 bit: round-half-up of x * 255 / refl_max,
-// saturating (double estimate within one of the quotient, then corrected).
+// saturating.  n < 2^24; below the saturation point the quotient is < 255.
 __device__ __forceinline__ uint32_t to8(uint32_t x, const ExArgs& a) {
   if (!a.u16) return x;
-  const uint32_t n = x * 255u + a.refl_max / 2u;
-  uint32_t q = (uint32_t)((double)n * a.rinv);
-  const int64_t r = (int64_t)n - (int64_t)q * a.refl_max;
-  q = r < 0 ? q - 1 : (r >= (int64_t)a.refl_max ? q + 1 : q);
-  return q > 255u ? 255u : q;
+  const uint32_t n = x * 255u + a.half;
+  return n >= a.sat_n ? 255u : div_small(n, a.refl_max, a.rd);
 }
 
 __device__ __forceinline__ uint32_t raw_at(const ExArgs& a, int i, int32_t y, int32_t x) {
@@ -128,11 +126,19 @@ __global__ __launch_bounds__(kTC) void k_ex_median(ExArgs a, int32_t parts) {
   for (int32_t t = part; t < nty * ntx; t += parts) {
     const int32_t ty = y0 + (t / ntx) * kTR, tx = x0 + (t % ntx) * kTC;
     const int32_t rows = min(kTR, y0 + ch - ty), cols = min(kTC, x0 + cw - tx);
-    for (int r = 0; r < rows + 2; ++r) {
-      const int32_t y = min(max(ty - 1 + r, 0), a.H - 1);
-      for (int c = tid; c < cols + 2; c += kTC) {
-        const int32_t x = min(max(tx - 1 + c, 0), a.W - 1);
-        sv[r][c] = (uint8_t)value_at(a, y, x);
+    // unrolled so that every row's loads are in flight before the LDS stores
+    {
+      const int32_t x = min(max(tx - 1 + tid, 0), a.W - 1);
+#pragma unroll
+      for (int r = 0; r < kTR + 2; ++r)
+        if (r < rows + 2 && tid < cols + 2)
+          sv[r][tid] = (uint8_t)value_at(a, min(max(ty - 1 + r, 0), a.H - 1), x);
+      if (tid < 2 && kTC + tid < cols + 2) {
+        const int32_t x2 = min(tx - 1 + kTC + tid, a.W - 1);
+#pragma unroll
+        for (int r = 0; r < kTR + 2; ++r)
+          if (r < rows + 2)
+            sv[r][kTC + tid] = (uint8_t)value_at(a, min(max(ty - 1 + r, 0), a.H - 1), x2);
       }
     }
     __syncthreads();
@@ -370,14 +376,9 @@ __device__ __forceinline__ void hue_sat(uint32_t r, uint32_t g, uint32_t b, uint
     H = 0;
     return;
   }
-  // sector position times d, shifted by 6d so it is never negative
-  int32_t num;
-  if (V == r)
-    num = (int32_t)g - (int32_t)b;
-  else if (V == g)
-    num = 2 * (int32_t)d + (int32_t)b - (int32_t)r;
-  else
-    num = 4 * (int32_t)d + (int32_t)r - (int32_t)g;
+  // sector position times d (selects, no divergent branches)
+  const int32_t ir = (int32_t)r, ig = (int32_t)g, ib = (int32_t)b, id = (int32_t)d;
+  const int32_t num = V == r ? ig - ib : (V == g ? 2 * id + ib - ir : 4 * id + ir - ig);
   // hue / 2 = floor((60 num + d) / (2d)); adding 360 d to the numerator adds 180
   const uint32_t top = (uint32_t)(60 * num + 361 * (int32_t)d);
   const uint32_t q = div_small(top, 2u * d, __builtin_amdgcn_rcpf((float)(2u * d)));
@@ -386,7 +387,22 @@ __device__ __forceinline__ void hue_sat(uint32_t r, uint32_t g, uint32_t b, uint
 
 __global__ __launch_bounds__(kTC) void k_ex_apply(ExArgs a, int32_t ntx, int64_t ntiles) {
   __shared__ uint32_t scnt[kMaxTilePatches][3];
+  // which masks admit each hue, saturation and filtered value (bit c = mask c)
+  __shared__ uint8_t tH[180], tS[256], tV[256];
   const int tid = threadIdx.x, lane = tid & 63;
+  {
+    uint32_t bh = 0, bs = 0, bv = 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      bh |= (uint32_t)(a.lo[c][0] <= tid && tid <= a.hi[c][0]) << c;
+      bs |= (uint32_t)(a.lo[c][1] <= tid && tid <= a.hi[c][1]) << c;
+      bv |= (uint32_t)(a.lo[c][2] <= tid && tid <= a.hi[c][2]) << c;
+    }
+    if (tid < 180) tH[tid] = (uint8_t)bh;
+    tS[tid] = (uint8_t)bs;
+    tV[tid] = (uint8_t)bv;
+  }
+  __syncthreads();
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int32_t ty = (int32_t)(tile / ntx) * kTRC, tx = (int32_t)(tile % ntx) * kTC;
     const int32_t rows = min(kTRC, a.H - ty), cols = min(kTC, a.W - tx);
@@ -439,11 +455,7 @@ __global__ __launch_bounds__(kTC) void k_ex_apply(ExArgs a, int32_t ntx, int64_t
         }
         uint32_t Hh, Ss;
         hue_sat(rd, gr, bl, Hh, Ss);
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-          if (a.lo[c][0] <= Hh && Hh <= a.hi[c][0] && a.lo[c][1] <= Ss && Ss <= a.hi[c][1] &&
-              a.lo[c][2] <= vc && vc <= a.hi[c][2])
-            bits |= 1u << c;
+        bits = (uint32_t)tH[Hh] & tS[Ss] & tV[vc];
         a.masks[(int64_t)y * a.mask_pitch + x] = (uint8_t)bits;
         if (a.rgb) {
           const float rv = V ? __builtin_amdgcn_rcpf((float)V) : 0.f;
@@ -576,7 +588,9 @@ int sil_label_ex(const void* scene, int32_t nbands, const int32_t sel[3], int32_
   a.W = W;
   a.u16 = esz == 2;
   a.refl_max = p->refl_max;
-  a.rinv = 1.0 / (double)(p->refl_max ? p->refl_max : 1);
+  a.half = p->refl_max / 2u;
+  a.sat_n = 255u * p->refl_max;
+  a.rd = 1.0f / (float)(p->refl_max ? p->refl_max : 1);
   a.filter = (int32_t)p->filter;
   a.chip = (int32_t)std::min<int64_t>(p->chip, std::max(H, W));
   a.ncx = (int32_t)((W + (int64_t)p->chip - 1) / p->chip);

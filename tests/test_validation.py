@@ -127,3 +127,59 @@ def test_hist_dims_and_defaults():
     op = R.make_params()
     assert bytes(cp) == bytes(op)  # same defaults, same layout
     assert sil.strerror(-2) and sil.strerror(0)
+
+
+# The general labeller's contract: any H/S/V limits and any chip side, up to
+# chips of 2^27 pixels; every other check as the fused labeller's.
+EX_CASES = [
+    ("defaults", {}, {}, 0),
+    ("overlapping V ranges", dict(lo=[[0, 0, 0], [0, 0, 30], [0, 0, 205]], hi=PAPER["hi"]), {}, 0),
+    ("gap in V ranges", dict(lo=[[0, 0, 0], [0, 0, 32], [0, 0, 205]], hi=PAPER["hi"]), {}, 0),
+    ("hue and saturation limits", dict(lo=[[0, 40, 0], [20, 0, 60], [100, 10, 150]],
+                                       hi=[[90, 255, 120], [179, 200, 220], [170, 255, 255]]),
+     {}, 0),
+    ("lo above hi", dict(lo=[[200, 0, 0], [0, 0, 31], [0, 0, 205]], hi=PAPER["hi"]), {}, 0),
+    ("chip 257 with filter", dict(chip=257), {}, 0),
+    ("scene-level chip", dict(chip=1 << 30), dict(H=11585, W=11585, pitch=11585,
+                                                  label_pitch=11585), 0),
+    ("chip beyond 2^27 px", dict(chip=1 << 30), dict(H=11586, W=11586, pitch=11586,
+                                                     label_pitch=11586), -2),
+    ("tall chip beyond 2^27 px", dict(chip=20000), dict(H=20000, W=7000, pitch=7000,
+                                                        label_pitch=7000), -2),
+    ("filter off, any chip", dict(filter=0, chip=1 << 30), dict(H=11586, W=11586, pitch=11586,
+                                                                label_pitch=11586), 0),
+    ("refl_max above 16 bits", dict(dtype=2, refl_max=70000), {}, -2),
+    ("bad dtype", dict(dtype=3), {}, -1),
+    ("chip 0", dict(chip=0), {}, -1),
+    ("clip_shift 32", dict(clip_shift=32), {}, -1),
+    ("eta num > den", dict(eta_num=5, eta_den=4), {}, -1),
+    ("patch_w 0", dict(patch_w=0), {}, -1),
+    ("mask pitch < W", {}, dict(label_pitch=9), -1),
+    ("pitch < W", {}, dict(pitch=9), -1),
+    ("sel out of range", {}, dict(sel=(0, 1, 3)), -1),
+]
+
+
+@pytest.mark.parametrize("name,fields,call,code", EX_CASES, ids=[c[0] for c in EX_CASES])
+def test_oracle_validation_ex(name, fields, call, code):
+    assert _call(R.validate_ex, R.make_params(**fields), call) == code
+
+
+@needs_lib
+@pytest.mark.parametrize("name,fields,call,code", EX_CASES, ids=[c[0] for c in EX_CASES])
+def test_gpu_lib_validation_ex(name, fields, call, code):
+    from paper_2403_13135_amd import sil
+    p = sil.Params()
+    for k, v in fields.items():
+        setattr(p, k, v)
+    assert _call(sil.validate_ex, p, call) == code
+
+
+@needs_lib
+def test_workspace_sizes():
+    from paper_2403_13135_amd import sil
+    assert sil.workspace_bytes(10980, 10980, sil.Params(filter=0)) == 0
+    n = sil.workspace_bytes(10980, 10980, sil.Params(chip=1 << 20))
+    assert n >= 10980 * 10980 + 256 * 4 + 256
+    m = sil.workspace_bytes(10980, 10980, sil.Params())
+    assert m >= 10980 * 10980 + 43 * 43 * 256 * 5
