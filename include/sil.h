@@ -214,12 +214,14 @@ int sil_label_batch(const sil_job* jobs, int32_t njobs, const sil_params* p, voi
  *                 [ceil(H/chip)][ceil(W/chip)] (a1/a2 refer to the last
  *                 V-interval holding the filtered value).
  *   workspace     device, caller-owned scratch of at least
- *                 sil_label_ex_workspace() bytes (0 when filter = 0, where it
- *                 may be NULL); its contents are not kept between calls.
+ *                 sil_label_ex_workspace() bytes, 16-byte aligned (0 bytes
+ *                 when filter = 0, where it may be NULL); its contents are not
+ *                 kept between calls, and calls that share one workspace must
+ *                 not overlap in time.
  *   stream        hipStream_t or NULL.
  *
- * Errors: SIL_EINVAL for NULL scene/masks/sel/p, a too small or NULL
- * workspace with filter = 1, rgb_pitch < W with rgb, a misaligned 16-bit
+ * Errors: SIL_EINVAL for NULL scene/masks/sel/p, a too small, NULL or
+ * misaligned workspace with filter = 1, rgb_pitch < W with rgb, a misaligned 16-bit
  * scene, and sil_label's argument errors except those on H/S/V limits (any
  * limits are accepted) and chip > 256; SIL_EUNSUPPORTED for a chip of more
  * than 2^27 pixels (min(chip,H) * min(chip,W)), refl_max > 65535 or

@@ -12,21 +12,22 @@
 // Three passes over HBM instead of the fused one, because a chip of
 // arbitrary size no longer fits one workgroup:
 //   A. k_ex_median (filter = 1): blocks own (chip, part) pairs and walk 16 x
-//      256 tiles of their chip; V = max(B,G,R) of the tile plus a one-pixel
-//      halo (clamped at the scene border) is staged in LDS, each thread takes
-//      one column and slides the 3x3 median down it (column sorts + median of
-//      three triples), writes the 8-bit median plane to the workspace and
-//      counts it in an 8-copy LDS histogram; one global atomic per nonzero
-//      bin and block.
+//      1024 tiles of their chip; V = max(B,G,R) of the tile plus a one-pixel
+//      halo (clamped at the scene border) is staged in LDS with 8-byte band
+//      loads, each thread slides the 3x3 median down four columns (column
+//      sorts + median of three triples), writes the 8-bit median plane to the
+//      workspace (one word per four pixels) and counts it in an 8-copy LDS
+//      histogram; one global atomic per nonzero bin and block.
 //   B. k_ex_stats: one wave per chip: exact Otsu with 192-bit cross-
 //      multiplied comparisons (chips up to 2^27 pixels), the eta gate, rank-k
 //      truncation levels and the stretch, written as a 256-entry table
 //      median -> filtered value.
-//   C. k_ex_apply: 8 x 256 tiles; per pixel the three 8-bit bands, V, the
-//      filtered Vc from the table, H and S, the masks, the filtered colour and
-//      per-patch mask counts (per-thread runs, wave-reduced when the wave
-//      shares a patch, LDS counters per tile, one global atomic per nonzero
-//      counter and tile).
+//   C. k_ex_apply: 8 x 1024 tiles, four pixels per thread, every row's loads
+//      in flight first; per pixel the three 8-bit bands, V, the filtered Vc
+//      from the chip tables (staged in LDS), H and S, the masks, the filtered
+//      colour and per-patch mask counts (per-thread runs, wave-reduced when
+//      the wave shares a patch, LDS counters per tile, one global atomic per
+//      nonzero counter and tile).
 // Divisions by small run-time divisors use a float estimate corrected by one
 // integer step, which is exact for the operand ranges involved.
 
@@ -41,10 +42,12 @@
 
 namespace {
 
+constexpr int kThreads = 256;     // threads per block of passes A and C
 constexpr int kTR = 16;           // pass A tile rows
-constexpr int kTC = 256;          // tile columns (= threads per block)
+constexpr int kTW = 4 * kThreads; // tile columns: 4 per thread
 constexpr int kTRC = 8;           // pass C tile rows
 constexpr int kMaxTilePatches = 128;
+constexpr int kMaxTileChips = 16; // per-chip tables a pass C tile stages in LDS
 constexpr int64_t kMaxChipPixels = int64_t(1) << 27;
 
 struct ExArgs {
@@ -60,7 +63,11 @@ struct ExArgs {
   int32_t cnt_lds;         // per-tile LDS counters (else per-pixel global atomics)
   uint8_t lo[3][3], hi[3][3];
   uint32_t clip_shift, eta_num, eta_den;
-  uint8_t* vm;             // workspace: [H][W] median plane
+  int32_t in_vec;          // band rows 8-byte (u16) / 4-byte (u8) aligned
+  int32_t out_vec;         // mask and colour rows 4-byte aligned
+  int32_t lut_lds;         // pass C tiles stage their chips' tables in LDS
+  int64_t vm_pitch;        // row pitch of the median plane (multiple of 16)
+  uint8_t* vm;             // workspace: [H][vm_pitch] median plane
   uint32_t* hist;          // workspace: [nchips][256]
   uint8_t* lut;            // workspace: [nchips][256] median -> filtered value
   uint8_t* masks;
@@ -111,61 +118,113 @@ __device__ __forceinline__ uint32_t med3u(uint32_t a, uint32_t b, uint32_t c) {
 
 // ---- pass A: median plane and per-chip histograms ------------------------------
 
-__global__ __launch_bounds__(kTC) void k_ex_median(ExArgs a, int32_t parts) {
-  __shared__ uint8_t sv[kTR + 2][kTC + 4];
+// V of four consecutive pixels (x .. x+3, all inside the row) with one 8-byte
+// (u16) or 4-byte (u8) load per band.
+__device__ __forceinline__ void value4(const ExArgs& a, int32_t y, int32_t x, uint32_t v[4]) {
+  uint32_t m[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const uint8_t* row = a.band[i] + (int64_t)y * a.pitch_b;
+    if (a.u16) {
+      const uint2 w = *(const uint2*)(row + 2 * (int64_t)x);
+      m[0] = max(m[0], w.x & 0xffffu);
+      m[1] = max(m[1], w.x >> 16);
+      m[2] = max(m[2], w.y & 0xffffu);
+      m[3] = max(m[3], w.y >> 16);
+    } else {
+      const uint32_t w = *(const uint32_t*)(row + x);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) m[j] = max(m[j], (w >> (8 * j)) & 255u);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) v[j] = to8(m[j], a);
+}
+
+// Blocks own (chip, part) pairs and walk 16 x 1024 tiles of their chip.  The
+// tile's V plus a one-pixel halo is staged in LDS (pixel column c at byte
+// c + 4 of its row, so each thread's four columns are one aligned word);
+// thread t then slides the 3x3 median down columns 4t .. 4t+3.
+__global__ __launch_bounds__(kThreads) void k_ex_median(ExArgs a, int32_t parts) {
+  __shared__ uint32_t svw[kTR + 2][kTW / 4 + 2];
   __shared__ uint32_t sh[8][256];
+  uint8_t* const svb = (uint8_t*)&svw[0][0];
+  constexpr int kRowB = 4 * (kTW / 4 + 2);  // bytes per staged row
   const int tid = threadIdx.x;
-  for (int i = tid; i < 8 * 256; i += kTC) (&sh[0][0])[i] = 0;
+  for (int i = tid; i < 8 * 256; i += kThreads) (&sh[0][0])[i] = 0;
   const int32_t chip_id = blockIdx.x / parts, part = blockIdx.x % parts;
   const int32_t cy = chip_id / a.ncx, cx = chip_id - cy * a.ncx;
   const int32_t y0 = (int32_t)((int64_t)cy * a.chip), x0 = (int32_t)((int64_t)cx * a.chip);
   const int32_t ch = min(a.chip, a.H - y0), cw = min(a.chip, a.W - x0);
-  const int32_t nty = (ch + kTR - 1) / kTR, ntx = (cw + kTC - 1) / kTC;
+  const int32_t nty = (ch + kTR - 1) / kTR, ntx = (cw + kTW - 1) / kTW;
   uint32_t* hc = sh[tid & 7];
+  const int32_t c0 = 4 * tid;  // this thread's first tile column
   __syncthreads();
   for (int32_t t = part; t < nty * ntx; t += parts) {
-    const int32_t ty = y0 + (t / ntx) * kTR, tx = x0 + (t % ntx) * kTC;
-    const int32_t rows = min(kTR, y0 + ch - ty), cols = min(kTC, x0 + cw - tx);
-    // unrolled so that every row's loads are in flight before the LDS stores
-    {
-      const int32_t x = min(max(tx - 1 + tid, 0), a.W - 1);
+    const int32_t ty = y0 + (t / ntx) * kTR, tx = x0 + (t % ntx) * kTW;
+    const int32_t rows = min(kTR, y0 + ch - ty), cols = min(kTW, x0 + cw - tx);
+    // stage tile columns -1 .. cols (clamped to the scene), rows -1 .. rows
+    const bool vec = a.in_vec && (tx & 3) == 0 && tx + c0 + 3 < a.W && c0 < cols;
 #pragma unroll
-      for (int r = 0; r < kTR + 2; ++r)
-        if (r < rows + 2 && tid < cols + 2)
-          sv[r][tid] = (uint8_t)value_at(a, min(max(ty - 1 + r, 0), a.H - 1), x);
-      if (tid < 2 && kTC + tid < cols + 2) {
-        const int32_t x2 = min(tx - 1 + kTC + tid, a.W - 1);
-#pragma unroll
-        for (int r = 0; r < kTR + 2; ++r)
-          if (r < rows + 2)
-            sv[r][kTC + tid] = (uint8_t)value_at(a, min(max(ty - 1 + r, 0), a.H - 1), x2);
+    for (int r = 0; r < kTR + 2; ++r) {
+      if (r < rows + 2) {
+        const int32_t y = min(max(ty - 1 + r, 0), a.H - 1);
+        if (vec) {
+          uint32_t v[4];
+          value4(a, y, tx + c0, v);
+          svw[r][tid + 1] = v[0] | (v[1] << 8) | (v[2] << 16) | (v[3] << 24);
+        } else if (c0 <= cols) {
+          for (int j = 0; j < 4 && c0 + j <= cols; ++j)
+            svb[r * kRowB + c0 + j + 4] = (uint8_t)value_at(a, y, min(tx + c0 + j, a.W - 1));
+        }
+        if (tid == 0) svb[r * kRowB + 3] = (uint8_t)value_at(a, y, max(tx - 1, 0));
+        if (tid == 1 && cols == kTW)
+          svb[r * kRowB + kTW + 4] = (uint8_t)value_at(a, y, min(tx + kTW, a.W - 1));
       }
     }
     __syncthreads();
-    if (tid < cols) {
-      // sorted column triples of the three columns around pixel column tid
-      uint32_t p0[3], p1[3];  // rows r and r + 1 of columns tid .. tid + 2
+    if (c0 < cols) {
+      // input columns c0-1 .. c0+4 are bytes 3 .. 8 of words tid, tid+1, tid+2
+      auto col6 = [&](int r, uint32_t c[6]) {
+        const uint32_t wl = svw[r][tid], wm = svw[r][tid + 1], wr = svw[r][tid + 2];
+        c[0] = wl >> 24;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        p0[k] = sv[0][tid + k];
-        p1[k] = sv[1][tid + k];
-      }
-      uint8_t* out = a.vm + (int64_t)ty * a.W + tx + tid;
+        for (int j = 0; j < 4; ++j) c[1 + j] = (wm >> (8 * j)) & 255u;
+        c[5] = wr & 255u;
+      };
+      uint32_t p0[6], p1[6];
+      col6(0, p0);
+      col6(1, p1);
+      const int nv = min(4, cols - c0);
+      uint8_t* out = a.vm + (int64_t)ty * a.vm_pitch + tx + c0;
       for (int r = 0; r < rows; ++r) {
-        uint32_t p2[3], lo3[3], md3[3], hi3[3];
+        uint32_t p2[6], lo3[6], md3[6], hi3[6];
+        col6(r + 2, p2);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          p2[k] = sv[r + 2][tid + k];
+        for (int k = 0; k < 6; ++k) {
           lo3[k] = min3u(p0[k], p1[k], p2[k]);
           md3[k] = med3u(p0[k], p1[k], p2[k]);
           hi3[k] = max3u(p0[k], p1[k], p2[k]);
         }
-        const uint32_t m = med3u(max3u(lo3[0], lo3[1], lo3[2]), med3u(md3[0], md3[1], md3[2]),
-                                 min3u(hi3[0], hi3[1], hi3[2]));
-        out[(int64_t)r * a.W] = (uint8_t)m;
-        atomicAdd(&hc[m], 1u);
+        uint32_t m[4];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
+        for (int j = 0; j < 4; ++j)
+          m[j] = med3u(max3u(lo3[j], lo3[j + 1], lo3[j + 2]),
+                       med3u(md3[j], md3[j + 1], md3[j + 2]),
+                       min3u(hi3[j], hi3[j + 1], hi3[j + 2]));
+        if (nv == 4 && (tx & 3) == 0) {
+          *(uint32_t*)(out + (int64_t)r * a.vm_pitch) =
+              m[0] | (m[1] << 8) | (m[2] << 16) | (m[3] << 24);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) atomicAdd(&hc[m[j]], 1u);
+        } else {
+          for (int j = 0; j < nv; ++j) {
+            out[(int64_t)r * a.vm_pitch + j] = (uint8_t)m[j];
+            atomicAdd(&hc[m[j]], 1u);
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
           p0[k] = p1[k];
           p1[k] = p2[k];
         }
@@ -173,10 +232,10 @@ __global__ __launch_bounds__(kTC) void k_ex_median(ExArgs a, int32_t parts) {
     }
     __syncthreads();
   }
-  uint32_t s = 0;
+  uint32_t sum = 0;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) s += sh[k][tid];
-  if (s) atomicAdd(&a.hist[(int64_t)chip_id * 256 + tid], s);
+  for (int k = 0; k < 8; ++k) sum += sh[k][tid];
+  if (sum) atomicAdd(&a.hist[(int64_t)chip_id * 256 + tid], sum);
 }
 
 // ---- pass B: per-chip statistics -------------------------------------------------
@@ -385,8 +444,13 @@ __device__ __forceinline__ void hue_sat(uint32_t r, uint32_t g, uint32_t b, uint
   H = q >= 360u ? q - 360u : (q >= 180u ? q - 180u : q);
 }
 
-__global__ __launch_bounds__(kTC) void k_ex_apply(ExArgs a, int32_t ntx, int64_t ntiles) {
+// Tiles of 8 x 1024 pixels; thread t owns columns 4t .. 4t+3.  All rows'
+// loads are issued before any use; the chips' median -> filtered-value tables
+// of the tile are staged in LDS (when the tile touches at most kMaxTileChips
+// chips, else read from the workspace).
+__global__ __launch_bounds__(kThreads) void k_ex_apply(ExArgs a, int32_t ntx, int64_t ntiles) {
   __shared__ uint32_t scnt[kMaxTilePatches][3];
+  __shared__ uint32_t slut[kMaxTileChips][64];
   // which masks admit each hue, saturation and filtered value (bit c = mask c)
   __shared__ uint8_t tH[180], tS[256], tV[256];
   const int tid = threadIdx.x, lane = tid & 63;
@@ -402,23 +466,84 @@ __global__ __launch_bounds__(kTC) void k_ex_apply(ExArgs a, int32_t ntx, int64_t
     tS[tid] = (uint8_t)bs;
     tV[tid] = (uint8_t)bv;
   }
-  __syncthreads();
+  const uint8_t* const slb = (const uint8_t*)&slut[0][0];
+  const int32_t c0 = 4 * tid;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int32_t ty = (int32_t)(tile / ntx) * kTRC, tx = (int32_t)(tile % ntx) * kTC;
-    const int32_t rows = min(kTRC, a.H - ty), cols = min(kTC, a.W - tx);
+    const int32_t ty = (int32_t)(tile / ntx) * kTRC, tx = (int32_t)(tile % ntx) * kTW;
+    const int32_t rows = min(kTRC, a.H - ty), cols = min(kTW, a.W - tx);
+    const int32_t nv = max(0, min(4, cols - c0));  // this thread's pixels in the row
+    const int32_t x = tx + c0;
+    // chips and patches this tile touches
+    int32_t cy0 = 0, cx0 = 0, ncx_t = 1;
+    if (a.filter && a.lut_lds) {
+      cy0 = ty / a.chip;
+      cx0 = tx / a.chip;
+      ncx_t = (tx + cols - 1) / a.chip - cx0 + 1;
+      const int32_t nch = ((ty + rows - 1) / a.chip - cy0 + 1) * ncx_t;
+      for (int i = tid; i < nch * 64; i += kThreads) {
+        const int32_t k = i >> 6;
+        const int64_t chip_id = (int64_t)(cy0 + k / ncx_t) * a.ncx + cx0 + k % ncx_t;
+        slut[k][i & 63] = ((const uint32_t*)(a.lut + chip_id * 256))[i & 63];
+      }
+    }
     int32_t py0 = 0, px0 = 0, npx_t = 0;
     if (a.counts && a.cnt_lds) {
       py0 = ty / a.ph;
       px0 = tx / a.pw;
       npx_t = (tx + cols - 1) / a.pw - px0 + 1;
       const int32_t np = ((ty + rows - 1) / a.ph - py0 + 1) * npx_t;
-      for (int i = tid; i < np * 3; i += kTC) (&scnt[0][0])[i] = 0;
-      __syncthreads();
+      for (int i = tid; i < np * 3; i += kThreads) (&scnt[0][0])[i] = 0;
     }
-    const bool active = tid < cols;
-    const int32_t x = tx + tid;
-    const int32_t cxi = a.filter && active ? x / a.chip : 0;
-    const int32_t ppx = a.counts && active ? x / a.pw : 0;
+    __syncthreads();
+
+    // raw values and medians of all rows first
+    const bool vec = a.in_vec && nv == 4;
+    uint32_t raw[kTRC][3][4], vmw[kTRC];
+#pragma unroll
+    for (int r = 0; r < kTRC; ++r) {
+      vmw[r] = 0;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) raw[r][i][j] = 0;
+      if (r < rows && nv > 0) {
+        const int32_t y = ty + r;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const uint8_t* row = a.band[i] + (int64_t)y * a.pitch_b;
+          if (vec) {
+            if (a.u16) {
+              const uint2 w = *(const uint2*)(row + 2 * (int64_t)x);
+              raw[r][i][0] = w.x & 0xffffu;
+              raw[r][i][1] = w.x >> 16;
+              raw[r][i][2] = w.y & 0xffffu;
+              raw[r][i][3] = w.y >> 16;
+            } else {
+              const uint32_t w = *(const uint32_t*)(row + x);
+#pragma unroll
+              for (int j = 0; j < 4; ++j) raw[r][i][j] = (w >> (8 * j)) & 255u;
+            }
+          } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              if (j < nv) raw[r][i][j] = raw_at(a, i, y, x + j);
+          }
+        }
+        if (a.filter) {
+          const uint8_t* vrow = a.vm + (int64_t)y * a.vm_pitch + x;
+          if (nv == 4) {
+            vmw[r] = *(const uint32_t*)vrow;
+          } else {
+            for (int j = 0; j < nv; ++j) vmw[r] |= (uint32_t)vrow[j] << (8 * j);
+          }
+        }
+      }
+    }
+
+    const int32_t cxi = a.filter ? x / a.chip : 0;
+    int32_t ppx[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) ppx[j] = a.counts ? (x + j) / a.pw : 0;
     int32_t run_key = -1;
     uint32_t run[3] = {0, 0, 0};
     auto flush = [&]() {
@@ -439,56 +564,88 @@ __global__ __launch_bounds__(kTC) void k_ex_apply(ExArgs a, int32_t ntx, int64_t
       }
       run[0] = run[1] = run[2] = 0;
     };
-    for (int r = 0; r < rows; ++r) {
+
+    // fully unrolled so that raw[][][] stays in registers
+#pragma unroll
+    for (int r = 0; r < kTRC; ++r) {
+      if (r >= rows) break;
       const int32_t y = ty + r;
-      int32_t key = -1;
-      uint32_t bits = 0;
-      if (active) {
-        const uint32_t bl = to8(raw_at(a, 0, y, x), a), gr = to8(raw_at(a, 1, y, x), a),
-                       rd = to8(raw_at(a, 2, y, x), a);
-        const uint32_t V = max3u(bl, gr, rd);
-        uint32_t vc = V;
-        if (a.filter) {
-          const uint32_t m = a.vm[(int64_t)y * a.W + x];
-          const int32_t chip_id = (y / a.chip) * a.ncx + cxi;
-          vc = a.lut[(int64_t)chip_id * 256 + m];
-        }
-        uint32_t Hh, Ss;
-        hue_sat(rd, gr, bl, Hh, Ss);
-        bits = (uint32_t)tH[Hh] & tS[Ss] & tV[vc];
-        a.masks[(int64_t)y * a.mask_pitch + x] = (uint8_t)bits;
-        if (a.rgb) {
-          const float rv = V ? __builtin_amdgcn_rcpf((float)V) : 0.f;
-          const uint32_t cband[3] = {bl, gr, rd};
+      const int32_t cyi = a.filter ? y / a.chip : 0;
+      uint32_t bits4 = 0, rgbw[3] = {0, 0, 0};
 #pragma unroll
-          for (int i = 0; i < 3; ++i)
-            a.rgb[((int64_t)i * a.H + y) * a.rgb_pitch + x] =
-                V ? (uint8_t)div_small(cband[i] * vc + V / 2u, V, rv) : (uint8_t)0;
-        }
-        if (a.counts) {
-          if (a.cnt_lds) {
-            key = (y / a.ph - py0) * npx_t + (ppx - px0);
-          } else {
-            uint32_t* cp = a.counts + ((int64_t)(y / a.ph) * a.nx + ppx) * 3;
+      for (int j = 0; j < 4; ++j) {
+        int32_t key = -1;
+        uint32_t bits = 0;
+        if (j < nv) {
+          const uint32_t bl = to8(raw[r][0][j], a), gr = to8(raw[r][1][j], a),
+                         rd = to8(raw[r][2][j], a);
+          const uint32_t V = max3u(bl, gr, rd);
+          uint32_t vc = V;
+          if (a.filter) {
+            const uint32_t m = (vmw[r] >> (8 * j)) & 255u;
+            if (a.lut_lds) {
+              const int32_t k = (cyi - cy0) * ncx_t + ((x + j) / a.chip - cx0);
+              vc = slb[k * 256 + m];
+            } else {
+              const int64_t chip_id = (int64_t)cyi * a.ncx + (j ? (x + j) / a.chip : cxi);
+              vc = a.lut[chip_id * 256 + m];
+            }
+          }
+          uint32_t Hh, Ss;
+          hue_sat(rd, gr, bl, Hh, Ss);
+          bits = (uint32_t)tH[Hh] & tS[Ss] & tV[vc];
+          bits4 |= bits << (8 * j);
+          if (a.rgb) {
+            const float rv = V ? __builtin_amdgcn_rcpf((float)V) : 0.f;
+            const uint32_t cband[3] = {bl, gr, rd};
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-              if (bits >> c & 1u) atomicAdd(&cp[c], 1u);
+            for (int i = 0; i < 3; ++i)
+              rgbw[i] |= (V ? div_small(cband[i] * vc + V / 2u, V, rv) : 0u) << (8 * j);
+          }
+          if (a.counts) {
+            if (a.cnt_lds) {
+              key = (y / a.ph - py0) * npx_t + (ppx[j] - px0);
+            } else {
+              uint32_t* cp = a.counts + ((int64_t)(y / a.ph) * a.nx + ppx[j]) * 3;
+#pragma unroll
+              for (int c = 0; c < 3; ++c)
+                if (bits >> c & 1u) atomicAdd(&cp[c], 1u);
+            }
           }
         }
-      }
-      if (a.counts && a.cnt_lds) {
-        // wave-uniform test: every lane takes part in flush()
-        if (__any(key != run_key && run_key >= 0)) flush();
-        run_key = key;
+        if (a.counts && a.cnt_lds) {
+          // wave-uniform test: every lane takes part in flush()
+          if (__any(key != run_key && run_key >= 0 && key >= 0)) flush();
+          if (key >= 0) run_key = key;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) run[c] += bits >> c & 1u;
+          for (int c = 0; c < 3; ++c) run[c] += bits >> c & 1u;
+        }
+      }
+      if (nv > 0) {
+        uint8_t* mrow = a.masks + (int64_t)y * a.mask_pitch + x;
+        if (a.out_vec && nv == 4) {
+          *(uint32_t*)mrow = bits4;
+        } else {
+          for (int j = 0; j < nv; ++j) mrow[j] = (uint8_t)(bits4 >> (8 * j));
+        }
+        if (a.rgb) {
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            uint8_t* crow = a.rgb + ((int64_t)i * a.H + y) * a.rgb_pitch + x;
+            if (a.out_vec && nv == 4) {
+              *(uint32_t*)crow = rgbw[i];
+            } else {
+              for (int j = 0; j < nv; ++j) crow[j] = (uint8_t)(rgbw[i] >> (8 * j));
+            }
+          }
+        }
       }
     }
     if (a.counts && a.cnt_lds) {
       flush();
       __syncthreads();
       const int32_t np = ((ty + rows - 1) / a.ph - py0 + 1) * npx_t;
-      for (int i = tid; i < np * 3; i += kTC) {
+      for (int i = tid; i < np * 3; i += kThreads) {
         const uint32_t v = (&scnt[0][0])[i];
         if (v) {
           const int32_t k = i / 3, c = i - k * 3;
@@ -496,8 +653,8 @@ __global__ __launch_bounds__(kTC) void k_ex_apply(ExArgs a, int32_t ntx, int64_t
           atomicAdd(&a.counts[((int64_t)py * a.nx + px) * 3 + c], v);
         }
       }
-      __syncthreads();
     }
+    __syncthreads();
   }
 }
 
@@ -512,7 +669,7 @@ __global__ void k_ex_fill(uint32_t* p, int64_t n) {
 int64_t align256(int64_t v) { return (v + 255) & ~int64_t(255); }
 
 struct Layout {
-  int64_t nchips, vm, hist, lut, total;
+  int64_t nchips, vm_pitch, vm, hist, lut, total;
 };
 
 Layout layout(int32_t H, int32_t W, const sil_params* p) {
@@ -520,8 +677,9 @@ Layout layout(int32_t H, int32_t W, const sil_params* p) {
   const int64_t C = p->chip;
   L.nchips = ((H + C - 1) / C) * ((W + C - 1) / C);
   if (!p->filter) return L;
+  L.vm_pitch = (W + 15) & ~int64_t(15);
   L.vm = 0;
-  L.hist = align256((int64_t)H * W);
+  L.hist = align256((int64_t)H * L.vm_pitch);
   L.lut = align256(L.hist + L.nchips * 256 * 4);
   L.total = L.lut + L.nchips * 256;
   return L;
@@ -577,7 +735,8 @@ int sil_label_ex(const void* scene, int32_t nbands, const int32_t sel[3], int32_
   const int64_t esz = p->dtype == SIL_U16 ? 2 : 1;
   if (esz == 2 && ((uintptr_t)scene & 1)) return SIL_EINVAL;
   const Layout L = layout(H, W, p);
-  if (p->filter && (!workspace || workspace_bytes < (uint64_t)L.total)) return SIL_EINVAL;
+  if (p->filter && (!workspace || workspace_bytes < (uint64_t)L.total || (uintptr_t)workspace % 16))
+    return SIL_EINVAL;
   if (L.nchips > INT32_MAX - 4096) return SIL_EUNSUPPORTED;
 
   ExArgs a{};
@@ -599,16 +758,25 @@ int sil_label_ex(const void* scene, int32_t nbands, const int32_t sel[3], int32_
   a.pw = (int32_t)std::min<int64_t>(p->patch_w, W);
   a.nx = (int32_t)((W + (int64_t)p->patch_w - 1) / p->patch_w);
   const int64_t ny = (H + (int64_t)p->patch_h - 1) / p->patch_h;
-  // patches a 8 x 256 tile can touch
+  // patches and chips an 8 x 1024 tile can touch
   const int64_t tp = (std::min<int64_t>(kTRC, H) - 1) / a.ph + 2;
-  const int64_t tq = (std::min<int64_t>(kTC, W) - 1) / a.pw + 2;
+  const int64_t tq = (std::min<int64_t>(kTW, W) - 1) / a.pw + 2;
   a.cnt_lds = tp * tq <= kMaxTilePatches;
+  const int64_t tcy = (std::min<int64_t>(kTRC, H) - 1) / a.chip + 2;
+  const int64_t tcx = (std::min<int64_t>(kTW, W) - 1) / a.chip + 2;
+  a.lut_lds = tcy * tcx <= kMaxTileChips;
+  const int64_t ain = esz == 2 ? 8 : 4;
+  a.in_vec = a.pitch_b % ain == 0;
+  for (int i = 0; i < 3; ++i) a.in_vec = a.in_vec && (uintptr_t)a.band[i] % ain == 0;
+  a.out_vec = mask_pitch % 4 == 0 && (uintptr_t)masks % 4 == 0 &&
+              (!rgb || (rgb_pitch % 4 == 0 && (uintptr_t)rgb % 4 == 0));
   memcpy(a.lo, p->lo, sizeof(a.lo));
   memcpy(a.hi, p->hi, sizeof(a.hi));
   a.clip_shift = p->clip_shift;
   a.eta_num = p->eta_num;
   a.eta_den = p->eta_den;
   if (p->filter) {
+    a.vm_pitch = L.vm_pitch;
     a.vm = (uint8_t*)workspace + L.vm;
     a.hist = (uint32_t*)((uint8_t*)workspace + L.hist);
     a.lut = (uint8_t*)workspace + L.lut;
@@ -627,10 +795,10 @@ int sil_label_ex(const void* scene, int32_t nbands, const int32_t sel[3], int32_
     hipLaunchKernelGGL(k_ex_fill, dim3((unsigned)std::min<int64_t>((nh + 255) / 256, 4096)),
                        dim3(256), 0, st, a.hist, nh);
     const int64_t tiles_per_chip = ((std::min<int64_t>(a.chip, H) + kTR - 1) / kTR) *
-                                   ((std::min<int64_t>(a.chip, W) + kTC - 1) / kTC);
+                                   ((std::min<int64_t>(a.chip, W) + kTW - 1) / kTW);
     const int32_t parts = (int32_t)std::max<int64_t>(
         1, std::min<int64_t>((2048 + L.nchips - 1) / L.nchips, tiles_per_chip));
-    hipLaunchKernelGGL(k_ex_median, dim3((unsigned)(L.nchips * parts)), dim3(kTC), 0, st, a,
+    hipLaunchKernelGGL(k_ex_median, dim3((unsigned)(L.nchips * parts)), dim3(kThreads), 0, st, a,
                        parts);
     hipLaunchKernelGGL(k_ex_stats, dim3((unsigned)L.nchips), dim3(64), 0, st, a);
   }
@@ -639,9 +807,9 @@ int sil_label_ex(const void* scene, int32_t nbands, const int32_t sel[3], int32_
     hipLaunchKernelGGL(k_ex_fill, dim3((unsigned)std::min<int64_t>((nc + 255) / 256, 4096)),
                        dim3(256), 0, st, counts, nc);
   }
-  const int32_t ntx = (W + kTC - 1) / kTC;
+  const int32_t ntx = (W + kTW - 1) / kTW;
   const int64_t ntiles = (int64_t)((H + kTRC - 1) / kTRC) * ntx;
-  hipLaunchKernelGGL(k_ex_apply, dim3((unsigned)std::min<int64_t>(ntiles, 8192)), dim3(kTC), 0,
+  hipLaunchKernelGGL(k_ex_apply, dim3((unsigned)std::min<int64_t>(ntiles, 8192)), dim3(kThreads), 0,
                      st, a, ntx, ntiles);
   return hipGetLastError() == hipSuccess ? SIL_OK : SIL_EDEVICE;
 }
