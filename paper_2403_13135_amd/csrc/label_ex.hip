@@ -11,8 +11,8 @@
 //
 // Three passes over HBM instead of the fused one, because a chip of
 // arbitrary size no longer fits one workgroup:
-//   A. k_ex_median (filter = 1): blocks own (chip, part) pairs and walk 16 x
-//      1024 tiles of their chip; V = max(B,G,R) of the tile plus a one-pixel
+//   A. k_ex_median (filter = 1): blocks own (chip, part) pairs and walk
+//      tiles of their chip (16 x 1024, 32 x 512 or 64 x 256 pixels); V = max(B,G,R) of the tile plus a one-pixel
 //      halo (clamped at the scene border) is staged in LDS with 8-byte band
 //      loads, each thread slides the 3x3 median down four columns (column
 //      sorts + median of three triples), writes the 8-bit median plane to the
@@ -37,6 +37,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "sil.h"
 
@@ -46,6 +47,7 @@ constexpr int kThreads = 256;     // threads per block of passes A and C
 constexpr int kTR = 16;           // pass A tile rows
 constexpr int kTW = 4 * kThreads; // tile columns: 4 per thread
 constexpr int kTRC = 8;           // pass C tile rows
+constexpr int kRB = 4;            // pass C rows per load batch
 constexpr int kMaxTilePatches = 128;
 constexpr int kMaxTileChips = 16; // per-chip tables a pass C tile stages in LDS
 constexpr int64_t kMaxChipPixels = int64_t(1) << 27;
@@ -57,6 +59,8 @@ struct ExArgs {
   int32_t u16;
   uint32_t refl_max, half, sat_n;  // sat_n = 255 * refl_max: first saturating numerator
   float rd;                // 1 / refl_max
+  uint32_t magic, shift;   // floor(n / refl_max) = mulhi(n, magic) >> shift below sat_n
+  int32_t use_magic;
   int32_t filter;
   int32_t chip, ncx, nchips;
   int32_t ph, pw, nx;
@@ -66,6 +70,7 @@ struct ExArgs {
   int32_t in_vec;          // band rows 8-byte (u16) / 4-byte (u8) aligned
   int32_t out_vec;         // mask and colour rows 4-byte aligned
   int32_t lut_lds;         // pass C tiles stage their chips' tables in LDS
+  int32_t hs_all;          // every mask admits every hue and saturation
   int64_t vm_pitch;        // row pitch of the median plane (multiple of 16)
   uint8_t* vm;             // workspace: [H][vm_pitch] median plane
   uint32_t* hist;          // workspace: [nchips][256]
@@ -89,21 +94,28 @@ __device__ __forceinline__ uint32_t div_small(uint32_t n, uint32_t d, float rd) 
 
 // 16-bit reflectance to 8 bit: round-half-up of x * 255 / refl_max,
 // saturating.  n < 2^24; below the saturation point the quotient is < 255.
+template <bool U16>
 __device__ __forceinline__ uint32_t to8(uint32_t x, const ExArgs& a) {
-  if (!a.u16) return x;
+  if (!U16) return x;
   const uint32_t n = x * 255u + a.half;
-  return n >= a.sat_n ? 255u : div_small(n, a.refl_max, a.rd);
+  if (n >= a.sat_n) return 255u;
+  return a.use_magic ? __umulhi(n, a.magic) >> a.shift : div_small(n, a.refl_max, a.rd);
 }
 
+template <bool U16>
 __device__ __forceinline__ uint32_t raw_at(const ExArgs& a, int i, int32_t y, int32_t x) {
   const uint8_t* row = a.band[i] + (int64_t)y * a.pitch_b;
-  return a.u16 ? (uint32_t)((const uint16_t*)row)[x] : (uint32_t)row[x];
+  return U16 ? (uint32_t)((const uint16_t*)row)[x] : (uint32_t)row[x];
 }
 
 // V = max over the bands (max commutes with the non-decreasing rescale)
 __device__ __forceinline__ uint32_t value_at(const ExArgs& a, int32_t y, int32_t x) {
-  const uint32_t m = max(max(raw_at(a, 0, y, x), raw_at(a, 1, y, x)), raw_at(a, 2, y, x));
-  return to8(m, a);
+  if (a.u16) {
+    const uint32_t m =
+        max(max(raw_at<true>(a, 0, y, x), raw_at<true>(a, 1, y, x)), raw_at<true>(a, 2, y, x));
+    return to8<true>(m, a);
+  }
+  return max(max(raw_at<false>(a, 0, y, x), raw_at<false>(a, 1, y, x)), raw_at<false>(a, 2, y, x));
 }
 
 __device__ __forceinline__ uint32_t min3u(uint32_t a, uint32_t b, uint32_t c) {
@@ -138,68 +150,79 @@ __device__ __forceinline__ void value4(const ExArgs& a, int32_t y, int32_t x, ui
     }
   }
 #pragma unroll
-  for (int j = 0; j < 4; ++j) v[j] = to8(m[j], a);
+  for (int j = 0; j < 4; ++j) v[j] = a.u16 ? to8<true>(m[j], a) : m[j];
 }
 
-// Blocks own (chip, part) pairs and walk 16 x 1024 tiles of their chip.  The
-// tile's V plus a one-pixel halo is staged in LDS (pixel column c at byte
-// c + 4 of its row, so each thread's four columns are one aligned word);
-// thread t then slides the 3x3 median down columns 4t .. 4t+3.
+// Blocks own (chip, part) pairs and walk tiles of their chip: TW columns
+// (256, 512 or 1024, the narrowest that spans the chip) by 16 * (1024 / TW)
+// rows, so narrow chips keep every thread busy.  The tile's V plus a one-pixel
+// halo is staged in LDS (pixel column c at byte c + 4 of its row, so each
+// thread's four columns are one aligned word); thread (g, u) then slides the
+// 3x3 median down columns 4u .. 4u+3 of rows 16g .. 16g+15.
+template <int TW>
 __global__ __launch_bounds__(kThreads) void k_ex_median(ExArgs a, int32_t parts) {
-  __shared__ uint32_t svw[kTR + 2][kTW / 4 + 2];
+  constexpr int RG = kTW / TW;          // row groups
+  constexpr int TH = kTR * RG;          // tile rows
+  constexpr int WPR = TW / 4 + 2;       // staged words per row
+  __shared__ uint32_t svw[TH + 2][WPR];
   __shared__ uint32_t sh[8][256];
   uint8_t* const svb = (uint8_t*)&svw[0][0];
-  constexpr int kRowB = 4 * (kTW / 4 + 2);  // bytes per staged row
   const int tid = threadIdx.x;
+  const int g = tid / (TW / 4), u = tid % (TW / 4);
   for (int i = tid; i < 8 * 256; i += kThreads) (&sh[0][0])[i] = 0;
   const int32_t chip_id = blockIdx.x / parts, part = blockIdx.x % parts;
   const int32_t cy = chip_id / a.ncx, cx = chip_id - cy * a.ncx;
   const int32_t y0 = (int32_t)((int64_t)cy * a.chip), x0 = (int32_t)((int64_t)cx * a.chip);
   const int32_t ch = min(a.chip, a.H - y0), cw = min(a.chip, a.W - x0);
-  const int32_t nty = (ch + kTR - 1) / kTR, ntx = (cw + kTW - 1) / kTW;
+  const int32_t nty = (ch + TH - 1) / TH, ntx = (cw + TW - 1) / TW;
   uint32_t* hc = sh[tid & 7];
-  const int32_t c0 = 4 * tid;  // this thread's first tile column
+  const int32_t c0 = 4 * u;  // this thread's first tile column
   __syncthreads();
   for (int32_t t = part; t < nty * ntx; t += parts) {
-    const int32_t ty = y0 + (t / ntx) * kTR, tx = x0 + (t % ntx) * kTW;
-    const int32_t rows = min(kTR, y0 + ch - ty), cols = min(kTW, x0 + cw - tx);
-    // stage tile columns -1 .. cols (clamped to the scene), rows -1 .. rows
+    const int32_t ty = y0 + (t / ntx) * TH, tx = x0 + (t % ntx) * TW;
+    const int32_t rows = min(TH, y0 + ch - ty), cols = min(TW, x0 + cw - tx);
+    // stage tile columns -1 .. cols (clamped to the scene), rows -1 .. rows;
+    // row group g stages rows g, g + RG, ...
     const bool vec = a.in_vec && (tx & 3) == 0 && tx + c0 + 3 < a.W && c0 < cols;
 #pragma unroll
-    for (int r = 0; r < kTR + 2; ++r) {
+    for (int k = 0; k < (TH + 2 + RG - 1) / RG; ++k) {
+      const int r = g + k * RG;
       if (r < rows + 2) {
         const int32_t y = min(max(ty - 1 + r, 0), a.H - 1);
         if (vec) {
           uint32_t v[4];
           value4(a, y, tx + c0, v);
-          svw[r][tid + 1] = v[0] | (v[1] << 8) | (v[2] << 16) | (v[3] << 24);
+          svw[r][u + 1] = v[0] | (v[1] << 8) | (v[2] << 16) | (v[3] << 24);
         } else if (c0 <= cols) {
           for (int j = 0; j < 4 && c0 + j <= cols; ++j)
-            svb[r * kRowB + c0 + j + 4] = (uint8_t)value_at(a, y, min(tx + c0 + j, a.W - 1));
+            svb[r * (4 * WPR) + c0 + j + 4] =
+                (uint8_t)value_at(a, y, min(tx + c0 + j, a.W - 1));
         }
-        if (tid == 0) svb[r * kRowB + 3] = (uint8_t)value_at(a, y, max(tx - 1, 0));
-        if (tid == 1 && cols == kTW)
-          svb[r * kRowB + kTW + 4] = (uint8_t)value_at(a, y, min(tx + kTW, a.W - 1));
+        if (u == 0) svb[r * (4 * WPR) + 3] = (uint8_t)value_at(a, y, max(tx - 1, 0));
+        if (u == 1 && cols == TW)
+          svb[r * (4 * WPR) + TW + 4] = (uint8_t)value_at(a, y, min(tx + TW, a.W - 1));
       }
     }
     __syncthreads();
-    if (c0 < cols) {
-      // input columns c0-1 .. c0+4 are bytes 3 .. 8 of words tid, tid+1, tid+2
+    const int32_t rb = kTR * g;  // this thread's first tile row
+    if (c0 < cols && rb < rows) {
+      // input columns c0-1 .. c0+4 are bytes 3 .. 8 of words u, u+1, u+2
       auto col6 = [&](int r, uint32_t c[6]) {
-        const uint32_t wl = svw[r][tid], wm = svw[r][tid + 1], wr = svw[r][tid + 2];
+        const uint32_t wl = svw[r][u], wm = svw[r][u + 1], wr = svw[r][u + 2];
         c[0] = wl >> 24;
 #pragma unroll
         for (int j = 0; j < 4; ++j) c[1 + j] = (wm >> (8 * j)) & 255u;
         c[5] = wr & 255u;
       };
       uint32_t p0[6], p1[6];
-      col6(0, p0);
-      col6(1, p1);
+      col6(rb, p0);
+      col6(rb + 1, p1);
       const int nv = min(4, cols - c0);
-      uint8_t* out = a.vm + (int64_t)ty * a.vm_pitch + tx + c0;
-      for (int r = 0; r < rows; ++r) {
+      const int nr = min(kTR, rows - rb);
+      uint8_t* out = a.vm + (int64_t)(ty + rb) * a.vm_pitch + tx + c0;
+      for (int r = 0; r < nr; ++r) {
         uint32_t p2[6], lo3[6], md3[6], hi3[6];
-        col6(r + 2, p2);
+        col6(rb + r + 2, p2);
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
           lo3[k] = min3u(p0[k], p1[k], p2[k]);
@@ -215,14 +238,14 @@ __global__ __launch_bounds__(kThreads) void k_ex_median(ExArgs a, int32_t parts)
         if (nv == 4 && (tx & 3) == 0) {
           *(uint32_t*)(out + (int64_t)r * a.vm_pitch) =
               m[0] | (m[1] << 8) | (m[2] << 16) | (m[3] << 24);
-#pragma unroll
-          for (int j = 0; j < 4; ++j) atomicAdd(&hc[m[j]], 1u);
         } else {
-          for (int j = 0; j < nv; ++j) {
-            out[(int64_t)r * a.vm_pitch + j] = (uint8_t)m[j];
-            atomicAdd(&hc[m[j]], 1u);
-          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (j < nv) out[(int64_t)r * a.vm_pitch + j] = (uint8_t)m[j];
         }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (j < nv) atomicAdd(&hc[m[j]], 1u);
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
           p0[k] = p1[k];
@@ -448,6 +471,7 @@ __device__ __forceinline__ void hue_sat(uint32_t r, uint32_t g, uint32_t b, uint
 // loads are issued before any use; the chips' median -> filtered-value tables
 // of the tile are staged in LDS (when the tile touches at most kMaxTileChips
 // chips, else read from the workspace).
+template <bool U16, bool FILTER, bool HSALL>
 __global__ __launch_bounds__(kThreads) void k_ex_apply(ExArgs a, int32_t ntx, int64_t ntiles) {
   __shared__ uint32_t scnt[kMaxTilePatches][3];
   __shared__ uint32_t slut[kMaxTileChips][64];
@@ -475,7 +499,7 @@ __global__ __launch_bounds__(kThreads) void k_ex_apply(ExArgs a, int32_t ntx, in
     const int32_t x = tx + c0;
     // chips and patches this tile touches
     int32_t cy0 = 0, cx0 = 0, ncx_t = 1;
-    if (a.filter && a.lut_lds) {
+    if (FILTER && a.lut_lds) {
       cy0 = ty / a.chip;
       cx0 = tx / a.chip;
       ncx_t = (tx + cols - 1) / a.chip - cx0 + 1;
@@ -496,51 +520,7 @@ __global__ __launch_bounds__(kThreads) void k_ex_apply(ExArgs a, int32_t ntx, in
     }
     __syncthreads();
 
-    // raw values and medians of all rows first
-    const bool vec = a.in_vec && nv == 4;
-    uint32_t raw[kTRC][3][4], vmw[kTRC];
-#pragma unroll
-    for (int r = 0; r < kTRC; ++r) {
-      vmw[r] = 0;
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) raw[r][i][j] = 0;
-      if (r < rows && nv > 0) {
-        const int32_t y = ty + r;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          const uint8_t* row = a.band[i] + (int64_t)y * a.pitch_b;
-          if (vec) {
-            if (a.u16) {
-              const uint2 w = *(const uint2*)(row + 2 * (int64_t)x);
-              raw[r][i][0] = w.x & 0xffffu;
-              raw[r][i][1] = w.x >> 16;
-              raw[r][i][2] = w.y & 0xffffu;
-              raw[r][i][3] = w.y >> 16;
-            } else {
-              const uint32_t w = *(const uint32_t*)(row + x);
-#pragma unroll
-              for (int j = 0; j < 4; ++j) raw[r][i][j] = (w >> (8 * j)) & 255u;
-            }
-          } else {
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-              if (j < nv) raw[r][i][j] = raw_at(a, i, y, x + j);
-          }
-        }
-        if (a.filter) {
-          const uint8_t* vrow = a.vm + (int64_t)y * a.vm_pitch + x;
-          if (nv == 4) {
-            vmw[r] = *(const uint32_t*)vrow;
-          } else {
-            for (int j = 0; j < nv; ++j) vmw[r] |= (uint32_t)vrow[j] << (8 * j);
-          }
-        }
-      }
-    }
-
-    const int32_t cxi = a.filter ? x / a.chip : 0;
+    const int32_t cxi = FILTER ? x / a.chip : 0;
     int32_t ppx[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) ppx[j] = a.counts ? (x + j) / a.pw : 0;
@@ -565,23 +545,70 @@ __global__ __launch_bounds__(kThreads) void k_ex_apply(ExArgs a, int32_t ntx, in
       run[0] = run[1] = run[2] = 0;
     };
 
-    // fully unrolled so that raw[][][] stays in registers
+    // rows in batches of kRB: every load of a batch is in flight before its
+    // first use; inner loops fully unrolled so raw[][][] stays in registers
+#pragma unroll 1
+    for (int rb = 0; rb < rows; rb += kRB) {
+      const bool vec = a.in_vec && nv == 4;
+      uint32_t raw[kRB][3][4], vmw[kRB];
 #pragma unroll
-    for (int r = 0; r < kTRC; ++r) {
-      if (r >= rows) break;
-      const int32_t y = ty + r;
-      const int32_t cyi = a.filter ? y / a.chip : 0;
+      for (int r = 0; r < kRB; ++r) {
+        vmw[r] = 0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) raw[r][i][j] = 0;
+        if (rb + r < rows && nv > 0) {
+          const int32_t y = ty + rb + r;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            const uint8_t* row = a.band[i] + (int64_t)y * a.pitch_b;
+            if (vec) {
+              if (U16) {
+                const uint2 w = *(const uint2*)(row + 2 * (int64_t)x);
+                raw[r][i][0] = w.x & 0xffffu;
+                raw[r][i][1] = w.x >> 16;
+                raw[r][i][2] = w.y & 0xffffu;
+                raw[r][i][3] = w.y >> 16;
+              } else {
+                const uint32_t w = *(const uint32_t*)(row + x);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) raw[r][i][j] = (w >> (8 * j)) & 255u;
+              }
+            } else {
+#pragma unroll
+              for (int j = 0; j < 4; ++j)
+                if (j < nv) raw[r][i][j] = raw_at<U16>(a, i, y, x + j);
+            }
+          }
+          if (FILTER) {
+            const uint8_t* vrow = a.vm + (int64_t)y * a.vm_pitch + x;
+            if (nv == 4) {
+              vmw[r] = *(const uint32_t*)vrow;
+            } else {
+              for (int j = 0; j < nv; ++j) vmw[r] |= (uint32_t)vrow[j] << (8 * j);
+            }
+          }
+        }
+      }
+
+
+#pragma unroll
+    for (int r = 0; r < kRB; ++r) {
+      if (rb + r >= rows) break;
+      const int32_t y = ty + rb + r;
+      const int32_t cyi = FILTER ? y / a.chip : 0;
       uint32_t bits4 = 0, rgbw[3] = {0, 0, 0};
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         int32_t key = -1;
         uint32_t bits = 0;
         if (j < nv) {
-          const uint32_t bl = to8(raw[r][0][j], a), gr = to8(raw[r][1][j], a),
-                         rd = to8(raw[r][2][j], a);
+          const uint32_t bl = to8<U16>(raw[r][0][j], a), gr = to8<U16>(raw[r][1][j], a),
+                         rd = to8<U16>(raw[r][2][j], a);
           const uint32_t V = max3u(bl, gr, rd);
           uint32_t vc = V;
-          if (a.filter) {
+          if (FILTER) {
             const uint32_t m = (vmw[r] >> (8 * j)) & 255u;
             if (a.lut_lds) {
               const int32_t k = (cyi - cy0) * ncx_t + ((x + j) / a.chip - cx0);
@@ -591,9 +618,13 @@ __global__ __launch_bounds__(kThreads) void k_ex_apply(ExArgs a, int32_t ntx, in
               vc = a.lut[chip_id * 256 + m];
             }
           }
-          uint32_t Hh, Ss;
-          hue_sat(rd, gr, bl, Hh, Ss);
-          bits = (uint32_t)tH[Hh] & tS[Ss] & tV[vc];
+          if (HSALL) {
+            bits = tV[vc];
+          } else {
+            uint32_t Hh, Ss;
+            hue_sat(rd, gr, bl, Hh, Ss);
+            bits = (uint32_t)tH[Hh] & tS[Ss] & tV[vc];
+          }
           bits4 |= bits << (8 * j);
           if (a.rgb) {
             const float rv = V ? __builtin_amdgcn_rcpf((float)V) : 0.f;
@@ -641,6 +672,7 @@ __global__ __launch_bounds__(kThreads) void k_ex_apply(ExArgs a, int32_t ntx, in
         }
       }
     }
+    }  // row batches
     if (a.counts && a.cnt_lds) {
       flush();
       __syncthreads();
@@ -667,6 +699,43 @@ __global__ void k_ex_fill(uint32_t* p, int64_t n) {
 // ---- host ---------------------------------------------------------------------------
 
 int64_t align256(int64_t v) { return (v + 255) & ~int64_t(255); }
+
+// A multiply-shift for floor(n / d) over every numerator the rescale reaches
+// below saturation (n = x * 255 + d/2 < 255 * d): the smallest shift whose
+// rounded-up 32-bit magic checks out on all of them (Granlund-Montgomery).
+bool derive_magic_uncached(uint32_t d, uint32_t* magic, uint32_t* shift) {
+  const uint64_t nmax = 255ull * d - 1;
+  for (uint32_t s = 0; s < 32; ++s) {
+    const uint64_t m = ((1ull << (32 + s)) + d - 1) / d;
+    if (m >= (1ull << 32)) break;
+    bool ok = true;
+    for (uint64_t x = 0; ok && x <= 65535; ++x) {
+      const uint64_t n = x * 255 + d / 2;
+      if (n > nmax) break;
+      ok = ((n * m) >> (32 + s)) == n / d;
+    }
+    if (ok) {
+      *magic = (uint32_t)m;
+      *shift = s;
+      return true;
+    }
+  }
+  return false;
+}
+
+bool derive_magic(uint32_t d, uint32_t* magic, uint32_t* shift) {
+  static std::mutex mu;
+  static uint32_t cd = 0, cm = 0, cs = 0;
+  static bool cok = false;
+  std::lock_guard<std::mutex> lock(mu);
+  if (cd != d) {
+    cok = derive_magic_uncached(d, &cm, &cs);
+    cd = d;
+  }
+  *magic = cm;
+  *shift = cs;
+  return cok;
+}
 
 struct Layout {
   int64_t nchips, vm_pitch, vm, hist, lut, total;
@@ -750,6 +819,7 @@ int sil_label_ex(const void* scene, int32_t nbands, const int32_t sel[3], int32_
   a.half = p->refl_max / 2u;
   a.sat_n = 255u * p->refl_max;
   a.rd = 1.0f / (float)(p->refl_max ? p->refl_max : 1);
+  if (esz == 2) a.use_magic = derive_magic(p->refl_max, &a.magic, &a.shift);
   a.filter = (int32_t)p->filter;
   a.chip = (int32_t)std::min<int64_t>(p->chip, std::max(H, W));
   a.ncx = (int32_t)((W + (int64_t)p->chip - 1) / p->chip);
@@ -771,6 +841,10 @@ int sil_label_ex(const void* scene, int32_t nbands, const int32_t sel[3], int32_
   a.out_vec = mask_pitch % 4 == 0 && (uintptr_t)masks % 4 == 0 &&
               (!rgb || (rgb_pitch % 4 == 0 && (uintptr_t)rgb % 4 == 0));
   memcpy(a.lo, p->lo, sizeof(a.lo));
+  a.hs_all = 1;
+  for (int c = 0; c < 3; ++c)
+    if (p->lo[c][0] != 0 || p->hi[c][0] < 179 || p->lo[c][1] != 0 || p->hi[c][1] != 255)
+      a.hs_all = 0;
   memcpy(a.hi, p->hi, sizeof(a.hi));
   a.clip_shift = p->clip_shift;
   a.eta_num = p->eta_num;
@@ -794,12 +868,21 @@ int sil_label_ex(const void* scene, int32_t nbands, const int32_t sel[3], int32_
     const int64_t nh = L.nchips * 256;
     hipLaunchKernelGGL(k_ex_fill, dim3((unsigned)std::min<int64_t>((nh + 255) / 256, 4096)),
                        dim3(256), 0, st, a.hist, nh);
-    const int64_t tiles_per_chip = ((std::min<int64_t>(a.chip, H) + kTR - 1) / kTR) *
-                                   ((std::min<int64_t>(a.chip, W) + kTW - 1) / kTW);
+    // the narrowest tile width that spans a chip
+    const int64_t cwid = std::min<int64_t>(a.chip, W);
+    const int tw = cwid <= 256 ? 256 : (cwid <= 512 ? 512 : kTW);
+    const int64_t th = (int64_t)kTR * (kTW / tw);
+    const int64_t tiles_per_chip = ((std::min<int64_t>(a.chip, H) + th - 1) / th) *
+                                   ((cwid + tw - 1) / tw);
     const int32_t parts = (int32_t)std::max<int64_t>(
         1, std::min<int64_t>((2048 + L.nchips - 1) / L.nchips, tiles_per_chip));
-    hipLaunchKernelGGL(k_ex_median, dim3((unsigned)(L.nchips * parts)), dim3(kThreads), 0, st, a,
-                       parts);
+    const dim3 grid((unsigned)(L.nchips * parts));
+    if (tw == 256)
+      hipLaunchKernelGGL(k_ex_median<256>, grid, dim3(kThreads), 0, st, a, parts);
+    else if (tw == 512)
+      hipLaunchKernelGGL(k_ex_median<512>, grid, dim3(kThreads), 0, st, a, parts);
+    else
+      hipLaunchKernelGGL(k_ex_median<kTW>, grid, dim3(kThreads), 0, st, a, parts);
     hipLaunchKernelGGL(k_ex_stats, dim3((unsigned)L.nchips), dim3(64), 0, st, a);
   }
   if (counts) {
@@ -809,8 +892,13 @@ int sil_label_ex(const void* scene, int32_t nbands, const int32_t sel[3], int32_
   }
   const int32_t ntx = (W + kTW - 1) / kTW;
   const int64_t ntiles = (int64_t)((H + kTRC - 1) / kTRC) * ntx;
-  hipLaunchKernelGGL(k_ex_apply, dim3((unsigned)std::min<int64_t>(ntiles, 8192)), dim3(kThreads), 0,
-                     st, a, ntx, ntiles);
+  const dim3 cgrid((unsigned)std::min<int64_t>(ntiles, 8192));
+#define SIL_EX_APPLY(U, F, HS)                                                             \
+  if (a.u16 == U && a.filter == F && a.hs_all == HS)                                       \
+    hipLaunchKernelGGL((k_ex_apply<U, F, HS>), cgrid, dim3(kThreads), 0, st, a, ntx, ntiles);
+  SIL_EX_APPLY(1, 1, 1) SIL_EX_APPLY(1, 1, 0) SIL_EX_APPLY(1, 0, 1) SIL_EX_APPLY(1, 0, 0)
+  SIL_EX_APPLY(0, 1, 1) SIL_EX_APPLY(0, 1, 0) SIL_EX_APPLY(0, 0, 1) SIL_EX_APPLY(0, 0, 0)
+#undef SIL_EX_APPLY
   return hipGetLastError() == hipSuccess ? SIL_OK : SIL_EDEVICE;
 }
 
