@@ -42,6 +42,16 @@ int sil_unet_conv3x3(const void* x0, int32_t c0, const void* x1, int32_t c1, con
                      void* y, float* stats, int32_t N, int32_t H, int32_t W, int32_t cout,
                      void* stream);
 
+/* Inference form of a conv + batch-norm + ReLU layer: the same 3x3
+ * convolution as sil_unet_conv3x3, with y = max(0, conv * scale[co] +
+ * shift[co]) applied to the fp32 result before rounding to bf16 (batch norm
+ * with running statistics folded into scale/shift, fp32 [cout]).  Every output
+ * pixel depends only on its own input neighbourhood, so a chip's result does
+ * not depend on the rest of the batch. */
+int sil_unet_conv3x3_affine_relu(const void* x0, int32_t c0, const void* x1, int32_t c1,
+                                 const void* w, const float* scale, const float* shift, void* y,
+                                 int32_t N, int32_t H, int32_t W, int32_t cout, void* stream);
+
 /* Input gradient of sil_unet_conv3x3: dx = conv3x3(dy, wt) with wt the
  * flipped, transposed weights [c0+c1][3][3][cout] (sil_unet_flip3x3).  The
  * result is split by channel into dx0 [N][H][W][c0] and dx1 [..][c1]

@@ -53,7 +53,9 @@ __device__ __forceinline__ u16 f2bf(float f) {
 // 32-wide reduction step lies inside one tap: the tap and channel offset are
 // block-uniform counters and each row's shifted address is one add.
 enum AMode : int { A_ROWS = 0, A_IM2COL = 1, A_UPGATHER = 2, A_IM2COL32 = 3 };
-enum EMode : int { E_STORE = 0, E_SPLIT = 1, E_UPSCATTER = 2 };
+// E_AFFRELU: inference epilogue, y = max(0, acc * scale[n] + shift[n]) (batch
+// norm with running statistics folded into scale/shift, then ReLU)
+enum EMode : int { E_STORE = 0, E_SPLIT = 1, E_UPSCATTER = 2, E_AFFRELU = 3 };
 
 struct GemmNT {
   int32_t M, N, K;
@@ -67,6 +69,8 @@ struct GemmNT {
   int32_t split, up_cout;
   const float* bias;  // UPSCATTER
   float* stats;       // STORE: [2][N] (nullable)
+  const float* scale;  // AFFRELU: [N]
+  const float* shift;  // AFFRELU: [N]
 };
 
 // 16 bytes (8 bf16) of A at row m, reduction index k (k % 8 == 0).
@@ -228,6 +232,9 @@ __global__ __launch_bounds__(kGT) void k_gemm_nt(GemmNT g) {
             g.y0[(int64_t)row * g.N + col] = f2bf(v);
             s1[j] += v;
             s2[j] += v * v;
+          } else if constexpr (EM == E_AFFRELU) {
+            const float t = v * g.scale[col] + g.shift[col];
+            g.y0[(int64_t)row * g.N + col] = f2bf(t > 0.f ? t : 0.f);
           } else if constexpr (EM == E_SPLIT) {
             if (col < g.split)
               g.y0[(int64_t)row * g.split + col] = f2bf(v);
@@ -1069,6 +1076,30 @@ int sil_unet_conv3x3(const void* x0, int32_t c0, const void* x1, int32_t c1, con
   g.stats = stats;
   if ((c0 + c1) % kBK == 0) return launch_nt<A_IM2COL32, E_STORE>(g, (hipStream_t)stream);
   return launch_nt<A_IM2COL, E_STORE>(g, (hipStream_t)stream);
+}
+
+int sil_unet_conv3x3_affine_relu(const void* x0, int32_t c0, const void* x1, int32_t c1,
+                                 const void* w, const float* scale, const float* shift, void* y,
+                                 int32_t N, int32_t H, int32_t W, int32_t cout, void* stream) {
+  if (!x0 || !w || !y || !scale || !shift || (c1 > 0 && !x1) || !ok_dims(N, H, W))
+    return SIL_EINVAL;
+  if (c0 <= 0 || c0 % 8 || c1 < 0 || c1 % 8 || cout <= 0 || cout % 8) return SIL_EINVAL;
+  GemmNT g{};
+  g.M = N * H * W;
+  g.N = cout;
+  g.K = 9 * (c0 + c1);
+  g.a0 = (const u16*)x0;
+  g.a1 = (const u16*)x1;
+  g.c0 = c0;
+  g.c1 = c1;
+  g.H = H;
+  g.W = W;
+  g.b = (const u16*)w;
+  g.y0 = (u16*)y;
+  g.scale = scale;
+  g.shift = shift;
+  if ((c0 + c1) % kBK == 0) return launch_nt<A_IM2COL32, E_AFFRELU>(g, (hipStream_t)stream);
+  return launch_nt<A_IM2COL, E_AFFRELU>(g, (hipStream_t)stream);
 }
 
 int sil_unet_conv3x3_dgrad(const void* dy, int32_t cout, const void* wt, void* dx0, int32_t c0,

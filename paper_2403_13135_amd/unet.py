@@ -34,6 +34,8 @@ def _lib():
         vp, i32, i64, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
         sig = {
             "sil_unet_conv3x3": [vp, i32, vp, i32, vp, vp, vp, i32, i32, i32, i32, vp],
+            "sil_unet_conv3x3_affine_relu": [vp, i32, vp, i32, vp, vp, vp, vp, i32, i32, i32,
+                                             i32, vp],
             "sil_unet_conv3x3_dgrad": [vp, i32, vp, vp, i32, vp, i32, i32, i32, i32, vp],
             "sil_unet_conv3x3_wgrad": [vp, i32, vp, i32, vp, i32, vp, i32, i32, i32, vp],
             "sil_unet_flip3x3": [vp, vp, i32, i32, vp],
@@ -320,15 +322,12 @@ class UNet:
             c1 = 0 if skip is None else skip.shape[3]
             wb = _bf16(P[n + ".w"])
             cout = wb.shape[0]
-            z = torch.empty((Nn, Hh, Ww, cout), dtype=torch.bfloat16, device=dev)
-            _call("sil_unet_conv3x3", _p(h), c0, _p(skip), c1, _p(wb), _p(z), None, Nn, Hh, Ww,
-                  cout, _s())
             rm, rv = self.running[n]
-            scale = P[n + ".gamma"] / torch.sqrt(rv + BN_EPS)
-            shift = P[n + ".beta"] - rm * scale
-            out = torch.empty_like(z)
-            _call("sil_unet_affine_relu", _p(z), _p(scale.contiguous()), _p(shift.contiguous()),
-                  _p(out), Nn * Hh * Ww, cout, _s())
+            scale = (P[n + ".gamma"] / torch.sqrt(rv + BN_EPS)).contiguous()
+            shift = (P[n + ".beta"] - rm * scale).contiguous()
+            out = torch.empty((Nn, Hh, Ww, cout), dtype=torch.bfloat16, device=dev)
+            _call("sil_unet_conv3x3_affine_relu", _p(h), c0, _p(skip), c1, _p(wb), _p(scale),
+                  _p(shift), _p(out), Nn, Hh, Ww, cout, _s())
             return out
 
         skips, h, L = [], x, len(self.widths)

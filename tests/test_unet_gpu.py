@@ -90,6 +90,29 @@ def test_conv3x3_forward_and_gradients(un, N, H, W, c0, c1, cout):
     assert _rel(dw, wr.grad.permute(0, 2, 3, 1)) < 1e-4
 
 
+@pytest.mark.parametrize("N,H,W,c0,c1,cout", [(2, 16, 16, 8, 0, 32), (1, 9, 13, 16, 16, 8),
+                                              (2, 32, 32, 64, 64, 128), (3, 64, 64, 32, 0, 32)])
+def test_conv3x3_affine_relu_inference(un, N, H, W, c0, c1, cout):
+    """The fused inference layer against a float32 CPU conv, affine and ReLU."""
+    _say(f"case conv3x3 affine relu {N, H, W, c0, c1, cout}")
+    g = torch.Generator().manual_seed(N * 7 + H + cout)
+    x0 = _bf((N, H, W, c0), g)
+    x1 = _bf((N, H, W, c1), g) if c1 else None
+    w = _bf((cout, 3, 3, c0 + c1), g, 0.1)
+    scale = torch.rand(cout, generator=g) + 0.5
+    shift = torch.randn(cout, generator=g) * 0.3
+    x = x0 if x1 is None else torch.cat([x0, x1], dim=3)
+    ref = F.conv2d(x.float().permute(0, 3, 1, 2), w.float().permute(0, 3, 1, 2), padding=1)
+    ref = torch.relu(ref * scale.view(1, -1, 1, 1) + shift.view(1, -1, 1, 1)).permute(0, 2, 3, 1)
+    x0c, wc, sc, shc = x0.cuda(), w.cuda(), scale.cuda(), shift.cuda()
+    x1c = x1.cuda() if x1 is not None else None
+    y = torch.empty((N, H, W, cout), dtype=torch.bfloat16, device="cuda")
+    un._call("sil_unet_conv3x3_affine_relu", un._p(x0c), c0, un._p(x1c), c1, un._p(wc),
+             un._p(sc), un._p(shc), un._p(y), N, H, W, cout, un._s())
+    torch.cuda.synchronize()
+    assert _rel(y, ref) < 5e-3
+
+
 @pytest.mark.parametrize("N,H,W,cin,cout", [(2, 8, 8, 16, 8), (1, 5, 7, 64, 32), (2, 16, 16, 256, 128)])
 def test_upconv_forward_and_gradients(un, N, H, W, cin, cout):
     _say(f"case upconv {N, H, W, cin, cout}")
