@@ -137,16 +137,28 @@ def accuracy(a: torch.Tensor, b: torch.Tensor) -> float:
 
 
 def evaluate(model: unet.UNet, scenes: List[Scene]) -> dict:
+    """Pixel accuracies against the synthetic truth, the U-Net's disagreement
+    with the labeller, and how that disagreement splits: pixels where the U-Net
+    matches the truth (it corrects the labeller), where the labeller does, and
+    where neither does."""
     acc_u, acc_l, acc_0, dis = [], [], [], []
+    n_dis = n_u = n_l = 0
     for sc in scenes:
         pred = predict_scene(model, sc.scene)
         acc_u.append(accuracy(pred, sc.truth))
         acc_l.append(accuracy(sc.labels, sc.truth))
         acc_0.append(accuracy(sc.labels0, sc.truth))
         dis.append(1.0 - accuracy(pred, sc.labels))
+        d = pred != sc.labels
+        n_dis += int(d.sum().item())
+        n_u += int((d & (pred == sc.truth)).sum().item())
+        n_l += int((d & (sc.labels == sc.truth)).sum().item())
+    n = max(n_dis, 1)
     return {"unet_vs_truth": float(np.mean(acc_u)), "labeller_vs_truth": float(np.mean(acc_l)),
             "thresholds_only_vs_truth": float(np.mean(acc_0)),
-            "unet_labeller_disagreement": float(np.mean(dis))}
+            "unet_labeller_disagreement": float(np.mean(dis)),
+            "disagreement_unet_right": n_u / n, "disagreement_labeller_right": n_l / n,
+            "disagreement_neither_right": (n_dis - n_u - n_l) / n}
 
 
 @torch.no_grad()
