@@ -282,6 +282,196 @@ __global__ __launch_bounds__(kGT) void k_gemm_nt(GemmNT g) {
   }
 }
 
+// ---- 3x3 convolution with the input tile staged in LDS --------------------------
+//
+// Implicit GEMM over an output tile of 8 x 32 pixels of one image (M = 256) and
+// BN output channels.  For each 32-channel chunk of the input, the 10 x 34
+// pixel input tile (one-pixel halo, zero outside the image) and the chunk's
+// weights for all 9 taps are staged in LDS once; the 9 taps then read their
+// shifted A operands straight from the staged tile, so every input value
+// leaves L2 once per tile instead of once per tap.  Wave w owns output rows
+// 2w, 2w+1 (four 16-pixel row blocks).  The next chunk's loads (or the next
+// tile's first chunk) are in flight during the current chunk's MFMAs.  Requires c0 % 32 == 0, c1 % 32 == 0 and
+// N % BN == 0; epilogues as k_gemm_nt (E_STORE with BN sums, E_SPLIT,
+// E_AFFRELU).
+constexpr int kCTH = 8, kCTW = 32;               // output tile rows, columns
+constexpr int kCIH = kCTH + 2, kCIW = kCTW + 2;  // staged input tile
+constexpr int kCPix = kCIH * kCIW;               // 340 staged pixels
+
+template <int EM, int BN>
+__global__ __launch_bounds__(kGT) void k_conv3_lds(GemmNT g) {
+  constexpr int NJ = BN / 16;
+  constexpr int IN_CH = kCPix * 4;               // 16-byte chunks of the input tile
+  constexpr int IN_R = (IN_CH + kGT - 1) / kGT;
+  constexpr int W_CH = 9 * BN * 4;               // 16-byte chunks of the weights
+  constexpr int W_R = (W_CH + kGT - 1) / kGT;
+  __shared__ u16 Si[kCIH][kCIW][kLdsRow];
+  __shared__ u16 Sw[9][BN][kLdsRow];
+  __shared__ float red[4][2][BN];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int32_t n0 = blockIdx.y * BN;
+  const int32_t ct = g.c0 + g.c1;
+  const int32_t nchunk = ct / kBK;
+  const int32_t ntx = (g.W + kCTW - 1) / kCTW, nty = (g.H + kCTH - 1) / kCTH;
+  const int32_t ntiles = g.M / (g.H * g.W) * nty * ntx;
+
+  float s1[NJ], s2[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) s1[j] = s2[j] = 0.f;
+
+  // The block's work is a sequence of (tile, chunk) items: tiles blockIdx.x,
+  // blockIdx.x + gridDim.x, ..., each with nchunk input chunks.  The loads of
+  // the next item (possibly the next tile's first chunk) are issued before
+  // the current item's MFMAs.
+  uint4 ri[IN_R], rw[W_R];
+  // with a single chunk the weights are the same for every tile: staged once
+  const bool w_once = nchunk == 1;
+  auto gload = [&](int32_t tile, int32_t cc, bool with_w) {
+    const int32_t img = tile / (nty * ntx), rem = tile - img * nty * ntx;
+    const int32_t oy0 = (rem / ntx) * kCTH, ox0 = (rem % ntx) * kCTW;
+    const bool first = cc < g.c0;
+    const u16* src = first ? g.a0 : g.a1;
+    const int32_t ld = first ? g.c0 : g.c1, off = first ? cc : cc - g.c0;
+#pragma unroll
+    for (int r = 0; r < IN_R; ++r) {
+      const int q = tid + kGT * r;
+      ri[r] = make_uint4(0, 0, 0, 0);
+      if (q < IN_CH) {
+        const int p = q >> 2, sub = q & 3;
+        const int32_t y = oy0 - 1 + p / kCIW, x = ox0 - 1 + p % kCIW;
+        if ((uint32_t)y < (uint32_t)g.H && (uint32_t)x < (uint32_t)g.W)
+          ri[r] = *(const uint4*)(src + (((int64_t)img * g.H + y) * g.W + x) * ld + off +
+                                  8 * sub);
+      }
+    }
+    if (!with_w) return;
+#pragma unroll
+    for (int r = 0; r < W_R; ++r) {
+      const int q = tid + kGT * r;
+      rw[r] = make_uint4(0, 0, 0, 0);
+      if (q < W_CH) {
+        const int sub = q & 3, nt = q >> 2, tap = nt / BN, n = nt - tap * BN;
+        rw[r] = *(const uint4*)(g.b + ((int64_t)(n0 + n) * 9 + tap) * ct + cc + 8 * sub);
+      }
+    }
+  };
+  auto lstore = [&](bool with_w) {
+#pragma unroll
+    for (int r = 0; r < IN_R; ++r) {
+      const int q = tid + kGT * r;
+      if (q < IN_CH) {
+        const int p = q >> 2;
+        *(uint4*)&Si[p / kCIW][p % kCIW][8 * (q & 3)] = ri[r];
+      }
+    }
+    if (!with_w) return;
+#pragma unroll
+    for (int r = 0; r < W_R; ++r) {
+      const int q = tid + kGT * r;
+      if (q < W_CH) {
+        const int nt = q >> 2, tap = nt / BN;
+        *(uint4*)&Sw[tap][nt - tap * BN][8 * (q & 3)] = rw[r];
+      }
+    }
+  };
+
+  if (blockIdx.x < ntiles) gload(blockIdx.x, 0, true);
+  for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int32_t img = t / (nty * ntx), rem = t - img * nty * ntx;
+    const int32_t oy0 = (rem / ntx) * kCTH, ox0 = (rem % ntx) * kCTW;
+
+    f32x4 acc[4][NJ];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int32_t c = 0; c < nchunk; ++c) {
+      const bool first_item = t == (int32_t)blockIdx.x && c == 0;
+      __syncthreads();  // the previous item's LDS reads are done
+      lstore(!w_once || first_item);
+      __syncthreads();
+      if (c + 1 < nchunk)
+        gload(t, (c + 1) * kBK, true);
+      else if (t + gridDim.x < ntiles)
+        gload(t + gridDim.x, 0, !w_once);
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) {
+        const int dy = tap / 3, dx = tap % 3;
+        bf16x8 a[4], b[NJ];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          a[i] = __builtin_bit_cast(
+              bf16x8, *(const uint4*)&Si[2 * wave + (i >> 1) + dy][16 * (i & 1) + (lane & 15) + dx]
+                                        [8 * (lane >> 4)]);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+          b[j] = __builtin_bit_cast(bf16x8,
+                                    *(const uint4*)&Sw[tap][16 * j + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < NJ; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+    }
+
+    // epilogue: acc[i][j][t] is output pixel (oy0 + 2*wave + i/2, ox0 + 16*(i%2) +
+    // 4*(lane/16) + t), channel n0 + 16j + lane%16
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int32_t col = n0 + 16 * j + (lane & 15);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int32_t oy = oy0 + 2 * wave + (i >> 1);
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) {
+          const int32_t ox = ox0 + 16 * (i & 1) + 4 * (lane >> 4) + tt;
+          if (oy >= g.H || ox >= g.W) continue;
+          const int64_t row = ((int64_t)img * g.H + oy) * g.W + ox;
+          const float v = acc[i][j][tt];
+          if constexpr (EM == E_STORE) {
+            g.y0[row * g.N + col] = f2bf(v);
+            s1[j] += v;
+            s2[j] += v * v;
+          } else if constexpr (EM == E_AFFRELU) {
+            const float z = v * g.scale[col] + g.shift[col];
+            g.y0[row * g.N + col] = f2bf(z > 0.f ? z : 0.f);
+          } else {
+            if (col < g.split)
+              g.y0[row * g.split + col] = f2bf(v);
+            else
+              g.y1[row * (g.N - g.split) + (col - g.split)] = f2bf(v);
+          }
+        }
+      }
+    }
+  }
+
+  if constexpr (EM == E_STORE) {
+    if (g.stats) {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        s1[j] += __shfl_xor(s1[j], 16);
+        s1[j] += __shfl_xor(s1[j], 32);
+        s2[j] += __shfl_xor(s2[j], 16);
+        s2[j] += __shfl_xor(s2[j], 32);
+        if (lane < 16) {
+          red[wave][0][16 * j + lane] = s1[j];
+          red[wave][1][16 * j + lane] = s2[j];
+        }
+      }
+      __syncthreads();
+      if (tid < BN) {
+        const float t1 = red[0][0][tid] + red[1][0][tid] + red[2][0][tid] + red[3][0][tid];
+        const float t2 = red[0][1][tid] + red[1][1][tid] + red[2][1][tid] + red[3][1][tid];
+        atomicAdd(&g.stats[n0 + tid], t1);
+        atomicAdd(&g.stats[g.N + n0 + tid], t2);
+      }
+    }
+  }
+}
+
 // ---- weight gradients ----------------------------------------------------------
 
 enum TMode : int { T_PLAIN = 0, T_IM2COL = 1, T_UPGATHER = 2 };
@@ -1014,6 +1204,23 @@ int launch_nt(const GemmNT& g, hipStream_t st) {
   return done();
 }
 
+// 3x3 convolutions whose channel counts allow it go through k_conv3_lds.
+bool conv_lds_ok(const GemmNT& g) { return g.c0 % kBK == 0 && g.c1 % kBK == 0 && g.N % 32 == 0; }
+
+template <int EM>
+int launch_conv_lds(const GemmNT& g, hipStream_t st) {
+  (void)hipGetLastError();
+  const int32_t ntiles =
+      g.M / (g.H * g.W) * ((g.H + kCTH - 1) / kCTH) * ((g.W + kCTW - 1) / kCTW);
+  // 32-channel output tiles: wider ones would need more registers than two
+  // blocks per CU leave
+  auto kern = k_conv3_lds<EM, 32>;
+  const int gy = g.N / 32;
+  const int cap = std::max(1, resident_blocks((const void*)kern) / gy);
+  hipLaunchKernelGGL(kern, dim3(std::min(ntiles, cap), gy), dim3(kGT), 0, st, g);
+  return done();
+}
+
 // Weight-gradient tile (32*MI x 32*NJ): the widest N tile that divides N
 // (192, 128, 96, 64), else 96 for N <= 96, else 32.
 template <int AM, int BMD>
@@ -1074,6 +1281,7 @@ int sil_unet_conv3x3(const void* x0, int32_t c0, const void* x1, int32_t c1, con
   g.b = (const u16*)w;
   g.y0 = (u16*)y;
   g.stats = stats;
+  if (conv_lds_ok(g)) return launch_conv_lds<E_STORE>(g, (hipStream_t)stream);
   if ((c0 + c1) % kBK == 0) return launch_nt<A_IM2COL32, E_STORE>(g, (hipStream_t)stream);
   return launch_nt<A_IM2COL, E_STORE>(g, (hipStream_t)stream);
 }
@@ -1098,6 +1306,7 @@ int sil_unet_conv3x3_affine_relu(const void* x0, int32_t c0, const void* x1, int
   g.y0 = (u16*)y;
   g.scale = scale;
   g.shift = shift;
+  if (conv_lds_ok(g)) return launch_conv_lds<E_AFFRELU>(g, (hipStream_t)stream);
   if ((c0 + c1) % kBK == 0) return launch_nt<A_IM2COL32, E_AFFRELU>(g, (hipStream_t)stream);
   return launch_nt<A_IM2COL, E_AFFRELU>(g, (hipStream_t)stream);
 }
@@ -1120,6 +1329,8 @@ int sil_unet_conv3x3_dgrad(const void* dy, int32_t cout, const void* wt, void* d
   g.y1 = (u16*)dx1;
   g.split = c1 > 0 ? c0 : c0 + c1;
   hipStream_t st = (hipStream_t)stream;
+  if (conv_lds_ok(g))
+    return c1 > 0 ? launch_conv_lds<E_SPLIT>(g, st) : launch_conv_lds<E_STORE>(g, st);
   if (cout % kBK == 0)
     return c1 > 0 ? launch_nt<A_IM2COL32, E_SPLIT>(g, st) : launch_nt<A_IM2COL32, E_STORE>(g, st);
   return c1 > 0 ? launch_nt<A_IM2COL, E_SPLIT>(g, st) : launch_nt<A_IM2COL, E_STORE>(g, st);
