@@ -490,6 +490,154 @@ struct GemmTN {
   float* c;
 };
 
+// ---- 3x3 weight gradient with the input tile staged in LDS ------------------------
+//
+// dw[n][tap][ci] += sum_p dy[p][n] * x[p + shift(tap)][ci] over 8 x 32-pixel
+// tiles.  A block owns 32 output channels (n0) and a 32-channel input chunk (cc)
+// and walks pixel tiles blockIdx.x, blockIdx.x + gridDim.x, ...  Per tile, dy^T
+// (32 channels x 256 pixels) and x^T of the 10 x 34 halo tile are staged in
+// LDS, x^T in three copies shifted by 0, 1 and 2 columns so that every tap's
+// 8-pixel MFMA operands stay 16-byte aligned; the K steps are the tile's 8 rows
+// of 32 pixels.  The 36 output blocks of 16 x 16 (9 taps x 2 x 2) are spread
+// 9 per wave.  Staging stores pixel pairs as 4-byte words (2-byte stores for
+// the odd-shifted copy).  The next tile's loads are in flight during the
+// current tile's MFMAs; partial sums reach dw with one fp32 atomic per element
+// per block.  Requires cout, c0 and c1 divisible by 32.
+constexpr int kXRow = kCIH * kCTW + 8;  // u16 per staged x^T channel row (padded)
+constexpr int kARow = kCTH * kCTW + 8;  // u16 per staged dy^T channel row (padded)
+
+__global__ __launch_bounds__(kGT) void k_wgrad3_lds(GemmTN g) {
+  constexpr int A_SLOTS = (kCTH * kCTW / 2) * 4;   // pixel pairs x 4 channel groups = 512
+  constexpr int A_R = A_SLOTS / kGT;               // 2
+  constexpr int X_SLOTS = kCIH * (kCIW / 2) * 4;   // 10 rows x 17 pairs x 4 groups = 680
+  constexpr int X_R = (X_SLOTS + kGT - 1) / kGT;   // 3
+  __shared__ u16 Sa[32][kARow];
+  __shared__ u16 Sx[3][32][kXRow];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int32_t ct = g.c0 + g.c1;
+  const int32_t nblk_ci = ct / 32;
+  const int32_t n0 = (blockIdx.y / nblk_ci) * 32, cc = (blockIdx.y % nblk_ci) * 32;
+  const int32_t cout = g.M;
+  const int32_t ntx = (g.W + kCTW - 1) / kCTW, nty = (g.H + kCTH - 1) / kCTH;
+  const int32_t ntiles = (int32_t)(g.P / ((int64_t)g.H * g.W)) * nty * ntx;
+  const bool first = cc < g.c0;
+  const u16* xsrc = first ? g.b0 : g.b1;
+  const int32_t xld = first ? g.c0 : g.c1, xoff = first ? cc : cc - g.c0;
+
+  uint4 ra[A_R][2], rx[X_R][2];
+  auto gload = [&](int32_t tile) {
+    const int32_t img = tile / (nty * ntx), rem = tile - img * nty * ntx;
+    const int32_t oy0 = (rem / ntx) * kCTH, ox0 = (rem % ntx) * kCTW;
+#pragma unroll
+    for (int r = 0; r < A_R; ++r) {
+      const int q = tid + kGT * r;  // pair (q >> 2) of the tile, channel group q & 3
+      const int pr = q >> 2, grp = q & 3;
+      const int32_t y = oy0 + pr / (kCTW / 2), x = ox0 + 2 * (pr % (kCTW / 2));
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        ra[r][e] = make_uint4(0, 0, 0, 0);
+        if (y < g.H && x + e < g.W)
+          ra[r][e] = *(const uint4*)(g.a + (((int64_t)img * g.H + y) * g.W + x + e) * cout + n0 +
+                                     8 * grp);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < X_R; ++r) {
+      const int q = tid + kGT * r;
+      const int pr = q >> 2, grp = q & 3;
+      const int32_t y = oy0 - 1 + pr / (kCIW / 2), x = ox0 - 1 + 2 * (pr % (kCIW / 2));
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        rx[r][e] = make_uint4(0, 0, 0, 0);
+        if (q < X_SLOTS && (uint32_t)y < (uint32_t)g.H && (uint32_t)(x + e) < (uint32_t)g.W)
+          rx[r][e] = *(const uint4*)(xsrc + (((int64_t)img * g.H + y) * g.W + x + e) * xld + xoff +
+                                     8 * grp);
+      }
+    }
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int r = 0; r < A_R; ++r) {
+      const int q = tid + kGT * r;
+      const int pr = q >> 2, grp = q & 3;
+      const int col = 2 * pr;  // tile pixel index (row-major, 32 per row)
+      const uint32_t w0[4] = {ra[r][0].x, ra[r][0].y, ra[r][0].z, ra[r][0].w};
+      const uint32_t w1[4] = {ra[r][1].x, ra[r][1].y, ra[r][1].z, ra[r][1].w};
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        *(uint32_t*)&Sa[8 * grp + 2 * t][col] = (w0[t] & 0xffffu) | (w1[t] << 16);
+        *(uint32_t*)&Sa[8 * grp + 2 * t + 1][col] = (w0[t] >> 16) | (w1[t] & 0xffff0000u);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < X_R; ++r) {
+      const int q = tid + kGT * r;
+      if (q >= X_SLOTS) continue;
+      const int pr = q >> 2, grp = q & 3;
+      const int hr = pr / (kCIW / 2), hp = pr % (kCIW / 2);  // halo row, pair (cols 2hp, 2hp+1)
+      const uint32_t w0[4] = {rx[r][0].x, rx[r][0].y, rx[r][0].z, rx[r][0].w};
+      const uint32_t w1[4] = {rx[r][1].x, rx[r][1].y, rx[r][1].z, rx[r][1].w};
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const uint32_t lo = (w0[t] & 0xffffu) | (w1[t] << 16);          // channel 2t
+        const uint32_t hi = (w0[t] >> 16) | (w1[t] & 0xffff0000u);     // channel 2t+1
+        const int ch0 = 8 * grp + 2 * t;
+        // copy d holds halo column c + d at column c
+        if (hp <= 15) {
+          *(uint32_t*)&Sx[0][ch0][hr * kCTW + 2 * hp] = lo;
+          *(uint32_t*)&Sx[0][ch0 + 1][hr * kCTW + 2 * hp] = hi;
+        }
+        if (hp >= 1) {
+          *(uint32_t*)&Sx[2][ch0][hr * kCTW + 2 * hp - 2] = lo;
+          *(uint32_t*)&Sx[2][ch0 + 1][hr * kCTW + 2 * hp - 2] = hi;
+          Sx[1][ch0][hr * kCTW + 2 * hp - 1] = (u16)(lo & 0xffffu);
+          Sx[1][ch0 + 1][hr * kCTW + 2 * hp - 1] = (u16)(hi & 0xffffu);
+        }
+        if (hp <= 15) {
+          Sx[1][ch0][hr * kCTW + 2 * hp] = (u16)(lo >> 16);
+          Sx[1][ch0 + 1][hr * kCTW + 2 * hp] = (u16)(hi >> 16);
+        }
+      }
+    }
+  };
+
+  // this wave's output blocks: b = wave + 4k, b = tap*4 + mi*2 + nj
+  f32x4 acc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  if (blockIdx.x < ntiles) gload(blockIdx.x);
+  for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    __syncthreads();  // the previous tile's LDS reads are done
+    lstore();
+    __syncthreads();
+    if (t + gridDim.x < ntiles) gload(t + gridDim.x);
+#pragma unroll
+    for (int r = 0; r < kCTH; ++r) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const int b = wave + 4 * k, tap = b >> 2, mi = (b >> 1) & 1, nj = b & 1;
+        const int dy = tap / 3, dx = tap % 3;
+        const bf16x8 av = __builtin_bit_cast(
+            bf16x8, *(const uint4*)&Sa[16 * mi + (lane & 15)][kCTW * r + 8 * (lane >> 4)]);
+        const bf16x8 bv = __builtin_bit_cast(
+            bf16x8, *(const uint4*)&Sx[dx][16 * nj + (lane & 15)][kCTW * (r + dy) + 8 * (lane >> 4)]);
+        acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[k], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const int b = wave + 4 * k, tap = b >> 2, mi = (b >> 1) & 1, nj = b & 1;
+    const int32_t ci = cc + 16 * nj + (lane & 15);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int32_t n = n0 + 16 * mi + 4 * (lane >> 4) + e;
+      atomicAdd(&g.c[((int64_t)n * 9 + tap) * ct + ci], acc[k][e]);
+    }
+  }
+}
+
 // Pixel coordinates of a running pixel index, advanced without divisions.
 struct Pix {
   int32_t img, h, w;
@@ -1353,6 +1501,14 @@ int sil_unet_conv3x3_wgrad(const void* dy, int32_t cout, const void* x0, int32_t
   g.c0 = c0;
   g.c1 = c1;
   g.c = dw;
+  if (cout % 32 == 0 && c0 % 32 == 0 && c1 % 32 == 0) {
+    (void)hipGetLastError();
+    const int32_t ntiles = N * ((H + kCTH - 1) / kCTH) * ((W + kCTW - 1) / kCTW);
+    const int gy = (cout / 32) * ((c0 + c1) / 32);
+    const int gx = std::min(ntiles, std::max(1, resident_blocks((const void*)k_wgrad3_lds) / gy));
+    hipLaunchKernelGGL(k_wgrad3_lds, dim3(gx, gy), dim3(kGT), 0, (hipStream_t)stream, g);
+    return done();
+  }
   return launch_tn<T_PLAIN, T_IM2COL>(g, (hipStream_t)stream);
 }
 
