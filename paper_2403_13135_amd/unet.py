@@ -86,7 +86,44 @@ def _bf16(w: torch.Tensor) -> torch.Tensor:
     return out
 
 
-def _zeros(shape, device):
+class _ZeroPool:
+    """Zeroed fp32 scratch for one training step: the batch-norm sums and the
+    gradient accumulators of a step are slices of one buffer cleared by a single
+    fill at the start of the step, instead of one fill launch per tensor.  A
+    step that needs more than the pool holds gets fresh zeroed tensors for the
+    rest, and the pool grows to that size at the next step."""
+
+    def __init__(self):
+        self.buf = None
+        self.used = 0
+        self.need = 0
+        self.active = False
+
+    def begin_step(self, device):
+        self.need = max(self.need, self.used)
+        if self.buf is None or self.buf.device != device or self.buf.numel() < self.need:
+            self.buf = torch.empty((max(self.need, 1 << 16),), dtype=torch.float32, device=device)
+        n = max(self.need, 1)
+        _call("sil_unet_fill_f32", _p(self.buf), n, ctypes.c_float(0.0), _s())
+        self.used = 0
+        self.active = True
+
+    def take(self, shape, device):
+        n = 1
+        for d in shape:
+            n *= int(d)
+        start = (self.used + 63) // 64 * 64  # 256-byte aligned slices
+        self.used = start + n
+        if not self.active or self.buf.device != device or self.used > self.buf.numel() \
+                or self.used > max(self.need, 1):
+            return None
+        return self.buf[start:start + n].view(shape)
+
+
+def _zeros(shape, device, pool: "_ZeroPool" = None):
+    t = pool.take(shape, device) if pool is not None and pool.active else None
+    if t is not None:
+        return t
     t = torch.empty(shape, dtype=torch.float32, device=device)
     _call("sil_unet_fill_f32", _p(t), t.numel(), ctypes.c_float(0.0), _s())
     return t
@@ -96,14 +133,15 @@ class Conv3x3BNReLU(torch.autograd.Function):
     """relu(batchnorm(conv3x3(concat(x0, x1)))) with batch statistics."""
 
     @staticmethod
-    def forward(ctx, x0, x1, w, gamma, beta, mr=None):
+    def forward(ctx, x0, x1, w, gamma, beta, mr=None, pool=None):
         """mr (optional [2, cout] fp32) receives the batch (mean, rstd)."""
         N, H, W, c0 = x0.shape
         c1 = 0 if x1 is None else x1.shape[3]
         cout = w.shape[0]
         wb = _bf16(w)
         z = torch.empty((N, H, W, cout), dtype=torch.bfloat16, device=x0.device)
-        stats = _zeros((2, cout), x0.device)
+        ctx.pool = pool
+        stats = _zeros((2, cout), x0.device, pool)
         _call("sil_unet_conv3x3", _p(x0), c0, _p(x1), c1, _p(wb), _p(z), _p(stats), N, H, W,
               cout, _s())
         out = torch.empty_like(z)
@@ -126,12 +164,12 @@ class Conv3x3BNReLU(torch.autograd.Function):
         cout = wb.shape[0]
         P = N * H * W
         dz = torch.empty_like(z)
-        dgamma = _zeros((cout,), z.device)
-        dbeta = _zeros((cout,), z.device)
+        dgamma = _zeros((cout,), z.device, ctx.pool)
+        dbeta = _zeros((cout,), z.device, ctx.pool)
         red = torch.empty((2, cout), dtype=torch.float32, device=z.device)
         _call("sil_unet_bn_relu_bwd", _p(dout), _p(z), _p(mr), _p(gamma), _p(beta), _p(dz),
               _p(dgamma), _p(dbeta), _p(red), P, cout, _s())
-        dw = _zeros(wb.shape, z.device)
+        dw = _zeros(wb.shape, z.device, ctx.pool)
         _call("sil_unet_conv3x3_wgrad", _p(dz), cout, _p(x0), c0, _p(x1), c1, _p(dw), N, H, W,
               _s())
         dx0 = dx1 = None
@@ -142,7 +180,7 @@ class Conv3x3BNReLU(torch.autograd.Function):
             dx1 = torch.empty_like(x1) if x1 is not None else None
             _call("sil_unet_conv3x3_dgrad", _p(dz), cout, _p(wt), _p(dx0), c0, _p(dx1), c1, N, H,
                   W, _s())
-        return dx0, dx1, dw, dgamma, dbeta, None
+        return dx0, dx1, dw, dgamma, dbeta, None, None
 
 
 class MaxPool2(torch.autograd.Function):
@@ -169,7 +207,8 @@ class UpConv2(torch.autograd.Function):
     """2x2 transposed convolution, stride 2, with bias; w: [2, 2, cout, cin]."""
 
     @staticmethod
-    def forward(ctx, x, w, b):
+    def forward(ctx, x, w, b, pool=None):
+        ctx.pool = pool
         N, H, W, cin = x.shape
         cout = w.shape[2]
         wb = _bf16(w)
@@ -184,26 +223,27 @@ class UpConv2(torch.autograd.Function):
         dy = dy.contiguous()
         N, H, W, cin = x.shape
         cout = wb.shape[2]
-        dw = _zeros(wb.shape, x.device)
-        db = _zeros((cout,), x.device)
+        dw = _zeros(wb.shape, x.device, ctx.pool)
+        db = _zeros((cout,), x.device, ctx.pool)
         _call("sil_unet_upconv_wgrad", _p(x), _p(dy), _p(dw), _p(db), N, H, W, cin, cout, _s())
         wt = torch.empty((cin, 2, 2, cout), dtype=torch.bfloat16, device=x.device)
         _call("sil_unet_up_t", _p(wb), _p(wt), cin, cout, _s())
         dx = torch.empty_like(x)
         _call("sil_unet_upconv_dgrad", _p(dy), _p(wt), _p(dx), N, H, W, cin, cout, _s())
-        return dx, dw, db
+        return dx, dw, db, None
 
 
 class HeadXent(torch.autograd.Function):
     """Mean softmax cross-entropy of the 1x1 head; returns (loss, logits)."""
 
     @staticmethod
-    def forward(ctx, x, w, b, labels):
+    def forward(ctx, x, w, b, labels, pool=None):
         N, H, W, C = x.shape
         P = N * H * W
         logits = torch.empty((P, 3), dtype=torch.float32, device=x.device)
         _call("sil_unet_head", _p(x), _p(w), _p(b), _p(logits), P, C, _s())
-        loss = _zeros((1,), x.device)
+        ctx.pool = pool
+        loss = _zeros((1,), x.device, pool)
         dlogits = torch.empty_like(logits)
         _call("sil_unet_softmax_xent", _p(logits), _p(labels), _p(loss), _p(dlogits),
               ctypes.c_float(1.0 / P), P, _s())
@@ -219,10 +259,10 @@ class HeadXent(torch.autograd.Function):
         # dlogits already carries the 1/P of the mean; scale by the incoming grad
         dl = dlogits * dloss if float(dloss) != 1.0 else dlogits
         dx = torch.empty_like(x)
-        dw = _zeros((3, C), x.device)
-        db = _zeros((3,), x.device)
+        dw = _zeros((3, C), x.device, ctx.pool)
+        db = _zeros((3,), x.device, ctx.pool)
         _call("sil_unet_head_bwd", _p(x), _p(w), _p(dl), _p(dx), _p(dw), _p(db), P, C, _s())
-        return dx, dw, db, None
+        return dx, dw, db, None, None
 
 
 def layer_specs(widths: Sequence[int], in_ch: int = IN_CH):
@@ -266,6 +306,7 @@ class UNet:
                 P[name + ".w"] = torch.randn(cout, cin, generator=g) * math.sqrt(2.0 / cin)
                 P[name + ".b"] = torch.zeros(cout)
         self.params = {k: v.to(device).float().requires_grad_(True) for k, v in P.items()}
+        self.pool = _ZeroPool()  # this model's per-step zeroed scratch
         # running batch-norm statistics for inference, and the last batch's (mean, rstd)
         self.bn_names = [n for n, kind, _, _ in layer_specs(widths) if kind == "conv3"]
         self.running = {n: (torch.zeros(P[n + ".gamma"].numel(), device=device),
@@ -276,7 +317,13 @@ class UNet:
         self.momentum = 0.1
 
     def forward(self, x: torch.Tensor, labels: torch.Tensor):
-        """x: bf16 [N, H, W, 8]; labels: uint8 [N, H, W].  Returns (loss, logits)."""
+        """x: bf16 [N, H, W, 8]; labels: uint8 [N, H, W].  Returns (loss, logits).
+
+        Starts a training step: the step's zeroed scratch (batch-norm sums and
+        gradient accumulators) is taken from one pool cleared here, so the
+        gradients of the previous step must have been consumed (optimizer step
+        taken, zero_grad called) before the next forward."""
+        self.pool.begin_step(x.device)
         P = self.params
         skips = []
         h = x
@@ -284,7 +331,7 @@ class UNet:
 
         def cbr(h, skip, n):
             return Conv3x3BNReLU.apply(h, skip, P[n + ".w"], P[n + ".gamma"], P[n + ".beta"],
-                                       self.batch_mr[n])
+                                       self.batch_mr[n], self.pool)
 
         for i in range(L):
             name = f"enc{i}" if i < L - 1 else "mid"
@@ -293,9 +340,9 @@ class UNet:
                 skips.append(h)
                 h = MaxPool2.apply(h)
         for i in reversed(range(L - 1)):
-            up = UpConv2.apply(h, P[f"dec{i}.up.w"], P[f"dec{i}.up.b"])
+            up = UpConv2.apply(h, P[f"dec{i}.up.w"], P[f"dec{i}.up.b"], self.pool)
             h = cbr(cbr(up, skips[i], f"dec{i}.conv0"), None, f"dec{i}.conv1")
-        return HeadXent.apply(h, P["head.w"], P["head.b"], labels)
+        return HeadXent.apply(h, P["head.w"], P["head.b"], labels, self.pool)
 
     @torch.no_grad()
     def update_running_stats(self):
@@ -347,7 +394,8 @@ class UNet:
         return logits
 
     def predict(self, x: torch.Tensor) -> torch.Tensor:
-        """Class map [N, H, W] (uint8).  Uses batch statistics of `x`, as in training."""
+        """Class map [N, H, W] (uint8).  Uses batch statistics of `x`, as in training
+        (a forward pass: it starts a step, see forward)."""
         N, H, W, _ = x.shape
         dummy = torch.zeros((N, H, W), dtype=torch.uint8, device=x.device)
         with torch.no_grad():
