@@ -252,8 +252,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the labelling path has no cross-GPU step "
-              "in this build (see DESIGN.md for how it shards); use --gpus 1.",
+        print("bench.py measures one GPU: labelling needs no cross-GPU step (a scene shards "
+              "by chip rows with a one-row halo, and requests shard with no communication), "
+              "and no multi-GPU path is built; use --gpus 1.",
               file=sys.stderr, flush=True)
         sys.exit(2)
 
