@@ -42,12 +42,8 @@ constexpr int kBK = 32;       // reduction step (one MFMA K)
 constexpr int kLdsRow = 40;   // u16 per LDS row: 32 + 8 padding (80 bytes)
 
 __device__ __forceinline__ float bf2f(u16 v) { return __uint_as_float((uint32_t)v << 16); }
-__device__ __forceinline__ u16 f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (u16)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
-  return (u16)(u >> 16);
-}
+// fp32 -> bf16, round to nearest even (gfx950's v_cvt_pk_bf16_f32)
+__device__ __forceinline__ u16 f2bf(float f) { return __builtin_bit_cast(u16, (__bf16)f); }
 
 // A_IM2COL32: the im2col of A_IM2COL when c0 + c1 is a multiple of 32, so a
 // 32-wide reduction step lies inside one tap: the tap and channel offset are
