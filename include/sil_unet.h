@@ -15,7 +15,9 @@
  *     accumulation; all other steps are plain HIP kernels.
  *   - Channel counts must be multiples of 8 (pad the 3-channel input to 8
  *     with zeros); batch-norm and head channel counts must divide 256.
- *     Violations: SIL_EINVAL.
+ *     Violations: SIL_EINVAL.  Tensors are read and written in 16-byte
+ *     chunks, so their base addresses must be 16-byte aligned (any device
+ *     allocation is).
  *   - Every call is asynchronous on `stream` (hipStream_t or NULL), allocates
  *     nothing and validates its sizes before enqueueing.  Outputs marked
  *     "accumulate" are ADDED to (zero them first, e.g. sil_unet_fill_f32).

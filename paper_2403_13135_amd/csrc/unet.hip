@@ -413,7 +413,10 @@ __global__ __launch_bounds__(kGT) void k_conv3_lds(GemmNT g) {
     }
 
     // epilogue: acc[i][j][t] is output pixel (oy0 + 2*wave + i/2, ox0 + 16*(i%2) +
-    // 4*(lane/16) + t), channel n0 + 16j + lane%16
+    // 4*(lane/16) + t), channel n0 + 16j + lane%16.  The bf16 tile goes through LDS
+    // (the staged input is no longer needed) so that global stores are 16 bytes.
+    u16* const So = &Si[0][0][0];  // [256 pixels][kLdsRow]
+    __syncthreads();                // every wave's MFMA reads of Si are done
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
       const int32_t col = n0 + 16 * j + (lane & 15);
@@ -423,23 +426,40 @@ __global__ __launch_bounds__(kGT) void k_conv3_lds(GemmNT g) {
 #pragma unroll
         for (int tt = 0; tt < 4; ++tt) {
           const int32_t ox = ox0 + 16 * (i & 1) + 4 * (lane >> 4) + tt;
-          if (oy >= g.H || ox >= g.W) continue;
-          const int64_t row = ((int64_t)img * g.H + oy) * g.W + ox;
+          const int pl = 32 * (2 * wave + (i >> 1)) + 16 * (i & 1) + 4 * (lane >> 4) + tt;
           const float v = acc[i][j][tt];
+          float o = v;
           if constexpr (EM == E_STORE) {
-            g.y0[row * g.N + col] = f2bf(v);
-            s1[j] += v;
-            s2[j] += v * v;
+            if (oy < g.H && ox < g.W) {
+              s1[j] += v;
+              s2[j] += v * v;
+            }
           } else if constexpr (EM == E_AFFRELU) {
             const float z = v * g.scale[col] + g.shift[col];
-            g.y0[row * g.N + col] = f2bf(z > 0.f ? z : 0.f);
-          } else {
-            if (col < g.split)
-              g.y0[row * g.split + col] = f2bf(v);
-            else
-              g.y1[row * (g.N - g.split) + (col - g.split)] = f2bf(v);
+            o = z > 0.f ? z : 0.f;
           }
+          So[pl * kLdsRow + 16 * j + (lane & 15)] = f2bf(o);
         }
+      }
+    }
+    __syncthreads();
+    // 256 pixels x BN channels as 16-byte chunks of 8 channels
+#pragma unroll
+    for (int r = 0; r < BN / 8; ++r) {
+      const int q = tid + kGT * r;
+      const int pl = q / (BN / 8), sub = q % (BN / 8);
+      const int32_t oy = oy0 + pl / kCTW, ox = ox0 + pl % kCTW;
+      if (oy >= g.H || ox >= g.W) continue;
+      const int64_t row = ((int64_t)img * g.H + oy) * g.W + ox;
+      const uint4 val = *(const uint4*)&So[pl * kLdsRow + 8 * sub];
+      const int32_t col = n0 + 8 * sub;
+      if constexpr (EM == E_SPLIT) {
+        if (col < g.split)
+          *(uint4*)(g.y0 + row * g.split + col) = val;
+        else
+          *(uint4*)(g.y1 + row * (g.N - g.split) + (col - g.split)) = val;
+      } else {
+        *(uint4*)(g.y0 + row * g.N + col) = val;
       }
     }
   }
