@@ -4,8 +4,9 @@
  * two 3x3 convolutions with ReLU per level, 2x2 max pooling with stride 2,
  * 2x2 up-convolutions that halve the channels, concatenation with the skip
  * map, a 1x1 convolution to the 3 classes; "U-Net Training": categorical
- * cross-entropy and the Adam optimizer).  This build adds batch
- * normalisation after each 3x3 convolution and uses "same" padding.
+ * cross-entropy and the Adam optimizer).  The network these kernels serve
+ * adds batch normalisation after each 3x3 convolution and uses "same"
+ * padding.
  *
  * Conventions:
  *   - Activations are bf16, NHWC, contiguous ([N][H][W][C]); a "pixel" is one

@@ -8,7 +8,7 @@ concatenation with the skip feature map and two 3x3 convolutions with ReLU,
 and a final 1x1 convolution to the 3 classes, trained with categorical
 cross-entropy (section III-C, "U-Net Training").
 
-This build's variant (its channel widths, batch normalisation, "same"
+The variant computed here (its channel widths, batch normalisation, "same"
 padding, so no cropping) is stated in ``CONFIG``; the GPU implementation in
 ``paper_2403_13135_amd/unet.py`` computes the same function with its own
 kernels.  Written with plain ``torch.nn.functional`` calls in float64, NCHW;
