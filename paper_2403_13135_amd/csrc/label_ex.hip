@@ -22,10 +22,10 @@
 //      multiplied comparisons (chips up to 2^27 pixels), the eta gate, rank-k
 //      truncation levels and the stretch, written as a 256-entry table
 //      median -> filtered value.
-//   C. k_ex_apply: 8 x 1024 tiles, four pixels per thread, every row's loads
-//      in flight first; per pixel the three 8-bit bands, V, the filtered Vc
-//      from the chip tables (staged in LDS), H and S, the masks, the filtered
-//      colour and per-patch mask counts (per-thread runs, wave-reduced when
+//   C. k_ex_apply: 8 x 1024 tiles, four pixels per thread, row by row; per
+//      pixel the three 8-bit bands, V, the filtered Vc from the chip tables
+//      (staged in LDS), H and S, the masks, the filtered colour and per-patch
+//      mask counts (per-thread runs, wave-reduced when
 //      the wave shares a patch, LDS counters per tile, one global atomic per
 //      nonzero counter and tile).
 // Divisions by small run-time divisors use a float estimate corrected by one
@@ -47,7 +47,8 @@ constexpr int kThreads = 256;     // threads per block of passes A and C
 constexpr int kTR = 16;           // pass A tile rows
 constexpr int kTW = 4 * kThreads; // tile columns: 4 per thread
 constexpr int kTRC = 8;           // pass C tile rows
-constexpr int kRB = 4;            // pass C rows per load batch
+constexpr int kRB = 1;            // pass C rows per load batch (1 measured fastest: batching
+                                  // more rows costs occupancy and SGPR spills)
 constexpr int kMaxTilePatches = 128;
 constexpr int kMaxTileChips = 16; // per-chip tables a pass C tile stages in LDS
 constexpr int64_t kMaxChipPixels = int64_t(1) << 27;
