@@ -448,3 +448,70 @@ def scatter_argmax(logits: torch.Tensor, origins: torch.Tensor, labels: torch.Te
     n, chip = logits.shape[0], logits.shape[1]
     _call("sil_unet_scatter_argmax", _p(logits.contiguous()), _p(origins.contiguous()), n, chip,
           _p(labels), H, W, labels.stride(0), _s())
+
+
+# ---- checkpoints -------------------------------------------------------------------
+
+def save_checkpoint(path: str, model: "UNet", opt: "Adam" = None, extra: Dict[str, int] = None):
+    """Write the model (fp32 master weights, running batch-norm statistics) and,
+    when given, the Adam state (moments and step count) to a safetensors file.
+    Integer metadata (e.g. the training step and the sampler seed) goes in
+    ``extra``.  The file's metadata records the widths and a SHA-256 over all
+    tensors, which load_checkpoint verifies."""
+    import hashlib
+    from safetensors.torch import save_file
+    tensors = {}
+    for k, v in model.params.items():
+        tensors["param." + k] = v.detach().contiguous().cpu()
+    for n, (rm, rv) in model.running.items():
+        tensors["running_mean." + n] = rm.detach().contiguous().cpu()
+        tensors["running_var." + n] = rv.detach().contiguous().cpu()
+    meta = {"widths": ",".join(str(w) for w in model.widths)}
+    if opt is not None:
+        for k in opt.m:
+            tensors["adam_m." + k] = opt.m[k].detach().contiguous().cpu()
+            tensors["adam_v." + k] = opt.v[k].detach().contiguous().cpu()
+        meta["adam_t"] = str(opt.t)
+        meta["adam_lr"] = repr(opt.lr)
+    for k, v in (extra or {}).items():
+        meta["extra." + k] = str(int(v))
+    h = hashlib.sha256()
+    for k in sorted(tensors):
+        h.update(k.encode())
+        h.update(tensors[k].numpy().tobytes())
+    meta["sha256"] = h.hexdigest()
+    save_file(tensors, path, metadata=meta)
+
+
+def load_checkpoint(path: str, device="cuda", lr: float = None):
+    """Read a file written by save_checkpoint: returns (model, opt or None,
+    extra).  Raises ValueError when the tensors do not match the recorded
+    SHA-256."""
+    import hashlib
+    from safetensors import safe_open
+    with safe_open(path, framework="pt") as f:
+        meta = f.metadata()
+        tensors = {k: f.get_tensor(k) for k in f.keys()}
+    h = hashlib.sha256()
+    for k in sorted(tensors):
+        h.update(k.encode())
+        h.update(tensors[k].numpy().tobytes())
+    if h.hexdigest() != meta.get("sha256"):
+        raise ValueError(f"{path}: checkpoint hash mismatch")
+    widths = tuple(int(w) for w in meta["widths"].split(","))
+    model = UNet(widths, device=device)
+    with torch.no_grad():
+        for k, v in model.params.items():
+            v.copy_(tensors["param." + k].to(device))
+        for n, (rm, rv) in model.running.items():
+            rm.copy_(tensors["running_mean." + n].to(device))
+            rv.copy_(tensors["running_var." + n].to(device))
+    opt = None
+    if "adam_t" in meta:
+        opt = Adam(model.params, lr=float(meta["adam_lr"]) if lr is None else lr)
+        for k in opt.m:
+            opt.m[k].copy_(tensors["adam_m." + k].to(device))
+            opt.v[k].copy_(tensors["adam_v." + k].to(device))
+        opt.t = int(meta["adam_t"])
+    extra = {k[len("extra."):]: int(v) for k, v in meta.items() if k.startswith("extra.")}
+    return model, opt, extra

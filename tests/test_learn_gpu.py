@@ -80,3 +80,35 @@ def test_fallback_to_the_labeller(mods, trained):
         model.params["head.b"].copy_(saved)
     assert all(r["fallback"] for r in bad)
     assert all(r["disagreement"] > 0.02 for r in bad)
+
+
+def test_checkpoint_round_trip(mods, trained, tmp_path):
+    """A trained model and its optimizer state survive save/load: identical
+    inference logits and Adam moments and step count; a corrupted file is
+    refused."""
+    learn, sil, unet = mods
+    model, _, test_sc = trained
+    opt = unet.Adam(model.params, lr=1e-3)
+    X, Y = learn.build_training_set(test_sc[:1])
+    for k in range(3):  # gives the optimizer a history
+        opt.zero_grad()
+        loss, _ = model.forward(X[4 * k:4 * k + 4].contiguous(), Y[4 * k:4 * k + 4].contiguous())
+        loss.backward()
+        opt.step()
+        model.update_running_stats()
+    torch.cuda.synchronize()
+    path = str(tmp_path / "unet.safetensors")
+    unet.save_checkpoint(path, model, opt, extra={"step": 3, "seed": 7})
+    m2, o2, extra = unet.load_checkpoint(path)
+    assert extra == {"step": 3, "seed": 7} and o2.t == opt.t
+    x = X[:2].contiguous()
+    assert torch.equal(model.infer_logits(x), m2.infer_logits(x))
+    for k in opt.m:
+        assert torch.equal(opt.m[k], o2.m[k]) and torch.equal(opt.v[k], o2.v[k])
+    # a corrupted file is refused
+    raw = bytearray(open(path, "rb").read())
+    raw[-5] ^= 0xFF
+    bad = str(tmp_path / "bad.safetensors")
+    open(bad, "wb").write(bytes(raw))
+    with pytest.raises(ValueError):
+        unet.load_checkpoint(bad)
