@@ -136,15 +136,44 @@ def accuracy(a: torch.Tensor, b: torch.Tensor) -> float:
     return (a == b).float().mean().item()
 
 
+def confusion(pred: torch.Tensor, truth: torch.Tensor, k: int = 3) -> np.ndarray:
+    """k x k pixel counts: rows the true class, columns the predicted class."""
+    idx = truth.reshape(-1).long() * k + pred.reshape(-1).long()
+    return torch.bincount(idx, minlength=k * k).reshape(k, k).cpu().numpy()
+
+
+def class_scores(cm: np.ndarray) -> dict:
+    """Per-class precision, recall and F1 from a confusion matrix (rows true,
+    columns predicted), and the column-normalised matrix (each predicted class's
+    column sums to 1), as the paper reports them."""
+    tp = np.diag(cm).astype(np.float64)
+    pred_tot = cm.sum(axis=0).astype(np.float64)
+    true_tot = cm.sum(axis=1).astype(np.float64)
+    prec = np.divide(tp, pred_tot, out=np.zeros_like(tp), where=pred_tot > 0)
+    rec = np.divide(tp, true_tot, out=np.zeros_like(tp), where=true_tot > 0)
+    f1 = np.divide(2 * prec * rec, prec + rec, out=np.zeros_like(tp), where=(prec + rec) > 0)
+    colnorm = np.divide(cm, pred_tot[None, :], out=np.zeros(cm.shape), where=pred_tot[None, :] > 0)
+    return {"precision": prec.tolist(), "recall": rec.tolist(), "f1": f1.tolist(),
+            "confusion_col_normalised": colnorm.round(4).tolist()}
+
+
 def evaluate(model: unet.UNet, scenes: List[Scene]) -> dict:
     """Pixel accuracies against the synthetic truth, the U-Net's disagreement
     with the labeller, and how that disagreement splits: pixels where the U-Net
     matches the truth (it corrects the labeller), where the labeller does, and
-    where neither does."""
+    where neither does.  Per class (0 water, 1 thin ice, 2 thick ice):
+    precision, recall, F1 and the column-normalised confusion matrix of each
+    of the U-Net, the labeller and the unfiltered thresholds against the
+    truth."""
     acc_u, acc_l, acc_0, dis = [], [], [], []
     n_dis = n_u = n_l = 0
+    cms = {"unet": np.zeros((3, 3), np.int64), "labeller": np.zeros((3, 3), np.int64),
+           "thresholds_only": np.zeros((3, 3), np.int64)}
     for sc in scenes:
         pred = predict_scene(model, sc.scene)
+        cms["unet"] += confusion(pred, sc.truth)
+        cms["labeller"] += confusion(sc.labels, sc.truth)
+        cms["thresholds_only"] += confusion(sc.labels0, sc.truth)
         acc_u.append(accuracy(pred, sc.truth))
         acc_l.append(accuracy(sc.labels, sc.truth))
         acc_0.append(accuracy(sc.labels0, sc.truth))
@@ -158,7 +187,8 @@ def evaluate(model: unet.UNet, scenes: List[Scene]) -> dict:
             "thresholds_only_vs_truth": float(np.mean(acc_0)),
             "unet_labeller_disagreement": float(np.mean(dis)),
             "disagreement_unet_right": n_u / n, "disagreement_labeller_right": n_l / n,
-            "disagreement_neither_right": (n_dis - n_u - n_l) / n}
+            "disagreement_neither_right": (n_dis - n_u - n_l) / n,
+            "per_class_vs_truth": {k: class_scores(v) for k, v in cms.items()}}
 
 
 @torch.no_grad()

@@ -183,3 +183,4 @@ def test_workspace_sizes():
     assert n >= 10980 * 10980 + 256 * 4 + 256
     m = sil.workspace_bytes(10980, 10980, sil.Params())
     assert m >= 10980 * 10980 + 43 * 43 * 256 * 5
+
