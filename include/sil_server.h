@@ -69,7 +69,7 @@ typedef struct sil_completion {
 } sil_completion;
 
 typedef struct sil_server_stats {
-  uint64_t submitted, admitted, completed, released;
+  uint64_t submitted, admitted, completed, released, cancelled;
   uint64_t launches, chips;
   uint64_t arena_used, arena_peak;
   int32_t queued, active, inflight, pad;
@@ -102,6 +102,19 @@ int sil_server_poll(sil_server* s, sil_completion* out, int32_t max, int32_t* n)
 /* Return a completed request's output space to the arena.  SIL_EINVAL if
  * `tag` is not a completed, unreleased request. */
 int sil_server_release(sil_server* s, uint64_t tag);
+
+/* Withdraw a request that is still queued (not yet admitted): it will never
+ * run or complete, and its tag may be reused.  SIL_EINVAL if `tag` is unknown;
+ * SIL_EUNSUPPORTED if it was already admitted (its chips may be on the GPU:
+ * wait for its completion and release it instead). */
+int sil_server_cancel(sil_server* s, uint64_t tag);
+
+/* Queue-wait timeout: withdraw, oldest first, the queued requests that have
+ * waited more than max_wait_ms since submission (at most `max` of them) and
+ * write their tags to tags[]; *n receives how many.  Admitted requests are
+ * never withdrawn.  SIL_EINVAL on NULL pointers or a negative wait. */
+int sil_server_expire(sil_server* s, double max_wait_ms, uint64_t* tags, int32_t max,
+                      int32_t* n);
 
 /* Block until every enqueued launch has completed (does not admit). */
 int sil_server_drain(sil_server* s);

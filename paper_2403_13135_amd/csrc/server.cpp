@@ -337,6 +337,39 @@ int sil_server_release(sil_server* s, uint64_t tag) {
   return SIL_OK;
 }
 
+int sil_server_cancel(sil_server* s, uint64_t tag) {
+  if (!s) return SIL_EINVAL;
+  auto it = s->reqs.find(tag);
+  if (it == s->reqs.end()) return SIL_EINVAL;
+  if (it->second.admitted) return SIL_EUNSUPPORTED;
+  for (auto q = s->queue.begin(); q != s->queue.end(); ++q)
+    if (*q == tag) {
+      s->queue.erase(q);
+      break;
+    }
+  s->reqs.erase(it);
+  ++s->st.cancelled;
+  return SIL_OK;
+}
+
+int sil_server_expire(sil_server* s, double max_wait_ms, uint64_t* tags, int32_t max,
+                      int32_t* n) {
+  if (!s || !n || max_wait_ms < 0 || (max > 0 && !tags)) return SIL_EINVAL;
+  const double now = s->now_ms();
+  int32_t k = 0;
+  // the queue is in submission order, so the requests that waited longest lead it
+  while (k < max && !s->queue.empty()) {
+    const uint64_t tag = s->queue.front();
+    if (now - s->reqs.at(tag).t_submit <= max_wait_ms) break;
+    s->queue.pop_front();
+    s->reqs.erase(tag);
+    ++s->st.cancelled;
+    tags[k++] = tag;
+  }
+  *n = k;
+  return SIL_OK;
+}
+
 int sil_server_drain(sil_server* s) {
   if (!s) return SIL_EINVAL;
   for (auto& L : s->inflight)

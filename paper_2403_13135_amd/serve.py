@@ -36,6 +36,7 @@ class _Completion(ctypes.Structure):
 class _Stats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("admitted", ctypes.c_uint64),
                 ("completed", ctypes.c_uint64), ("released", ctypes.c_uint64),
+                ("cancelled", ctypes.c_uint64),
                 ("launches", ctypes.c_uint64), ("chips", ctypes.c_uint64),
                 ("arena_used", ctypes.c_uint64), ("arena_peak", ctypes.c_uint64),
                 ("queued", ctypes.c_int32), ("active", ctypes.c_int32),
@@ -59,6 +60,9 @@ def _lib():
         L.sil_server_poll.argtypes = [vp, P(_Completion), ctypes.c_int32, P(ctypes.c_int32)]
         L.sil_server_release.argtypes = [vp, ctypes.c_uint64]
         L.sil_server_drain.argtypes = [vp]
+        L.sil_server_cancel.argtypes = [vp, ctypes.c_uint64]
+        L.sil_server_expire.argtypes = [vp, ctypes.c_double, P(ctypes.c_uint64), ctypes.c_int32,
+                                        P(ctypes.c_int32)]
         L.sil_server_get_stats.argtypes = [vp, P(_Stats)]
         L.sil_server_clock_ms.argtypes = [vp]
         L.sil_server_clock_ms.restype = ctypes.c_double
@@ -67,6 +71,7 @@ def _lib():
         L.sil_server_destroy.argtypes = [vp]
         for f in ("sil_server_create", "sil_server_submit", "sil_server_pump", "sil_server_poll",
                   "sil_server_release", "sil_server_drain", "sil_server_get_stats",
+                  "sil_server_cancel", "sil_server_expire",
                   "sil_server_run", "sil_server_destroy"):
             getattr(L, f).restype = ctypes.c_int
         _bound = True
@@ -176,6 +181,22 @@ class Server:
     def release(self, tag: int):
         _check(_lib().sil_server_release(self._h, int(tag)))
         self._scenes.pop(int(tag), None)
+
+    def cancel(self, tag: int):
+        """Withdraw a request that is still queued (raises if it was admitted)."""
+        _check(_lib().sil_server_cancel(self._h, int(tag)))
+        self._scenes.pop(int(tag), None)
+
+    def expire(self, max_wait_ms: float, max_n: int = 4096) -> List[int]:
+        """Withdraw queued requests that waited longer than max_wait_ms; their tags."""
+        buf = (ctypes.c_uint64 * max_n)()
+        n = ctypes.c_int32()
+        _check(_lib().sil_server_expire(self._h, float(max_wait_ms), buf, max_n,
+                                        ctypes.byref(n)))
+        tags = [int(buf[i]) for i in range(n.value)]
+        for t in tags:
+            self._scenes.pop(t, None)
+        return tags
 
     def drain(self):
         _check(_lib().sil_server_drain(self._h))

@@ -128,3 +128,45 @@ def test_server_argument_errors(env):
     assert [c.tag for c in got] == [2]
     srv.release(2)
     srv.close()
+
+
+def test_cancel_and_queue_timeout(env):
+    """Requests still queued behind a full arena can be withdrawn one by one or
+    by a queue-wait timeout; withdrawn requests never complete, admitted ones
+    cannot be withdrawn, and everything that does complete is still
+    bit-identical to its solo run."""
+    import time
+    serve, sil, p, pool, rng = env
+    # room for one 2048^2 request's outputs at a time: the rest queue
+    srv = serve.Server(p, arena_bytes=5 << 20, max_chips_per_launch=64, max_inflight=1)
+    big = pool[3]
+    for t in range(6):
+        srv.submit(big[0], tag=t)
+    srv.pump()
+    st = srv.stats()
+    assert st["admitted"] == 1 and st["queued"] == 5
+    with pytest.raises(sil.SilError) as e:
+        srv.cancel(0)  # admitted: its chips may be on the GPU
+    assert e.value.code == sil.EUNSUPPORTED
+    srv.cancel(2)
+    with pytest.raises(sil.SilError) as e:
+        srv.cancel(2)  # gone
+    assert e.value.code == sil.EINVAL
+    time.sleep(0.05)
+    srv.submit(big[0], tag=9)  # fresh: survives the timeout below
+    expired = srv.expire(max_wait_ms=20.0)
+    assert expired == [1, 3, 4, 5]
+    assert srv.stats()["cancelled"] == 5
+    done = []
+    t0 = time.time()
+    while len(done) < 2:
+        srv.pump()
+        for c in srv.poll():
+            assert _check(c, big)
+            srv.release(c.tag)
+            done.append(c.tag)
+        assert time.time() - t0 < 60, "server made no progress"
+    assert sorted(done) == [0, 9]
+    st = srv.stats()
+    assert st["queued"] == 0 and st["active"] == 0 and st["completed"] == 2
+    srv.close()
