@@ -42,13 +42,15 @@ def _rel(a, b):
 
 # Shapes reach every tile family: narrow (32-wide) and wide outputs, ragged
 # weight-gradient N tiles (9*cin = 72), N tiles of 96/192/128 with 32-, 64- and
-# 128-row M tiles, and a 256 x 256 batch whose M tiles outnumber the resident
-# blocks, so each block of the forward GEMM walks several tiles.
+# 128-row M tiles, a 256 x 256 batch whose tiles outnumber the resident blocks
+# (each block walks several tiles), and images that are not multiples of the
+# LDS kernels' 8 x 32 pixel tiles in either direction.
 @pytest.mark.parametrize("N,H,W,c0,c1,cout", [(2, 16, 16, 8, 0, 32), (1, 9, 13, 16, 16, 8),
                                               (2, 32, 32, 32, 0, 64), (1, 8, 8, 64, 64, 128),
                                               (3, 4, 4, 128, 0, 256), (1, 16, 16, 32, 32, 32),
                                               (2, 8, 8, 64, 0, 64), (1, 8, 8, 64, 0, 128),
-                                              (1, 8, 8, 32, 0, 128), (4, 256, 256, 32, 0, 32)])
+                                              (1, 8, 8, 32, 0, 128), (4, 256, 256, 32, 0, 32),
+                                              (2, 9, 45, 32, 32, 64), (1, 17, 33, 64, 0, 32)])
 def test_conv3x3_forward_and_gradients(un, N, H, W, c0, c1, cout):
     _say(f"case conv3x3 {N, H, W, c0, c1, cout}")
     g = torch.Generator().manual_seed(N * 1000 + H * 10 + cout)
@@ -91,7 +93,8 @@ def test_conv3x3_forward_and_gradients(un, N, H, W, c0, c1, cout):
 
 
 @pytest.mark.parametrize("N,H,W,c0,c1,cout", [(2, 16, 16, 8, 0, 32), (1, 9, 13, 16, 16, 8),
-                                              (2, 32, 32, 64, 64, 128), (3, 64, 64, 32, 0, 32)])
+                                              (2, 32, 32, 64, 64, 128), (3, 64, 64, 32, 0, 32),
+                                              (2, 9, 45, 32, 32, 64)])
 def test_conv3x3_affine_relu_inference(un, N, H, W, c0, c1, cout):
     """The fused inference layer against a float32 CPU conv, affine and ReLU."""
     _say(f"case conv3x3 affine relu {N, H, W, c0, c1, cout}")
