@@ -278,7 +278,8 @@ def main():
     scene = torch.from_numpy(scene_np.view(np.int16)).to(dev)
     params = sil.Params(dtype=sil.U16)
     ny, nx = sil.hist_dims(H, W, params)
-    labels = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    # label rows on 128-byte boundaries (pitch 11008 for the 10980-wide tile)
+    labels = sil.alloc_labels(H, W, dev)
     hist = torch.empty((ny, nx, 3), dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream(dev)
     torch.cuda.synchronize()
@@ -340,7 +341,7 @@ def main():
 
     # thresholds-only mode (the paper's unfiltered segmentation) on the same tile
     p0 = sil.Params(dtype=sil.U16, filter=0)
-    labels0 = torch.empty_like(labels)
+    labels0 = sil.alloc_labels(H, W, dev)
     hist0 = torch.empty_like(hist)
     for _ in range(3):
         sil.label(scene, p0, W=W, labels=labels0, hist=hist0, stream=stream)

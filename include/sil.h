@@ -135,7 +135,9 @@ int sil_validate(int32_t nbands, const int32_t sel[3], int32_t H, int32_t W,
  *                     limits that do not span H in [0,179] and S in [0,255]
  *                     (OpenCV 8-bit HSV); class order along V other than
  *                     water <= thin <= thick; chip > 256; refl_max > 65535;
- *                     H*W beyond 2^31 chips or pixel offsets beyond int64.
+ *                     H*W beyond 2^31 chips or pixel offsets beyond int64;
+ *                     with filter = 1, input rows of 2^32/34 bytes or more
+ *                     (a chip walk addresses 34 rows with 32-bit offsets).
  *   SIL_EDEVICE       the kernel launch failed.
  */
 int sil_label(const void* scene, int32_t nbands, const int32_t sel[3], int32_t H,

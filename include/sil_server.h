@@ -6,7 +6,8 @@
  *
  * Model:
  *   - A request names a device-resident scene (planar [nbands][H][pitch]).
- *   - Its outputs (label plane [H][W] and per-chip counts [ncy][ncx][3]) are
+ *   - Its outputs (label plane [H][label_pitch], rows of W labels starting on
+ *     128-byte boundaries, and per-chip counts [ncy][ncx][3]) are
  *     placed in an HBM arena of fixed size allocated at creation.  Requests
  *     are admitted first-in first-out when their outputs fit in the free
  *     arena space; the head of the queue is never overtaken.
@@ -58,11 +59,11 @@ typedef struct sil_request {
 
 typedef struct sil_completion {
   uint64_t tag;
-  uint8_t* labels;    /* device, [H][W], valid until sil_server_release(tag) */
+  uint8_t* labels;    /* device, [H][label_pitch], valid until sil_server_release(tag) */
   uint32_t* hist;     /* device, [ceil(H/chip)][ceil(W/chip)][3] */
   int32_t H, W;
   int32_t launches;   /* launches that held chips of this request */
-  int32_t pad;
+  int32_t label_pitch; /* bytes between label rows: W rounded up to a multiple of 128 */
   double t_submit_ms; /* host clock at submit, ms since creation */
   double t_admit_ms;  /* host clock at admission */
   double t_done_ms;   /* GPU completion time, ms since creation */

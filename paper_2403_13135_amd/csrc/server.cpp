@@ -23,6 +23,9 @@ namespace {
 constexpr uint64_t kAlign = 256;
 
 uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+// Label rows start on 128-byte boundaries, so the labeller writes whole
+// cache lines (rows of W bytes rounded up).
+int64_t label_pitch_of(int32_t W) { return ((int64_t)W + 127) / 128 * 128; }
 
 struct Req {
   sil_request r;
@@ -108,7 +111,8 @@ struct sil_server {
   }
 
   uint64_t out_bytes(int32_t H, int32_t W, int32_t ncy, int32_t ncx) const {
-    return align_up((uint64_t)H * (uint64_t)W) + align_up((uint64_t)ncy * ncx * 3 * 4);
+    return align_up((uint64_t)H * (uint64_t)label_pitch_of(W)) +
+           align_up((uint64_t)ncy * ncx * 3 * 4);
   }
 
   // Retire launches whose events have completed.
@@ -143,7 +147,7 @@ struct sil_server {
       uint64_t off;
       if (!arena->alloc(rq.bytes, &off)) break;
       rq.off = off;
-      rq.hist_off = off + align_up((uint64_t)rq.r.H * rq.r.W);
+      rq.hist_off = off + align_up((uint64_t)rq.r.H * (uint64_t)label_pitch_of(rq.r.W));
       rq.admitted = true;
       rq.t_admit = now_ms();
       active.push_back(queue.front());
@@ -170,7 +174,7 @@ struct sil_server {
       j.W = rq.r.W;
       j.pitch = rq.r.pitch;
       j.labels = (uint8_t*)(base + rq.off);
-      j.label_pitch = rq.r.W;
+      j.label_pitch = label_pitch_of(rq.r.W);
       j.hist = (uint32_t*)(base + rq.hist_off);
       j.chips = nullptr;
       j.chip_begin = rq.next_chip;
@@ -318,7 +322,7 @@ int sil_server_poll(sil_server* s, sil_completion* out, int32_t max, int32_t* n)
     c.H = rq.r.H;
     c.W = rq.r.W;
     c.launches = rq.launches;
-    c.pad = 0;
+    c.label_pitch = (int32_t)label_pitch_of(rq.r.W);
     c.t_submit_ms = rq.t_submit;
     c.t_admit_ms = rq.t_admit;
     c.t_done_ms = rq.t_done;

@@ -55,6 +55,11 @@ constexpr int kMaxPatchSlots = 1024;          // LDS per-patch counters per work
 #ifndef SIL_WAVES_PER_EU
 #define SIL_WAVES_PER_EU 4
 #endif
+// Label stores bypass the L2's write-back order (nontemporal): mixed with the
+// chip walk's reads, written-back lines reach HBM in scattered order otherwise.
+#ifndef SIL_NT_LABELS
+#define SIL_NT_LABELS 1
+#endif
 constexpr int kPrefetch = SIL_PREFETCH;       // rows of loads in flight per wave
 constexpr int kMaxBatch = SIL_BATCH_MAX_JOBS; // scenes per batched launch
 
@@ -113,6 +118,26 @@ __device__ __forceinline__ uint32_t med3u(uint32_t a, uint32_t b, uint32_t c) {
   return max(min(a, b), min(max(a, b), c));
 }
 
+// The same three order statistics as single VOP3 instructions.  Written out so
+// that the compiler does not split them into two-operand min/max chains to
+// share partial results between neighbouring rows, which costs more issue
+// slots than the three-operand forms.
+__device__ __forceinline__ uint32_t vmin3(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_min3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+__device__ __forceinline__ uint32_t vmax3(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_max3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+__device__ __forceinline__ uint32_t vmed3(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
 // Lane i receives lane i-1's value; lane 0 receives `edge`.
 __device__ __forceinline__ uint32_t from_left(uint32_t v, uint32_t edge) {
   return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, 0x138 /*wave_shr:1*/, 0xF,
@@ -136,12 +161,15 @@ __device__ __forceinline__ uint32_t rescale(uint32_t x, const Shared& sh, bool f
   if constexpr (sizeof(T) == 1) {
     return x;
   } else {
-    uint32_t n = min(x, sh.x_sat) * 255u + sh.half;
     if (fast24) {
-      // n < 2^24 and magic < 2^24 (checked on the host): 24-bit multiplies
-      uint64_t p = (uint64_t)(n & 0xFFFFFFu) * (uint64_t)(sh.magic & 0xFFFFFFu);
-      return (uint32_t)(p >> sh.shift);
+      // n < 2^24, magic < 2^24 and shift >= 32 (checked on the host): a 24-bit
+      // multiply-add, the high word of a 24 x 24-bit product and a 32-bit shift
+      uint32_t n;
+      asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(n) : "v"(min(x, sh.x_sat)), "v"(255u), "v"(sh.half));
+      const uint64_t p = (uint64_t)(n & 0xFFFFFFu) * (uint64_t)(sh.magic & 0xFFFFFFu);
+      return (uint32_t)(p >> 32) >> (sh.shift - 32u);
     }
+    const uint32_t n = min(x, sh.x_sat) * 255u + sh.half;
     return (uint32_t)(((uint64_t)n * sh.magic) >> sh.shift);
   }
 }
@@ -153,29 +181,28 @@ __device__ __forceinline__ uint32_t rescale(uint32_t x, const Shared& sh, bool f
 
 // Raw 4-pixel row segments of the three bands, plus one halo pixel per band
 // (lanes 0-31 fetch the chip's left halo column, lanes 32-63 its right one,
-// so every halo load instruction touches only two cache lines).
-template <typename T, bool VEC>
-struct Raw {
-  uint32_t v[3][4];
-  uint32_t h[3];
-};
+// so every halo load instruction touches only two cache lines).  The four
+// pixels of a band are packed as they lie in memory: two per 32-bit word for
+// 16-bit scenes, four per word for 8-bit ones.
+template <typename T>
+struct Raw;
 template <>
-struct Raw<uint16_t, true> {
+struct Raw<uint16_t> {
   uint2 v[3];
   uint32_t h[3];
 };
 template <>
-struct Raw<uint8_t, true> {
+struct Raw<uint8_t> {
   uint32_t v[3];
   uint32_t h[3];
 };
 
 // Row gy (wave-uniform).  VEC: one aligned vector per band at coff[0] (the
 // caller guarantees the 4 columns lie inside the scene).  Otherwise element
-// loads at the 4 (clamped) column offsets coff[j].
+// loads at the 4 (clamped) column offsets coff[j], packed the same way.
 template <typename T, bool VEC>
 __device__ __forceinline__ void load_raw(const Scene& sc, int32_t gy, const uint32_t coff[4],
-                                         uint32_t hoff, Raw<T, VEC>& r) {
+                                         uint32_t hoff, Raw<T>& r) {
   const char* row = sc.scene + (int64_t)gy * sc.pitch;
 #pragma unroll
   for (int b = 0; b < 3; ++b) {
@@ -186,37 +213,41 @@ __device__ __forceinline__ void load_raw(const Scene& sc, int32_t gy, const uint
       else
         r.v[b] = *(const uint32_t*)(rb + coff[0]);
     } else {
+      uint32_t e[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) r.v[b][j] = *(const T*)(rb + coff[j]);
+      for (int j = 0; j < 4; ++j) e[j] = *(const T*)(rb + coff[j]);
+      if constexpr (sizeof(T) == 2)
+        r.v[b] = make_uint2(e[0] | (e[1] << 16), e[2] | (e[3] << 16));
+      else
+        r.v[b] = e[0] | (e[1] << 8) | (e[2] << 16) | (e[3] << 24);
     }
     r.h[b] = *(const T*)(rb + hoff);
   }
 }
 
 // max over the three bands, 4 pixels
-template <typename T, bool VEC>
-__device__ __forceinline__ void max_bands(const Raw<T, VEC>& r, uint32_t x[4]) {
-  if constexpr (VEC) {
-    if constexpr (sizeof(T) == 2) {
-      uint32_t lo[3], hi[3];
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        lo[b] = r.v[b].x;
-        hi[b] = r.v[b].y;
-      }
-      x[0] = max3u(lo[0] & 0xFFFFu, lo[1] & 0xFFFFu, lo[2] & 0xFFFFu);
-      x[1] = max3u(lo[0] >> 16, lo[1] >> 16, lo[2] >> 16);
-      x[2] = max3u(hi[0] & 0xFFFFu, hi[1] & 0xFFFFu, hi[2] & 0xFFFFu);
-      x[3] = max3u(hi[0] >> 16, hi[1] >> 16, hi[2] >> 16);
-    } else {
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        x[j] = max3u((r.v[0] >> (8 * j)) & 0xFFu, (r.v[1] >> (8 * j)) & 0xFFu,
-                     (r.v[2] >> (8 * j)) & 0xFFu);
-    }
+template <typename T>
+__device__ __forceinline__ void max_bands(const Raw<T>& r, uint32_t x[4]) {
+  if constexpr (sizeof(T) == 2) {
+    // two pixels per register: packed 16-bit maxima, then unpack
+    typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+    auto pmax = [](uint32_t a, uint32_t b, uint32_t c) {
+      const u16x2 m = __builtin_elementwise_max(
+          __builtin_elementwise_max(__builtin_bit_cast(u16x2, a), __builtin_bit_cast(u16x2, b)),
+          __builtin_bit_cast(u16x2, c));
+      return __builtin_bit_cast(uint32_t, m);
+    };
+    const uint32_t m01 = pmax(r.v[0].x, r.v[1].x, r.v[2].x);
+    const uint32_t m23 = pmax(r.v[0].y, r.v[1].y, r.v[2].y);
+    x[0] = m01 & 0xFFFFu;
+    x[1] = m01 >> 16;
+    x[2] = m23 & 0xFFFFu;
+    x[3] = m23 >> 16;
   } else {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) x[j] = max3u(r.v[0][j], r.v[1][j], r.v[2][j]);
+    for (int j = 0; j < 4; ++j)
+      x[j] = max3u((r.v[0] >> (8 * j)) & 0xFFu, (r.v[1] >> (8 * j)) & 0xFFu,
+                   (r.v[2] >> (8 * j)) & 0xFFu);
   }
 }
 
@@ -307,7 +338,10 @@ __device__ __forceinline__ void pix_publish(const Shared& sh, const Scene& sc,
 __device__ __forceinline__ void store_labels(uint8_t* row, uint32_t off, int valid_n, bool vec4,
                                              uint32_t packed) {
   if (valid_n == 4 && vec4) {
-    *(uint32_t*)(row + off) = packed;
+    if constexpr (SIL_NT_LABELS)
+      __builtin_nontemporal_store(packed, (uint32_t*)(row + off));
+    else
+      *(uint32_t*)(row + off) = packed;
   } else {
     for (int j = 0; j < valid_n; ++j) row[off + j] = (uint8_t)(packed >> (8 * j));
   }
@@ -322,48 +356,103 @@ struct FilterLds {
   uint8_t lut[256];
 };
 
+// Addresses of one wave's walk over a chip: 34 input rows, chip rows -1..32
+// of the wave's band (down) or 32..-1 (up), clamped into the scene; the lane's
+// four column offsets and its halo column (lanes 0-31 the chip's left halo
+// column, lanes 32-63 its right one), also clamped.  Rows are addressed from
+// the walk's first row in each band: a wave-uniform 64-bit base per band plus
+// a 32-bit per-lane offset (the walk spans 34 rows, and the host checks that
+// 34 row pitches fit in 32 bits), so each load is a scalar-base +
+// vector-offset load and the walk keeps few scalar registers live.
+template <typename T>
+struct Walk {
+  const char* band[3];  // row `top` of each band
+  int32_t base, top, last;
+  uint32_t pitch;
+  bool down;
+  uint32_t coff[4];
+  uint32_t hoff;
+  __device__ __forceinline__ Walk(const Scene& sc, int32_t y0, int32_t x0, int wave, int lane) {
+    down = (wave & 1) == 0;
+    base = y0 + wave * kRowsPerWave;
+    last = sc.H - 1;
+    top = min(max(base - 1, 0), last);
+    pitch = (uint32_t)sc.pitch;
+    const char* row = sc.scene + (int64_t)top * sc.pitch;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) band[b] = row + sc.off[b];
+    const int32_t gx = x0 + 4 * lane;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) coff[j] = (uint32_t)(min(gx + j, sc.W - 1) * (int)sizeof(T));
+    hoff = (uint32_t)(min(max(lane < 32 ? x0 - 1 : x0 + 4 * 64, 0), sc.W - 1) * (int)sizeof(T));
+  }
+  // byte offset, from row `top`, of the input row of walk step st (0..33)
+  __device__ __forceinline__ uint32_t roff(int st) const {
+    const int32_t r = down ? st - 1 : kRowsPerWave - st;
+    return (uint32_t)(min(max(base + r, 0), last) - top) * pitch;
+  }
+};
+
+// Walk step st into r.  VEC: one aligned vector per band at coff[0] (the
+// caller guarantees the 4 columns lie inside the scene).  Otherwise element
+// loads at the 4 (clamped) column offsets, packed the same way.
+template <typename T, bool VEC>
+__device__ __forceinline__ void load_step(const Walk<T>& wk, int st, Raw<T>& r) {
+  const uint32_t ro = wk.roff(st);
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const char* rb = wk.band[b];
+    if constexpr (VEC) {
+      if constexpr (sizeof(T) == 2)
+        r.v[b] = *(const uint2*)(rb + (ro + wk.coff[0]));
+      else
+        r.v[b] = *(const uint32_t*)(rb + (ro + wk.coff[0]));
+    } else {
+      uint32_t e[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) e[j] = *(const T*)(rb + (ro + wk.coff[j]));
+      if constexpr (sizeof(T) == 2)
+        r.v[b] = make_uint2(e[0] | (e[1] << 16), e[2] | (e[3] << 16));
+      else
+        r.v[b] = e[0] | (e[1] << 8) | (e[2] << 16) | (e[3] << 24);
+    }
+    r.h[b] = *(const T*)(rb + (ro + wk.hoff));
+  }
+}
+
+// The first kPrefetch rows of a walk (the loads phase 1 starts with).
+template <typename T, bool VEC>
+__device__ __forceinline__ void walk_prefetch(const Walk<T>& wk, Raw<T> (&ring)[kPrefetch]) {
+#pragma unroll
+  for (int p = 0; p < kPrefetch; ++p) load_step<T, VEC>(wk, p, ring[p]);
+}
+
 // Phase 1 for one wave: walk 34 rows, median, rescale, histogram, keep the
-// packed 8-bit medians in vm[].  `wave` is wave-uniform.
-template <typename T, bool VEC, bool FAST24>
+// packed 8-bit medians in vm[].  `wave` is wave-uniform.  The ring holds the
+// walk's first kPrefetch rows on entry (walk_prefetch with the same VEC).
+template <typename T, bool VEC, bool FAST24, bool FULL>
 __device__ __forceinline__ void filter_phase1(const Shared& sh, const Scene& sc, FilterLds& s,
                                               int32_t y0, int32_t x0, int32_t ch, int32_t cw,
-                                              int wave, int lane, uint32_t vm[kRowsPerWave]) {
-  const bool down = (wave & 1) == 0;
+                                              int wave, int lane, uint32_t vm[kRowsPerWave],
+                                              Raw<T> (&ring)[kPrefetch]) {
+  const Walk<T> wk(sc, y0, x0, wave, lane);
+  const bool down = wk.down;
   const int32_t wy0 = wave * kRowsPerWave;
-  const int32_t gx = x0 + 4 * lane;
-
-  // input row of walk step st (0..33): chip row -1..32 (down) or 32..-1 (up)
-  auto row_of = [&](int st) -> int32_t {
-    int32_t r = down ? st - 1 : kRowsPerWave - st;
-    return min(max(y0 + wy0 + r, 0), sc.H - 1);
-  };
-
-  uint32_t coff[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) coff[j] = (uint32_t)(min(gx + j, sc.W - 1) * (int)sizeof(T));
-  // Halo column fetched by this lane with every row (clamped into the scene).
-  const uint32_t hoff =
-      (uint32_t)(min(max(lane < 32 ? x0 - 1 : x0 + 4 * 64, 0), sc.W - 1) * (int)sizeof(T));
 
   // columns of this lane that lie inside the chip
   const int valid_cols = min(max(cw - 4 * lane, 0), 4);
   const uint32_t hist_lane = (uint32_t)(lane & (kCopies - 1));
-
-  Raw<T, VEC> ring[kPrefetch];
-#pragma unroll
-  for (int p = 0; p < kPrefetch; ++p) load_raw<T, VEC>(sc, row_of(p), coff, hoff, ring[p]);
 
   uint32_t w0[6], w1[6] = {0, 0, 0, 0, 0, 0}, w2[6] = {0, 0, 0, 0, 0, 0};
 
 #pragma unroll
   for (int st = 0; st < kRowsPerWave + 2; ++st) {
     uint32_t x[4];
-    const Raw<T, VEC>& cur = ring[st % kPrefetch];
-    max_bands<T, VEC>(cur, x);
+    const Raw<T>& cur = ring[st % kPrefetch];
+    max_bands<T>(cur, x);
     // lane 0 takes the left halo, lane 63 the right one (as the DPP fill value)
     const uint32_t hv = max3u(cur.h[0], cur.h[1], cur.h[2]);
-    if (st + kPrefetch < kRowsPerWave + 2)
-      load_raw<T, VEC>(sc, row_of(st + kPrefetch), coff, hoff, ring[st % kPrefetch]);
+    if (st + kPrefetch < kRowsPerWave + 2) load_step<T, VEC>(wk, st + kPrefetch, ring[st % kPrefetch]);
 
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
@@ -386,17 +475,17 @@ __device__ __forceinline__ void filter_phase1(const Shared& sh, const Scene& sc,
     uint32_t lo[6], mi[6], hi[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-      lo[c] = min3u(w0[c], w1[c], w2[c]);
-      mi[c] = med3u(w0[c], w1[c], w2[c]);
-      hi[c] = max3u(w0[c], w1[c], w2[c]);
+      lo[c] = vmin3(w0[c], w1[c], w2[c]);
+      mi[c] = vmed3(w0[c], w1[c], w2[c]);
+      hi[c] = vmax3(w0[c], w1[c], w2[c]);
     }
     uint32_t packed = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      uint32_t m = med3u(max3u(lo[j], lo[j + 1], lo[j + 2]), med3u(mi[j], mi[j + 1], mi[j + 2]),
-                         min3u(hi[j], hi[j + 1], hi[j + 2]));
+      uint32_t m = vmed3(vmax3(lo[j], lo[j + 1], lo[j + 2]), vmed3(mi[j], mi[j + 1], mi[j + 2]),
+                         vmin3(hi[j], hi[j + 1], hi[j + 2]));
       uint32_t v = rescale<T>(m, sh, FAST24);
-      atomicAdd(&s.hist[(v << 5) | hist_lane], j < nvalid ? 1u : 0u);
+      atomicAdd(&s.hist[(v << 5) | hist_lane], FULL || j < nvalid ? 1u : 0u);
       packed |= v << (8 * j);
     }
     vm[k] = packed;
@@ -552,32 +641,65 @@ __device__ void filter_phase2(const Shared& sh, const Scene& sc, FilterLds& s, i
   }
 }
 
+// A chip of a launch: its scene, raster id and extent.
+struct ChipAt {
+  const Scene* sc;
+  int32_t chip_id, y0, x0, ch, cw;
+};
+
+__device__ __forceinline__ ChipAt chip_at(const Shared& sh, const Scene& sc, int32_t chip_id) {
+  ChipAt c;
+  c.sc = &sc;
+  c.chip_id = chip_id;
+  const int32_t cy = chip_id / sc.ncx, cx = chip_id - cy * sc.ncx;
+  c.y0 = cy * sh.chip;
+  c.x0 = cx * sh.chip;
+  c.ch = min(sh.chip, sc.H - c.y0);
+  c.cw = min(sh.chip, sc.W - c.x0);
+  return c;
+}
+
+__device__ __forceinline__ void zero_hist(FilterLds& s, int t0, int nt) {
+  for (int i = t0; i < 256 * kCopies / 4; i += nt) ((uint4*)s.hist)[i] = make_uint4(0, 0, 0, 0);
+}
+
 // One chip, all three phases, by the whole workgroup.
 template <typename T, bool FAST24>
-__device__ __forceinline__ void filter_chip(const Shared& sh, const Scene& sc, int chip_id,
-                                            FilterLds& s) {
+__device__ __forceinline__ void filter_chip(const Shared& sh, const ChipAt& c, FilterLds& s) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int32_t cy = chip_id / sc.ncx, cx = chip_id - cy * sc.ncx;
-  const int32_t y0 = cy * sh.chip, x0 = cx * sh.chip;
-  const int32_t ch = min(sh.chip, sc.H - y0), cw = min(sh.chip, sc.W - x0);
+  const Scene& sc = *c.sc;
+  const int32_t y0 = c.y0, x0 = c.x0, ch = c.ch, cw = c.cw;
   const bool active = wave * kRowsPerWave < ch;
   const bool pix = sh.count_mode >= CM_PIX_LDS;
   const bool pix_lds = sh.count_mode == CM_PIX_LDS;
+  // whole-vector loads need aligned rows and every lane's 4 columns inside the scene
+  const bool vec = sc.vec && x0 + 4 * 64 <= sc.W;
 
-  for (int i = threadIdx.x; i < 256 * kCopies / 4; i += kThreads)
-    ((uint4*)s.hist)[i] = make_uint4(0, 0, 0, 0);
+  // the walk's first rows are in flight while the histogram is cleared
+  Raw<T> ring[kPrefetch];
+  const Walk<T> wk(sc, y0, x0, wave, lane);
+  if (active) {
+    if (vec)
+      walk_prefetch<T, true>(wk, ring);
+    else
+      walk_prefetch<T, false>(wk, ring);
+  }
+  zero_hist(s, threadIdx.x, kThreads);
   if (pix_lds)
     for (int i = threadIdx.x; i < sh.npy_l * sh.npx_l * 3; i += kThreads) s.cnt[i] = 0;
   __syncthreads();
 
   uint32_t vm[kRowsPerWave];
   if (active) {
-    // whole-vector loads need aligned rows and every lane's 4 columns inside the scene
-    if (sc.vec && x0 + 4 * 64 <= sc.W)
-      filter_phase1<T, true, FAST24>(sh, sc, s, y0, x0, ch, cw, wave, lane, vm);
+    // whole chips (every column, and every row of this wave, inside the
+    // scene) skip the per-pixel validity masks
+    if (vec && cw == kTile && (wave + 1) * kRowsPerWave <= ch)
+      filter_phase1<T, true, FAST24, true>(sh, sc, s, y0, x0, ch, cw, wave, lane, vm, ring);
+    else if (vec)
+      filter_phase1<T, true, FAST24, false>(sh, sc, s, y0, x0, ch, cw, wave, lane, vm, ring);
     else
-      filter_phase1<T, false, FAST24>(sh, sc, s, y0, x0, ch, cw, wave, lane, vm);
+      filter_phase1<T, false, FAST24, false>(sh, sc, s, y0, x0, ch, cw, wave, lane, vm, ring);
   }
   __syncthreads();
 
@@ -585,11 +707,11 @@ __device__ __forceinline__ void filter_chip(const Shared& sh, const Scene& sc, i
     const uint32_t bin = threadIdx.x;
     uint32_t sum = 0;
 #pragma unroll 8
-    for (uint32_t c = 0; c < kCopies; ++c) sum += s.hist[(bin << 5) | ((c + bin) & (kCopies - 1))];
+    for (uint32_t k = 0; k < kCopies; ++k) sum += s.hist[(bin << 5) | ((k + bin) & (kCopies - 1))];
     s.hsum[bin] = sum;
   }
   __syncthreads();
-  if (wave == 0) filter_phase2(sh, sc, s, chip_id, y0, x0, lane);
+  if (wave == 0) filter_phase2(sh, sc, s, c.chip_id, y0, x0, lane);
   __syncthreads();
 
   if (active) {
@@ -616,8 +738,8 @@ __device__ __forceinline__ void filter_chip(const Shared& sh, const Scene& sc, i
 #pragma unroll
       for (int j = 0; j < 4; ++j) cls[j] = s.lut[(v >> (8 * j)) & 0xFFu];
       const uint32_t packed = cls[0] | (cls[1] << 8) | (cls[2] << 16) | (cls[3] << 24);
-      if (valid_cols > 0) store_labels(sc.labels + (int64_t)gy * sc.lpitch, loff, valid_cols, vec4,
-                                       packed);
+      if (valid_cols > 0)
+        store_labels(sc.labels + (int64_t)gy * sc.lpitch, loff, valid_cols, vec4, packed);
       if (pix) {
         const int32_t py = gy / sh.ph - (pix_lds ? y0 / sh.ph : 0);
         const int32_t rowkey = py * (pix_lds ? sh.npx_l : sc.nx);
@@ -634,11 +756,12 @@ __device__ __forceinline__ void filter_chip(const Shared& sh, const Scene& sc, i
 }
 
 template <typename T, bool FAST24>
-__global__ __launch_bounds__(kThreads, SIL_WAVES_PER_EU) void k_filter(Shared sh, Scene sc, int per_xcd) {
+__global__ __launch_bounds__(kThreads, SIL_WAVES_PER_EU) void k_filter(Shared sh, Scene sc,
+                                                                       int per_xcd) {
   __shared__ FilterLds s;
   const int chip_id = xcd_work_index(per_xcd);
   if (chip_id >= sc.nchips) return;
-  filter_chip<T, FAST24>(sh, sc, chip_id, s);
+  filter_chip<T, FAST24>(sh, chip_at(sh, sc, chip_id), s);
 }
 
 // Chips of up to kMaxBatch scenes in one launch: scene j contributes chips
@@ -651,7 +774,7 @@ __global__ __launch_bounds__(kThreads, SIL_WAVES_PER_EU) void k_filter_batch(Sha
   int j = 0;
   while (j + 1 < bt.n && bt.prefix[j + 1] <= i) ++j;
   const Scene& sc = bt.sc[j];
-  filter_chip<T, FAST24>(sh, sc, sc.chip_begin + (i - bt.prefix[j]), s);
+  filter_chip<T, FAST24>(sh, chip_at(sh, sc, sc.chip_begin + (i - bt.prefix[j])), s);
 }
 
 // ---- filter = 0: thresholds only ----------------------------------------------
@@ -674,10 +797,10 @@ __device__ __forceinline__ void thresh_rows(const Shared& sh, const Scene& sc, u
   for (int j = 0; j < 4; ++j) colkey[j] = min(gx + j, sc.W - 1) / sh.pw - px_base;
   for (int r = 0; r < kRowsPerWave && wy0 + r < ch; ++r) {
     const int32_t gy = y0 + wy0 + r;
-    Raw<T, VEC> raw;
+    Raw<T> raw;
     load_raw<T, VEC>(sc, gy, coff, coff[0], raw);
     uint32_t x[4];
-    max_bands<T, VEC>(raw, x);
+    max_bands<T>(raw, x);
     uint32_t cls[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) cls[j] = (x[j] >= sh.X1) + (x[j] >= sh.X2);
@@ -769,11 +892,12 @@ bool derive_rescale(uint32_t d, RescaleConst* rc) {
     }
     return true;
   };
-  // prefer a 24-bit magic (full-rate 24-bit multiplies on the device)
+  // prefer a 24-bit magic with shift >= 32 (full-rate 24-bit multiplies and
+  // the product's high word on the device)
   for (int s = nb + l; s < 64 && !r.fast24; ++s) {
     uint64_t m = ((1ull << s) + d - 1) / d;
     if (m >= (1ull << 24)) break;
-    if (nmax < (1ull << 24) && check(m, s)) {
+    if (s >= 32 && nmax < (1ull << 24) && check(m, s)) {
       r.magic = (uint32_t)m;
       r.shift = (uint32_t)s;
       r.fast24 = true;
@@ -841,6 +965,9 @@ int validate(int32_t nbands, const int32_t* sel, int32_t H, int32_t W, int64_t p
   if ((int64_t)nbands * H > INT64_MAX / (pitch * esize)) return SIL_EUNSUPPORTED;
   if ((int64_t)H > INT64_MAX / label_pitch) return SIL_EUNSUPPORTED;
   if ((int64_t)W * esize + 1024 > INT32_MAX) return SIL_EUNSUPPORTED;  // 32-bit lane offsets
+  // a chip walk addresses its 34 rows with 32-bit offsets from its first row
+  if (p->filter == 1 && pitch * esize * (kRowsPerWave + 2) > (int64_t)UINT32_MAX)
+    return SIL_EUNSUPPORTED;
   return SIL_OK;
 }
 

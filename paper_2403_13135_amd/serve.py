@@ -29,7 +29,7 @@ class _Request(ctypes.Structure):
 class _Completion(ctypes.Structure):
     _fields_ = [("tag", ctypes.c_uint64), ("labels", ctypes.c_void_p), ("hist", ctypes.c_void_p),
                 ("H", ctypes.c_int32), ("W", ctypes.c_int32), ("launches", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("t_submit_ms", ctypes.c_double),
+                ("label_pitch", ctypes.c_int32), ("t_submit_ms", ctypes.c_double),
                 ("t_admit_ms", ctypes.c_double), ("t_done_ms", ctypes.c_double)]
 
 
@@ -86,10 +86,10 @@ def _check(rc):
 class _DevView:
     """Zero-copy view of device memory for torch.as_tensor."""
 
-    def __init__(self, ptr, shape, typestr):
+    def __init__(self, ptr, shape, typestr, strides=None):
         self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr,
                                          "data": (int(ptr), False), "version": 2,
-                                         "strides": None}
+                                         "strides": strides}
 
 
 @dataclass
@@ -104,10 +104,13 @@ class Completion:
     labels_ptr: int
     hist_ptr: int
     chip: int
+    label_pitch: int
 
     def labels(self) -> torch.Tensor:
-        """[H, W] uint8 view of the arena (valid until release)."""
-        return torch.as_tensor(_DevView(self.labels_ptr, (self.H, self.W), "|u1"), device="cuda")
+        """[H, W] uint8 view of the arena (rows `label_pitch` bytes apart; valid
+        until release)."""
+        return torch.as_tensor(_DevView(self.labels_ptr, (self.H, self.W), "|u1",
+                                        (self.label_pitch, 1)), device="cuda")
 
     def hist(self) -> torch.Tensor:
         c = self.chip
@@ -117,7 +120,7 @@ class Completion:
 
 def _completion(c: _Completion, chip: int) -> Completion:
     return Completion(c.tag, c.H, c.W, c.launches, c.t_submit_ms, c.t_admit_ms, c.t_done_ms,
-                      c.labels or 0, c.hist or 0, chip)
+                      c.labels or 0, c.hist or 0, chip, c.label_pitch)
 
 
 def _request(scene: torch.Tensor, tag: int, W: Optional[int] = None, sel=(0, 1, 2)) -> _Request:

@@ -176,6 +176,19 @@ def validate(nbands: int, sel, H: int, W: int, pitch: int, label_pitch: int,
 _SCENE_DTYPES = {U8: (torch.uint8,), U16: (torch.uint16, torch.int16)}
 
 
+def label_pitch_for(W: int) -> int:
+    """Row pitch (bytes) for a label plane of width W: W rounded up to a
+    multiple of 128, so every row starts on a cache-line boundary and the
+    labeller writes whole lines."""
+    return (int(W) + 127) // 128 * 128
+
+
+def alloc_labels(H: int, W: int, device) -> torch.Tensor:
+    """An [H, W] uint8 label plane whose rows are ``label_pitch_for(W)`` bytes
+    apart (a view of an [H, pitch] allocation)."""
+    return torch.empty((H, label_pitch_for(W)), dtype=torch.uint8, device=device)[:, :W]
+
+
 def label(scene: torch.Tensor, params: Optional[Params] = None, sel=(0, 1, 2),
           W: Optional[int] = None, labels: Optional[torch.Tensor] = None,
           hist: Optional[torch.Tensor] = None, chips: bool = False,
@@ -183,8 +196,8 @@ def label(scene: torch.Tensor, params: Optional[Params] = None, sel=(0, 1, 2),
     """Label ``scene`` ([nbands, H, pitch] on the GPU) with ``sil_label``.
 
     ``W`` defaults to the pitch (the last dimension).  ``labels`` ([H, >=W]
-    uint8) and ``hist`` ([ny, nx, 3] int32/uint32) may be given to reuse
-    buffers.  Returns (labels, hist) or (labels, hist, chip_info_bytes) with
+    uint8, any row stride) and ``hist`` ([ny, nx, 3] int32/uint32) may be given
+    to reuse buffers; by default labels come from ``alloc_labels``.  Returns (labels, hist) or (labels, hist, chip_info_bytes) with
     ``chips=True`` (a uint8 tensor of ``[ncy, ncx, 12]`` raw sil_chip_info).
     Enqueued on ``stream`` (default: the current stream); not synchronised.
     """
@@ -201,7 +214,7 @@ def label(scene: torch.Tensor, params: Optional[Params] = None, sel=(0, 1, 2),
     dev = scene.device
     ny, nx = hist_dims(H, W, params)
     if labels is None:
-        labels = torch.empty((H, W), dtype=torch.uint8, device=dev)
+        labels = alloc_labels(H, W, dev)
     if labels.dtype != torch.uint8 or labels.dim() != 2 or labels.shape[0] != H \
             or labels.shape[1] < W or labels.stride(1) != 1:
         raise ValueError("labels must be uint8 [H, >=W] with unit column stride")

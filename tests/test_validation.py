@@ -55,6 +55,13 @@ GPU_ONLY = [
     ("V order not water<=thin<=thick", dict(lo=[[0, 0, 205], [0, 0, 31], [0, 0, 0]],
                                             hi=[[185, 255, 255], [185, 255, 204],
                                                 [185, 255, 30]]), {}, -2, 0),
+    # the chip walk's 34 rows are addressed with 32-bit offsets
+    ("u16 rows of 2^32/34 bytes", dict(dtype=2), dict(H=1, W=10, pitch=(1 << 32) // 68 + 1,
+                                                       label_pitch=10), -2, 0),
+    ("u16 rows just below", dict(dtype=2), dict(H=1, W=10, pitch=(1 << 32) // 68 - 1,
+                                                 label_pitch=10), 0, 0),
+    ("filter off, long rows", dict(dtype=2, filter=0), dict(H=1, W=10, pitch=(1 << 32) // 68 + 1,
+                                                             label_pitch=10), 0, 0),
 ]
 
 
