@@ -225,9 +225,11 @@ __device__ __forceinline__ void load_raw(const Scene& sc, int32_t gy, const uint
   }
 }
 
-// max over the three bands, 4 pixels
-template <typename T>
-__device__ __forceinline__ void max_bands(const Raw<T>& r, uint32_t x[4]) {
+// max over the three bands, 4 pixels.  PERM: first rearrange the 4 pixels
+// by the byte selectors `sel` (v_perm_b32; see Walk).
+template <typename T, bool PERM = false>
+__device__ __forceinline__ void max_bands(const Raw<T>& r, uint32_t x[4],
+                                          const uint32_t* sel = nullptr) {
   if constexpr (sizeof(T) == 2) {
     // two pixels per register: packed 16-bit maxima, then unpack
     typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
@@ -237,17 +239,24 @@ __device__ __forceinline__ void max_bands(const Raw<T>& r, uint32_t x[4]) {
           __builtin_bit_cast(u16x2, c));
       return __builtin_bit_cast(uint32_t, m);
     };
-    const uint32_t m01 = pmax(r.v[0].x, r.v[1].x, r.v[2].x);
-    const uint32_t m23 = pmax(r.v[0].y, r.v[1].y, r.v[2].y);
+    uint32_t m01 = pmax(r.v[0].x, r.v[1].x, r.v[2].x);
+    uint32_t m23 = pmax(r.v[0].y, r.v[1].y, r.v[2].y);
+    if constexpr (PERM) {
+      const uint32_t a = __builtin_amdgcn_perm(m23, m01, sel[0]);
+      m23 = __builtin_amdgcn_perm(m23, m01, sel[1]);
+      m01 = a;
+    }
     x[0] = m01 & 0xFFFFu;
     x[1] = m01 >> 16;
     x[2] = m23 & 0xFFFFu;
     x[3] = m23 >> 16;
   } else {
+    uint32_t v[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) v[b] = PERM ? __builtin_amdgcn_perm(r.v[b], r.v[b], sel[0]) : r.v[b];
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      x[j] = max3u((r.v[0] >> (8 * j)) & 0xFFu, (r.v[1] >> (8 * j)) & 0xFFu,
-                   (r.v[2] >> (8 * j)) & 0xFFu);
+      x[j] = max3u((v[0] >> (8 * j)) & 0xFFu, (v[1] >> (8 * j)) & 0xFFu, (v[2] >> (8 * j)) & 0xFFu);
   }
 }
 
@@ -372,6 +381,13 @@ struct Walk {
   bool down;
   uint32_t coff[4];
   uint32_t hoff;
+  // Vector loads (aligned scenes): each lane loads the aligned group of 4
+  // columns at vcol, moved left so that it ends inside the scene's padded row
+  // (the last group that holds column W-1), and `sel` rearranges the loaded
+  // pixels so that column c reads column min(c, W-1), the clamped border.
+  // Both are the identity away from the scene's right edge.
+  uint32_t vcol;
+  uint32_t sel[2];
   __device__ __forceinline__ Walk(const Scene& sc, int32_t y0, int32_t x0, int wave, int lane) {
     down = (wave & 1) == 0;
     base = y0 + wave * kRowsPerWave;
@@ -385,6 +401,19 @@ struct Walk {
 #pragma unroll
     for (int j = 0; j < 4; ++j) coff[j] = (uint32_t)(min(gx + j, sc.W - 1) * (int)sizeof(T));
     hoff = (uint32_t)(min(max(lane < 32 ? x0 - 1 : x0 + 4 * 64, 0), sc.W - 1) * (int)sizeof(T));
+    const int32_t g = min(gx, (sc.W - 1) & ~3);  // first column of the loaded group
+    vcol = (uint32_t)(g * (int)sizeof(T));
+    uint32_t o[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o[j] = (uint32_t)(min(gx + j, sc.W - 1) - g);
+    if constexpr (sizeof(T) == 2) {
+      // byte selectors over {hi word : lo word} of two packed 16-bit pairs
+      sel[0] = (2 * o[0]) | ((2 * o[0] + 1) << 8) | ((2 * o[1]) << 16) | ((2 * o[1] + 1) << 24);
+      sel[1] = (2 * o[2]) | ((2 * o[2] + 1) << 8) | ((2 * o[3]) << 16) | ((2 * o[3] + 1) << 24);
+    } else {
+      sel[0] = o[0] | (o[1] << 8) | (o[2] << 16) | (o[3] << 24);
+      sel[1] = 0;
+    }
   }
   // byte offset, from row `top`, of the input row of walk step st (0..33)
   __device__ __forceinline__ uint32_t roff(int st) const {
@@ -393,9 +422,9 @@ struct Walk {
   }
 };
 
-// Walk step st into r.  VEC: one aligned vector per band at coff[0] (the
-// caller guarantees the 4 columns lie inside the scene).  Otherwise element
-// loads at the 4 (clamped) column offsets, packed the same way.
+// Walk step st into r.  VEC: one aligned vector per band at vcol (aligned
+// scenes; max_bands applies `sel`).  Otherwise element loads at the 4
+// (clamped) column offsets, packed the same way.
 template <typename T, bool VEC>
 __device__ __forceinline__ void load_step(const Walk<T>& wk, int st, Raw<T>& r) {
   const uint32_t ro = wk.roff(st);
@@ -404,9 +433,9 @@ __device__ __forceinline__ void load_step(const Walk<T>& wk, int st, Raw<T>& r) 
     const char* rb = wk.band[b];
     if constexpr (VEC) {
       if constexpr (sizeof(T) == 2)
-        r.v[b] = *(const uint2*)(rb + (ro + wk.coff[0]));
+        r.v[b] = *(const uint2*)(rb + (ro + wk.vcol));
       else
-        r.v[b] = *(const uint32_t*)(rb + (ro + wk.coff[0]));
+        r.v[b] = *(const uint32_t*)(rb + (ro + wk.vcol));
     } else {
       uint32_t e[4];
 #pragma unroll
@@ -421,74 +450,109 @@ __device__ __forceinline__ void load_step(const Walk<T>& wk, int st, Raw<T>& r) 
 }
 
 // The first kPrefetch rows of a walk (the loads phase 1 starts with).
-template <typename T, bool VEC>
+template <typename T>
 __device__ __forceinline__ void walk_prefetch(const Walk<T>& wk, Raw<T> (&ring)[kPrefetch]) {
 #pragma unroll
-  for (int p = 0; p < kPrefetch; ++p) load_step<T, VEC>(wk, p, ring[p]);
+  for (int p = 0; p < kPrefetch; ++p) load_step<T, true>(wk, p, ring[p]);
+}
+
+// One step of a wave's walk: take row `cur` into the three-row window of
+// band maxima (horizontal neighbours from the adjacent lanes, the chip's halo
+// columns from lanes 0 and 63); from step 2 on, the window's middle row gives
+// an output row: 3x3 median, rescale, histogram (adding inc & rowmask per
+// pixel: 1 for pixels inside the chip), and the packed 8-bit medians.
+template <typename T, bool FAST24, bool PERM>
+__device__ __forceinline__ uint32_t walk_row(const Shared& sh, FilterLds& s, const Raw<T>& cur,
+                                             const uint32_t* sel, uint32_t (&w0)[6],
+                                             uint32_t (&w1)[6], uint32_t (&w2)[6], bool out,
+                                             uint32_t rowmask, const uint32_t inc[4],
+                                             uint32_t hist_lane) {
+  uint32_t x[4];
+  max_bands<T, PERM>(cur, x, sel);
+  // lane 0 takes the left halo, lane 63 the right one (as the DPP fill value)
+  const uint32_t hv = max3u(cur.h[0], cur.h[1], cur.h[2]);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    w0[c] = w1[c];
+    w1[c] = w2[c];
+  }
+  w2[0] = from_left(x[3], hv);
+  w2[1] = x[0];
+  w2[2] = x[1];
+  w2[3] = x[2];
+  w2[4] = x[3];
+  w2[5] = from_right(x[0], hv);
+  if (!out) return 0;
+
+  uint32_t lo[6], mi[6], hi[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    lo[c] = vmin3(w0[c], w1[c], w2[c]);
+    mi[c] = vmed3(w0[c], w1[c], w2[c]);
+    hi[c] = vmax3(w0[c], w1[c], w2[c]);
+  }
+  uint32_t packed = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    uint32_t m = vmed3(vmax3(lo[j], lo[j + 1], lo[j + 2]), vmed3(mi[j], mi[j + 1], mi[j + 2]),
+                       vmin3(hi[j], hi[j + 1], hi[j + 2]));
+    uint32_t v = rescale<T>(m, sh, FAST24);
+    atomicAdd(&s.hist[(v << 5) | hist_lane], inc[j] & rowmask);
+    packed |= v << (8 * j);
+  }
+  return packed;
 }
 
 // Phase 1 for one wave: walk 34 rows, median, rescale, histogram, keep the
-// packed 8-bit medians in vm[].  `wave` is wave-uniform.  The ring holds the
-// walk's first kPrefetch rows on entry (walk_prefetch with the same VEC).
-template <typename T, bool VEC, bool FAST24, bool FULL>
-__device__ __forceinline__ void filter_phase1(const Shared& sh, const Scene& sc, FilterLds& s,
-                                              int32_t y0, int32_t x0, int32_t ch, int32_t cw,
-                                              int wave, int lane, uint32_t vm[kRowsPerWave],
+// packed 8-bit medians in vm[].  `wave` is wave-uniform.
+//
+// Aligned scenes take the vector walk, fully unrolled with a 3-row prefetch
+// ring that holds the first rows on entry (walk_prefetch); at the scene's
+// right edge the loads move left and `sel` clamps the columns.  Scenes whose
+// base or pitch is not aligned take the element walk: a rolled loop of element
+// loads that waits for each row, slower but small.
+template <typename T, bool FAST24>
+__device__ __forceinline__ void filter_phase1(const Shared& sh, const Walk<T>& wk, bool vec,
+                                              FilterLds& s, int32_t ch, int32_t cw, int wave,
+                                              int lane, uint32_t vm[kRowsPerWave],
                                               Raw<T> (&ring)[kPrefetch]) {
-  const Walk<T> wk(sc, y0, x0, wave, lane);
   const bool down = wk.down;
   const int32_t wy0 = wave * kRowsPerWave;
-
-  // columns of this lane that lie inside the chip
-  const int valid_cols = min(max(cw - 4 * lane, 0), 4);
+  // histogram increments of the lane's 4 columns: 1 inside the chip, else 0
+  uint32_t inc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) inc[j] = 4 * lane + j < cw ? 1u : 0u;
   const uint32_t hist_lane = (uint32_t)(lane & (kCopies - 1));
-
+  // rows of output step k inside the chip (wave-uniform)
+  auto rowmask = [&](int k) {
+    return wy0 + (down ? k : kRowsPerWave - 1 - k) < ch ? ~0u : 0u;
+  };
   uint32_t w0[6], w1[6] = {0, 0, 0, 0, 0, 0}, w2[6] = {0, 0, 0, 0, 0, 0};
 
+  if (vec) {
 #pragma unroll
-  for (int st = 0; st < kRowsPerWave + 2; ++st) {
-    uint32_t x[4];
-    const Raw<T>& cur = ring[st % kPrefetch];
-    max_bands<T>(cur, x);
-    // lane 0 takes the left halo, lane 63 the right one (as the DPP fill value)
-    const uint32_t hv = max3u(cur.h[0], cur.h[1], cur.h[2]);
-    if (st + kPrefetch < kRowsPerWave + 2) load_step<T, VEC>(wk, st + kPrefetch, ring[st % kPrefetch]);
-
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      w0[c] = w1[c];
-      w1[c] = w2[c];
+    for (int st = 0; st < kRowsPerWave + 2; ++st) {
+      const Raw<T> cur = ring[st % kPrefetch];
+      if (st + kPrefetch < kRowsPerWave + 2)
+        load_step<T, true>(wk, st + kPrefetch, ring[st % kPrefetch]);
+      const uint32_t packed = walk_row<T, FAST24, true>(
+          sh, s, cur, wk.sel, w0, w1, w2, st >= 2, st >= 2 ? rowmask(st - 2) : 0u, inc, hist_lane);
+      if (st >= 2) vm[st - 2] = packed;
     }
-    w2[0] = from_left(x[3], hv);
-    w2[1] = x[0];
-    w2[2] = x[1];
-    w2[3] = x[2];
-    w2[4] = x[3];
-    w2[5] = from_right(x[0], hv);
-    if (st < 2) continue;
-
-    // output row of this step (chip-relative)
-    const int k = st - 2;
-    const int32_t rout = wy0 + (down ? k : kRowsPerWave - 1 - k);
-    const int nvalid = rout < ch ? valid_cols : 0;
-
-    uint32_t lo[6], mi[6], hi[6];
+  } else {
+#pragma unroll 1
+    for (int st = 0; st < kRowsPerWave + 2; ++st) {
+      Raw<T> cur;
+      load_step<T, false>(wk, st, cur);
+      const uint32_t packed = walk_row<T, FAST24, false>(
+          sh, s, cur, nullptr, w0, w1, w2, st >= 2, st >= 2 ? rowmask(st - 2) : 0u, inc, hist_lane);
+      if (st >= 2) {
+        // static register indices in a rolled loop: shift the medians down
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      lo[c] = vmin3(w0[c], w1[c], w2[c]);
-      mi[c] = vmed3(w0[c], w1[c], w2[c]);
-      hi[c] = vmax3(w0[c], w1[c], w2[c]);
+        for (int k = 0; k + 1 < kRowsPerWave; ++k) vm[k] = vm[k + 1];
+        vm[kRowsPerWave - 1] = packed;
+      }
     }
-    uint32_t packed = 0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      uint32_t m = vmed3(vmax3(lo[j], lo[j + 1], lo[j + 2]), vmed3(mi[j], mi[j + 1], mi[j + 2]),
-                         vmin3(hi[j], hi[j + 1], hi[j + 2]));
-      uint32_t v = rescale<T>(m, sh, FAST24);
-      atomicAdd(&s.hist[(v << 5) | hist_lane], FULL || j < nvalid ? 1u : 0u);
-      packed |= v << (8 * j);
-    }
-    vm[k] = packed;
   }
 }
 
@@ -663,44 +727,31 @@ __device__ __forceinline__ void zero_hist(FilterLds& s, int t0, int nt) {
   for (int i = t0; i < 256 * kCopies / 4; i += nt) ((uint4*)s.hist)[i] = make_uint4(0, 0, 0, 0);
 }
 
-// One chip, all three phases, by the whole workgroup.
-template <typename T, bool FAST24>
+// One chip, all three phases, by the whole workgroup.  PIX: patch counts per
+// pixel (patches that do not nest with chips); otherwise from the histogram.
+template <typename T, bool FAST24, bool PIX>
 __device__ __forceinline__ void filter_chip(const Shared& sh, const ChipAt& c, FilterLds& s) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const Scene& sc = *c.sc;
   const int32_t y0 = c.y0, x0 = c.x0, ch = c.ch, cw = c.cw;
   const bool active = wave * kRowsPerWave < ch;
-  const bool pix = sh.count_mode >= CM_PIX_LDS;
-  const bool pix_lds = sh.count_mode == CM_PIX_LDS;
-  // whole-vector loads need aligned rows and every lane's 4 columns inside the scene
-  const bool vec = sc.vec && x0 + 4 * 64 <= sc.W;
+  constexpr bool pix = PIX;
+  const bool pix_lds = PIX && sh.count_mode == CM_PIX_LDS;
+  // whole-vector loads need aligned rows (the walk clamps the right edge)
+  const bool vec = sc.vec != 0;
 
   // the walk's first rows are in flight while the histogram is cleared
   Raw<T> ring[kPrefetch];
   const Walk<T> wk(sc, y0, x0, wave, lane);
-  if (active) {
-    if (vec)
-      walk_prefetch<T, true>(wk, ring);
-    else
-      walk_prefetch<T, false>(wk, ring);
-  }
+  if (active && vec) walk_prefetch<T>(wk, ring);
   zero_hist(s, threadIdx.x, kThreads);
   if (pix_lds)
     for (int i = threadIdx.x; i < sh.npy_l * sh.npx_l * 3; i += kThreads) s.cnt[i] = 0;
   __syncthreads();
 
   uint32_t vm[kRowsPerWave];
-  if (active) {
-    // whole chips (every column, and every row of this wave, inside the
-    // scene) skip the per-pixel validity masks
-    if (vec && cw == kTile && (wave + 1) * kRowsPerWave <= ch)
-      filter_phase1<T, true, FAST24, true>(sh, sc, s, y0, x0, ch, cw, wave, lane, vm, ring);
-    else if (vec)
-      filter_phase1<T, true, FAST24, false>(sh, sc, s, y0, x0, ch, cw, wave, lane, vm, ring);
-    else
-      filter_phase1<T, false, FAST24, false>(sh, sc, s, y0, x0, ch, cw, wave, lane, vm, ring);
-  }
+  if (active) filter_phase1<T, FAST24>(sh, wk, vec, s, ch, cw, wave, lane, vm, ring);
   __syncthreads();
 
   if (threadIdx.x < 256) {
@@ -723,7 +774,7 @@ __device__ __forceinline__ void filter_chip(const Shared& sh, const ChipAt& c, F
     const bool vec4 = sc.label_vec != 0;
     PixCount pc{-1, 0};
     int32_t colkey[4] = {0, 0, 0, 0};
-    if (pix) {
+    if constexpr (pix) {
       const int32_t px_base = pix_lds ? x0 / sh.pw : 0;
 #pragma unroll
       for (int j = 0; j < 4; ++j) colkey[j] = min(gx + j, sc.W - 1) / sh.pw - px_base;
@@ -740,14 +791,14 @@ __device__ __forceinline__ void filter_chip(const Shared& sh, const ChipAt& c, F
       const uint32_t packed = cls[0] | (cls[1] << 8) | (cls[2] << 16) | (cls[3] << 24);
       if (valid_cols > 0)
         store_labels(sc.labels + (int64_t)gy * sc.lpitch, loff, valid_cols, vec4, packed);
-      if (pix) {
+      if constexpr (pix) {
         const int32_t py = gy / sh.ph - (pix_lds ? y0 / sh.ph : 0);
         const int32_t rowkey = py * (pix_lds ? sh.npx_l : sc.nx);
         for (int j = 0; j < valid_cols; ++j)
           pix_add(sc, s.cnt, pix_lds, pc, rowkey + colkey[j], cls[j]);
       }
     }
-    if (pix) pix_flush(sc, s.cnt, pix_lds, pc.key, pc.cnt);
+    if constexpr (pix) pix_flush(sc, s.cnt, pix_lds, pc.key, pc.cnt);
   }
   if (pix_lds) {
     __syncthreads();
@@ -755,13 +806,13 @@ __device__ __forceinline__ void filter_chip(const Shared& sh, const ChipAt& c, F
   }
 }
 
-template <typename T, bool FAST24>
+template <typename T, bool FAST24, bool PIX>
 __global__ __launch_bounds__(kThreads, SIL_WAVES_PER_EU) void k_filter(Shared sh, Scene sc,
                                                                        int per_xcd) {
   __shared__ FilterLds s;
   const int chip_id = xcd_work_index(per_xcd);
   if (chip_id >= sc.nchips) return;
-  filter_chip<T, FAST24>(sh, chip_at(sh, sc, chip_id), s);
+  filter_chip<T, FAST24, PIX>(sh, chip_at(sh, sc, chip_id), s);
 }
 
 // Chips of up to kMaxBatch scenes in one launch: scene j contributes chips
@@ -774,7 +825,7 @@ __global__ __launch_bounds__(kThreads, SIL_WAVES_PER_EU) void k_filter_batch(Sha
   int j = 0;
   while (j + 1 < bt.n && bt.prefix[j + 1] <= i) ++j;
   const Scene& sc = bt.sc[j];
-  filter_chip<T, FAST24>(sh, chip_at(sh, sc, sc.chip_begin + (i - bt.prefix[j])), s);
+  filter_chip<T, FAST24, false>(sh, chip_at(sh, sc, sc.chip_begin + (i - bt.prefix[j])), s);
 }
 
 // ---- filter = 0: thresholds only ----------------------------------------------
@@ -1049,10 +1100,15 @@ void launch_single(const Shared& sh, const Scene& sc, bool fast24, int filter, i
                    hipStream_t stream) {
   const dim3 grid(per_xcd * 8), block(kThreads);
   if (filter == 1) {
-    if (fast24)
-      hipLaunchKernelGGL((k_filter<T, true>), grid, block, 0, stream, sh, sc, per_xcd);
+    const bool pix = sh.count_mode >= CM_PIX_LDS;
+    if (fast24 && !pix)
+      hipLaunchKernelGGL((k_filter<T, true, false>), grid, block, 0, stream, sh, sc, per_xcd);
+    else if (fast24)
+      hipLaunchKernelGGL((k_filter<T, true, true>), grid, block, 0, stream, sh, sc, per_xcd);
+    else if (!pix)
+      hipLaunchKernelGGL((k_filter<T, false, false>), grid, block, 0, stream, sh, sc, per_xcd);
     else
-      hipLaunchKernelGGL((k_filter<T, false>), grid, block, 0, stream, sh, sc, per_xcd);
+      hipLaunchKernelGGL((k_filter<T, false, true>), grid, block, 0, stream, sh, sc, per_xcd);
   } else {
     hipLaunchKernelGGL((k_thresh<T>), grid, block, 0, stream, sh, sc, per_xcd);
   }

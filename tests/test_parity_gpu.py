@@ -121,6 +121,16 @@ RNG_CASES = [
     (999, 1001, "u16", 64, 128, 192, 1, 0, 0, 0, 0),
     (1031, 517, "u8", 128, 256, 256, 1, 0, 0, 0, 0),
     (260, 4100, "u16", 256, 256, 256, 1, 0, 0, 0, 0),
+    # aligned rows (vector loads) with widths that end inside a lane's 4
+    # columns: the right-edge chips clamp the loaded columns to W-1
+    (300, 901, "u16", 256, 256, 256, 1, 3, 0, 0, 0),
+    (513, 1003, "u16", 256, 256, 256, 1, 1, 0, 0, 0),
+    (257, 1022, "u8", 256, 256, 256, 1, 2, 0, 0, 0),
+    (100, 130, "u16", 256, 256, 256, 1, 2, 0, 0, 0),
+    (37, 53, "u8", 256, 7, 9, 1, 3, 0, 0, 0),
+    (333, 777, "u16", 64, 64, 64, 1, 3, 0, 0, 0),
+    (70, 4, "u16", 256, 256, 256, 1, 0, 0, 0, 0),
+    (90, 5, "u8", 3, 256, 256, 1, 3, 0, 0, 0),
 ]
 
 
