@@ -72,7 +72,7 @@ struct ExArgs {
   int32_t out_vec;         // mask and colour rows 4-byte aligned
   int32_t lut_lds;         // pass C tiles stage their chips' tables in LDS
   int32_t hs_all;          // every mask admits every hue and saturation
-  int64_t vm_pitch;        // row pitch of the median plane (multiple of 16)
+  int64_t vm_pitch;        // row pitch of the median plane (multiple of 128)
   uint8_t* vm;             // workspace: [H][vm_pitch] median plane
   uint32_t* hist;          // workspace: [nchips][256]
   uint8_t* lut;            // workspace: [nchips][256] median -> filtered value
@@ -237,8 +237,8 @@ __global__ __launch_bounds__(kThreads) void k_ex_median(ExArgs a, int32_t parts)
                        med3u(md3[j], md3[j + 1], md3[j + 2]),
                        min3u(hi3[j], hi3[j + 1], hi3[j + 2]));
         if (nv == 4 && (tx & 3) == 0) {
-          *(uint32_t*)(out + (int64_t)r * a.vm_pitch) =
-              m[0] | (m[1] << 8) | (m[2] << 16) | (m[3] << 24);
+          __builtin_nontemporal_store(m[0] | (m[1] << 8) | (m[2] << 16) | (m[3] << 24),
+                                      (uint32_t*)(out + (int64_t)r * a.vm_pitch));
         } else {
 #pragma unroll
           for (int j = 0; j < 4; ++j)
@@ -656,7 +656,7 @@ __global__ __launch_bounds__(kThreads) void k_ex_apply(ExArgs a, int32_t ntx, in
       if (nv > 0) {
         uint8_t* mrow = a.masks + (int64_t)y * a.mask_pitch + x;
         if (a.out_vec && nv == 4) {
-          *(uint32_t*)mrow = bits4;
+          __builtin_nontemporal_store(bits4, (uint32_t*)mrow);
         } else {
           for (int j = 0; j < nv; ++j) mrow[j] = (uint8_t)(bits4 >> (8 * j));
         }
@@ -665,7 +665,7 @@ __global__ __launch_bounds__(kThreads) void k_ex_apply(ExArgs a, int32_t ntx, in
           for (int i = 0; i < 3; ++i) {
             uint8_t* crow = a.rgb + ((int64_t)i * a.H + y) * a.rgb_pitch + x;
             if (a.out_vec && nv == 4) {
-              *(uint32_t*)crow = rgbw[i];
+              __builtin_nontemporal_store(rgbw[i], (uint32_t*)crow);
             } else {
               for (int j = 0; j < nv; ++j) crow[j] = (uint8_t)(rgbw[i] >> (8 * j));
             }
@@ -747,7 +747,8 @@ Layout layout(int32_t H, int32_t W, const sil_params* p) {
   const int64_t C = p->chip;
   L.nchips = ((H + C - 1) / C) * ((W + C - 1) / C);
   if (!p->filter) return L;
-  L.vm_pitch = (W + 15) & ~int64_t(15);
+  // 128-byte rows: the median plane is written as whole cache lines
+  L.vm_pitch = (W + 127) & ~int64_t(127);
   L.vm = 0;
   L.hist = align256((int64_t)H * L.vm_pitch);
   L.lut = align256(L.hist + L.nchips * 256 * 4);

@@ -326,7 +326,8 @@ def label_ex(scene: torch.Tensor, params: Optional[Params] = None, sel=(0, 1, 2)
     on the GPU): full-HSV masks, any filter unit, optional filtered colour.
 
     Returns a dict with ``masks`` [H, W] uint8 (bit c = mask c), ``counts``
-    [ny, nx, 3] int32 (if asked), ``rgb`` [3, H, W] uint8 (if asked) and
+    [ny, nx, 3] int32 (if asked), ``rgb`` [3, H, W] uint8 (if asked; masks and
+    colour rows are ``label_pitch_for(W)`` bytes apart unless given) and
     ``chips`` (raw [ncy, ncx, 12] sil_chip_info bytes, if asked).  ``out`` may
     hold preallocated tensors under the same keys; ``workspace`` a uint8 GPU
     tensor of at least ``workspace_bytes`` bytes (allocated here if omitted).
@@ -344,7 +345,7 @@ def label_ex(scene: torch.Tensor, params: Optional[Params] = None, sel=(0, 1, 2)
     out = dict(out or {})
     masks = out.get("masks")
     if masks is None:
-        masks = out["masks"] = torch.empty((H, W), dtype=torch.uint8, device=dev)
+        masks = out["masks"] = alloc_labels(H, W, dev)
     if masks.dtype != torch.uint8 or masks.dim() != 2 or masks.shape[0] != H \
             or masks.shape[1] < W or masks.stride(1) != 1:
         raise ValueError("masks must be uint8 [H, >=W] with unit column stride")
@@ -361,7 +362,8 @@ def label_ex(scene: torch.Tensor, params: Optional[Params] = None, sel=(0, 1, 2)
     if rgb:
         col = out.get("rgb")
         if col is None:
-            col = out["rgb"] = torch.empty((3, H, W), dtype=torch.uint8, device=dev)
+            col = out["rgb"] = torch.empty((3, H, label_pitch_for(W)), dtype=torch.uint8,
+                                           device=dev)[:, :, :W]
         if col.dtype != torch.uint8 or col.dim() != 3 or col.shape[0] != 3 \
                 or col.shape[1] != H or col.shape[2] < W or col.stride(2) != 1 \
                 or col.stride(0) != H * col.stride(1):
