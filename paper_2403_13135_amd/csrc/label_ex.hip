@@ -43,6 +43,9 @@
 
 namespace {
 
+#include "chip_walk.h"
+#include "rescale.h"
+
 constexpr int kThreads = 256;     // threads per block of passes A and C
 constexpr int kTR = 16;           // pass A tile rows
 constexpr int kTW = 4 * kThreads; // tile columns: 4 per thread
@@ -62,6 +65,9 @@ struct ExArgs {
   float rd;                // 1 / refl_max
   uint32_t magic, shift;   // floor(n / refl_max) = mulhi(n, magic) >> shift below sat_n
   int32_t use_magic;
+  // the chip walk's rescale (rescale.h): valid when fast24 is set
+  uint32_t x_sat, magic24, shift24;
+  int32_t fast24;
   int32_t filter;
   int32_t chip, ncx, nchips;
   int32_t ph, pw, nx;
@@ -260,6 +266,76 @@ __global__ __launch_bounds__(kThreads) void k_ex_median(ExArgs a, int32_t parts)
 #pragma unroll
   for (int k = 0; k < 8; ++k) sum += sh[k][tid];
   if (sum) atomicAdd(&a.hist[(int64_t)chip_id * 256 + tid], sum);
+}
+
+// Pass A for chips of 128 columns or more: 512-thread workgroups own 256 x 256
+// tiles of one chip (a chip of side c has ceil(c/256)^2 of them) and run the
+// fused labeller's chip walk over them (chip_walk.h): each wave walks 32 rows
+// with a 3-row prefetch ring, medians in registers, a 32-copy LDS histogram.
+// The tile's medians are then written to the median plane with nontemporal
+// stores, and its histogram is added to the chip's.  Workgroup b serves XCD
+// b mod 8, which owns a contiguous run of tiles.
+constexpr int kWalkThreads = 512;
+constexpr int kWalkTile = kWalkThreads / 64 * kWalkRows;  // 256
+
+template <typename T>
+__global__ __launch_bounds__(kWalkThreads, 4) void k_ex_walk(ExArgs a, int32_t tpc, int32_t ntx,
+                                                             int32_t per_xcd) {
+  __shared__ uint32_t hist[256 * kWalkCopies];
+  const int32_t u = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (u >= a.nchips * tpc) return;
+  const int32_t chip_id = u / tpc, part = u - chip_id * tpc;
+  const int32_t cy = chip_id / a.ncx, cx = chip_id - cy * a.ncx;
+  const int32_t y0 = cy * a.chip, x0 = cx * a.chip;
+  const int32_t ch = min(a.chip, a.H - y0), cw = min(a.chip, a.W - x0);
+  const int32_t ty = y0 + (part / ntx) * kWalkTile, tx = x0 + (part % ntx) * kWalkTile;
+  const int32_t th = min(kWalkTile, y0 + ch - ty), tw = min(kWalkTile, x0 + cw - tx);
+  if (th <= 0 || tw <= 0) return;  // edge chips have fewer tiles (uniform per block)
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const bool active = wave * kWalkRows < th;
+  const bool vec = a.in_vec && (tx & 3) == 0;
+  const char* const planes[3] = {(const char*)a.band[0], (const char*)a.band[1],
+                                 (const char*)a.band[2]};
+  const Walk<T> wk(planes, a.pitch_b, a.H, a.W, ty, tx, wave, lane);
+  Raw<T> ring[kWalkPrefetch];
+  if (active && vec) walk_prefetch<T>(wk, ring);
+  for (int i = threadIdx.x; i < 256 * kWalkCopies / 4; i += kWalkThreads)
+    ((uint4*)hist)[i] = make_uint4(0, 0, 0, 0);
+  __syncthreads();
+
+  if (active) {
+    uint32_t vm[kWalkRows];
+    // the rescale by 24-bit multiplies (the host launches this pass for
+    // 16-bit scenes only when those constants exist for refl_max)
+    walk_wave<T>(wk, vec, hist, th, tw, wave, lane, vm, ring, [&](uint32_t m) {
+      if constexpr (sizeof(T) == 1) return m;
+      return rescale24(m, a.x_sat, a.half, a.magic24, a.shift24);
+    });
+    const int32_t wy0 = wave * kWalkRows;
+    const int nv = min(max(tw - 4 * lane, 0), 4);
+    uint8_t* const col = a.vm + tx + 4 * lane;
+#pragma unroll
+    for (int k = 0; k < kWalkRows; ++k) {
+      const int32_t r = wy0 + (wk.down ? k : kWalkRows - 1 - k);
+      if (r >= th || nv == 0) continue;
+      uint8_t* const q = col + (int64_t)(ty + r) * a.vm_pitch;
+      if (nv == 4 && (tx & 3) == 0) {
+        __builtin_nontemporal_store(vm[k], (uint32_t*)q);
+      } else {
+        for (int j = 0; j < nv; ++j) q[j] = (uint8_t)(vm[k] >> (8 * j));
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 256) {
+    const uint32_t bin = threadIdx.x;
+    uint32_t sum = 0;
+#pragma unroll 8
+    for (uint32_t k = 0; k < kWalkCopies; ++k) sum += hist[(bin << 5) | ((k + bin) & 31u)];
+    if (sum) atomicAdd(&a.hist[(int64_t)chip_id * 256 + bin], sum);
+  }
 }
 
 // ---- pass B: per-chip statistics -------------------------------------------------
@@ -822,6 +898,15 @@ int sil_label_ex(const void* scene, int32_t nbands, const int32_t sel[3], int32_
   a.sat_n = 255u * p->refl_max;
   a.rd = 1.0f / (float)(p->refl_max ? p->refl_max : 1);
   if (esz == 2) a.use_magic = derive_magic(p->refl_max, &a.magic, &a.shift);
+  if (esz == 2) {
+    RescaleConst rc;
+    if (derive_rescale(p->refl_max, &rc) && rc.fast24) {
+      a.x_sat = rc.x_sat;
+      a.magic24 = rc.magic;
+      a.shift24 = rc.shift;
+      a.fast24 = 1;
+    }
+  }
   a.filter = (int32_t)p->filter;
   a.chip = (int32_t)std::min<int64_t>(p->chip, std::max(H, W));
   a.ncx = (int32_t)((W + (int64_t)p->chip - 1) / p->chip);
@@ -870,8 +955,25 @@ int sil_label_ex(const void* scene, int32_t nbands, const int32_t sel[3], int32_
     const int64_t nh = L.nchips * 256;
     hipLaunchKernelGGL(k_ex_fill, dim3((unsigned)std::min<int64_t>((nh + 255) / 256, 4096)),
                        dim3(256), 0, st, a.hist, nh);
-    // the narrowest tile width that spans a chip
     const int64_t cwid = std::min<int64_t>(a.chip, W);
+    if (cwid >= 128 && a.pitch_b * (kWalkRows + 2) <= (int64_t)UINT32_MAX &&
+        (!a.u16 || a.fast24)) {
+      // the chip walk over 256 x 256 tiles (its 34-row window is addressed
+      // with 32-bit offsets)
+      const int32_t ntx = (int32_t)((cwid + kWalkTile - 1) / kWalkTile);
+      const int32_t nty = (int32_t)((std::min<int64_t>(a.chip, H) + kWalkTile - 1) / kWalkTile);
+      const int64_t units = (int64_t)L.nchips * ntx * nty;
+      const int32_t per_xcd = (int32_t)((units + 7) / 8);
+      const dim3 wgrid((unsigned)(per_xcd * 8));
+      if (a.u16)
+        hipLaunchKernelGGL(k_ex_walk<uint16_t>, wgrid, dim3(kWalkThreads), 0, st, a, ntx * nty,
+                           ntx, per_xcd);
+      else
+        hipLaunchKernelGGL(k_ex_walk<uint8_t>, wgrid, dim3(kWalkThreads), 0, st, a, ntx * nty,
+                           ntx, per_xcd);
+      hipLaunchKernelGGL(k_ex_stats, dim3((unsigned)L.nchips), dim3(64), 0, st, a);
+    } else {
+    // the narrowest tile width that spans a chip
     const int tw = cwid <= 256 ? 256 : (cwid <= 512 ? 512 : kTW);
     const int64_t th = (int64_t)kTR * (kTW / tw);
     const int64_t tiles_per_chip = ((std::min<int64_t>(a.chip, H) + th - 1) / th) *
@@ -886,6 +988,7 @@ int sil_label_ex(const void* scene, int32_t nbands, const int32_t sel[3], int32_
     else
       hipLaunchKernelGGL(k_ex_median<kTW>, grid, dim3(kThreads), 0, st, a, parts);
     hipLaunchKernelGGL(k_ex_stats, dim3((unsigned)L.nchips), dim3(64), 0, st, a);
+    }
   }
   if (counts) {
     const int64_t nc = ny * a.nx * 3;

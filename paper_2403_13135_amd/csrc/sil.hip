@@ -43,15 +43,15 @@
 
 namespace {
 
+#include "chip_walk.h"
+#include "rescale.h"
+
 constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / 64;
-constexpr int kRowsPerWave = 32;
+constexpr int kRowsPerWave = kWalkRows;
 constexpr int kTile = kWaves * kRowsPerWave;  // 256: chip side handled per workgroup
-constexpr int kCopies = 32;                   // LDS histogram copies
+constexpr int kCopies = kWalkCopies;          // LDS histogram copies
 constexpr int kMaxPatchSlots = 1024;          // LDS per-patch counters per workgroup
-#ifndef SIL_PREFETCH
-#define SIL_PREFETCH 3
-#endif
 #ifndef SIL_WAVES_PER_EU
 #define SIL_WAVES_PER_EU 4
 #endif
@@ -60,7 +60,7 @@ constexpr int kMaxPatchSlots = 1024;          // LDS per-patch counters per work
 #ifndef SIL_NT_LABELS
 #define SIL_NT_LABELS 1
 #endif
-constexpr int kPrefetch = SIL_PREFETCH;       // rows of loads in flight per wave
+constexpr int kPrefetch = kWalkPrefetch;      // rows of loads in flight per wave
 constexpr int kMaxBatch = SIL_BATCH_MAX_JOBS; // scenes per batched launch
 
 enum CountMode : uint32_t {
@@ -118,37 +118,6 @@ __device__ __forceinline__ uint32_t med3u(uint32_t a, uint32_t b, uint32_t c) {
   return max(min(a, b), min(max(a, b), c));
 }
 
-// The same three order statistics as single VOP3 instructions.  Written out so
-// that the compiler does not split them into two-operand min/max chains to
-// share partial results between neighbouring rows, which costs more issue
-// slots than the three-operand forms.
-__device__ __forceinline__ uint32_t vmin3(uint32_t a, uint32_t b, uint32_t c) {
-  uint32_t r;
-  asm("v_min3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
-  return r;
-}
-__device__ __forceinline__ uint32_t vmax3(uint32_t a, uint32_t b, uint32_t c) {
-  uint32_t r;
-  asm("v_max3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
-  return r;
-}
-__device__ __forceinline__ uint32_t vmed3(uint32_t a, uint32_t b, uint32_t c) {
-  uint32_t r;
-  asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
-  return r;
-}
-
-// Lane i receives lane i-1's value; lane 0 receives `edge`.
-__device__ __forceinline__ uint32_t from_left(uint32_t v, uint32_t edge) {
-  return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, 0x138 /*wave_shr:1*/, 0xF,
-                                               0xF, false);
-}
-// Lane i receives lane i+1's value; lane 63 receives `edge`.
-__device__ __forceinline__ uint32_t from_right(uint32_t v, uint32_t edge) {
-  return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, 0x130 /*wave_shl:1*/, 0xF,
-                                               0xF, false);
-}
-
 // Workgroup id -> logical work index: XCD k = id % 8 gets the contiguous run
 // [k * per_xcd, (k+1) * per_xcd) in order.
 __device__ __forceinline__ int xcd_work_index(int per_xcd) {
@@ -161,14 +130,7 @@ __device__ __forceinline__ uint32_t rescale(uint32_t x, const Shared& sh, bool f
   if constexpr (sizeof(T) == 1) {
     return x;
   } else {
-    if (fast24) {
-      // n < 2^24, magic < 2^24 and shift >= 32 (checked on the host): a 24-bit
-      // multiply-add, the high word of a 24 x 24-bit product and a 32-bit shift
-      uint32_t n;
-      asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(n) : "v"(min(x, sh.x_sat)), "v"(255u), "v"(sh.half));
-      const uint64_t p = (uint64_t)(n & 0xFFFFFFu) * (uint64_t)(sh.magic & 0xFFFFFFu);
-      return (uint32_t)(p >> 32) >> (sh.shift - 32u);
-    }
+    if (fast24) return rescale24(x, sh.x_sat, sh.half, sh.magic, sh.shift);
     const uint32_t n = min(x, sh.x_sat) * 255u + sh.half;
     return (uint32_t)(((uint64_t)n * sh.magic) >> sh.shift);
   }
@@ -178,24 +140,6 @@ __device__ __forceinline__ uint32_t rescale(uint32_t x, const Shared& sh, bool f
 //
 // Row bases are wave-uniform (scalar registers); each lane adds a 32-bit byte
 // offset, so every load is a scalar-base + vector-offset global load.
-
-// Raw 4-pixel row segments of the three bands, plus one halo pixel per band
-// (lanes 0-31 fetch the chip's left halo column, lanes 32-63 its right one,
-// so every halo load instruction touches only two cache lines).  The four
-// pixels of a band are packed as they lie in memory: two per 32-bit word for
-// 16-bit scenes, four per word for 8-bit ones.
-template <typename T>
-struct Raw;
-template <>
-struct Raw<uint16_t> {
-  uint2 v[3];
-  uint32_t h[3];
-};
-template <>
-struct Raw<uint8_t> {
-  uint32_t v[3];
-  uint32_t h[3];
-};
 
 // Row gy (wave-uniform).  VEC: one aligned vector per band at coff[0] (the
 // caller guarantees the 4 columns lie inside the scene).  Otherwise element
@@ -222,41 +166,6 @@ __device__ __forceinline__ void load_raw(const Scene& sc, int32_t gy, const uint
         r.v[b] = e[0] | (e[1] << 8) | (e[2] << 16) | (e[3] << 24);
     }
     r.h[b] = *(const T*)(rb + hoff);
-  }
-}
-
-// max over the three bands, 4 pixels.  PERM: first rearrange the 4 pixels
-// by the byte selectors `sel` (v_perm_b32; see Walk).
-template <typename T, bool PERM = false>
-__device__ __forceinline__ void max_bands(const Raw<T>& r, uint32_t x[4],
-                                          const uint32_t* sel = nullptr) {
-  if constexpr (sizeof(T) == 2) {
-    // two pixels per register: packed 16-bit maxima, then unpack
-    typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-    auto pmax = [](uint32_t a, uint32_t b, uint32_t c) {
-      const u16x2 m = __builtin_elementwise_max(
-          __builtin_elementwise_max(__builtin_bit_cast(u16x2, a), __builtin_bit_cast(u16x2, b)),
-          __builtin_bit_cast(u16x2, c));
-      return __builtin_bit_cast(uint32_t, m);
-    };
-    uint32_t m01 = pmax(r.v[0].x, r.v[1].x, r.v[2].x);
-    uint32_t m23 = pmax(r.v[0].y, r.v[1].y, r.v[2].y);
-    if constexpr (PERM) {
-      const uint32_t a = __builtin_amdgcn_perm(m23, m01, sel[0]);
-      m23 = __builtin_amdgcn_perm(m23, m01, sel[1]);
-      m01 = a;
-    }
-    x[0] = m01 & 0xFFFFu;
-    x[1] = m01 >> 16;
-    x[2] = m23 & 0xFFFFu;
-    x[3] = m23 >> 16;
-  } else {
-    uint32_t v[3];
-#pragma unroll
-    for (int b = 0; b < 3; ++b) v[b] = PERM ? __builtin_amdgcn_perm(r.v[b], r.v[b], sel[0]) : r.v[b];
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      x[j] = max3u((v[0] >> (8 * j)) & 0xFFu, (v[1] >> (8 * j)) & 0xFFu, (v[2] >> (8 * j)) & 0xFFu);
   }
 }
 
@@ -364,197 +273,6 @@ struct FilterLds {
   uint32_t cnt[kMaxPatchSlots * 3];
   uint8_t lut[256];
 };
-
-// Addresses of one wave's walk over a chip: 34 input rows, chip rows -1..32
-// of the wave's band (down) or 32..-1 (up), clamped into the scene; the lane's
-// four column offsets and its halo column (lanes 0-31 the chip's left halo
-// column, lanes 32-63 its right one), also clamped.  Rows are addressed from
-// the walk's first row in each band: a wave-uniform 64-bit base per band plus
-// a 32-bit per-lane offset (the walk spans 34 rows, and the host checks that
-// 34 row pitches fit in 32 bits), so each load is a scalar-base +
-// vector-offset load and the walk keeps few scalar registers live.
-template <typename T>
-struct Walk {
-  const char* band[3];  // row `top` of each band
-  int32_t base, top, last;
-  uint32_t pitch;
-  bool down;
-  uint32_t coff[4];
-  uint32_t hoff;
-  // Vector loads (aligned scenes): each lane loads the aligned group of 4
-  // columns at vcol, moved left so that it ends inside the scene's padded row
-  // (the last group that holds column W-1), and `sel` rearranges the loaded
-  // pixels so that column c reads column min(c, W-1), the clamped border.
-  // Both are the identity away from the scene's right edge.
-  uint32_t vcol;
-  uint32_t sel[2];
-  __device__ __forceinline__ Walk(const Scene& sc, int32_t y0, int32_t x0, int wave, int lane) {
-    down = (wave & 1) == 0;
-    base = y0 + wave * kRowsPerWave;
-    last = sc.H - 1;
-    top = min(max(base - 1, 0), last);
-    pitch = (uint32_t)sc.pitch;
-    const char* row = sc.scene + (int64_t)top * sc.pitch;
-#pragma unroll
-    for (int b = 0; b < 3; ++b) band[b] = row + sc.off[b];
-    const int32_t gx = x0 + 4 * lane;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) coff[j] = (uint32_t)(min(gx + j, sc.W - 1) * (int)sizeof(T));
-    hoff = (uint32_t)(min(max(lane < 32 ? x0 - 1 : x0 + 4 * 64, 0), sc.W - 1) * (int)sizeof(T));
-    const int32_t g = min(gx, (sc.W - 1) & ~3);  // first column of the loaded group
-    vcol = (uint32_t)(g * (int)sizeof(T));
-    uint32_t o[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) o[j] = (uint32_t)(min(gx + j, sc.W - 1) - g);
-    if constexpr (sizeof(T) == 2) {
-      // byte selectors over {hi word : lo word} of two packed 16-bit pairs
-      sel[0] = (2 * o[0]) | ((2 * o[0] + 1) << 8) | ((2 * o[1]) << 16) | ((2 * o[1] + 1) << 24);
-      sel[1] = (2 * o[2]) | ((2 * o[2] + 1) << 8) | ((2 * o[3]) << 16) | ((2 * o[3] + 1) << 24);
-    } else {
-      sel[0] = o[0] | (o[1] << 8) | (o[2] << 16) | (o[3] << 24);
-      sel[1] = 0;
-    }
-  }
-  // byte offset, from row `top`, of the input row of walk step st (0..33)
-  __device__ __forceinline__ uint32_t roff(int st) const {
-    const int32_t r = down ? st - 1 : kRowsPerWave - st;
-    return (uint32_t)(min(max(base + r, 0), last) - top) * pitch;
-  }
-};
-
-// Walk step st into r.  VEC: one aligned vector per band at vcol (aligned
-// scenes; max_bands applies `sel`).  Otherwise element loads at the 4
-// (clamped) column offsets, packed the same way.
-template <typename T, bool VEC>
-__device__ __forceinline__ void load_step(const Walk<T>& wk, int st, Raw<T>& r) {
-  const uint32_t ro = wk.roff(st);
-#pragma unroll
-  for (int b = 0; b < 3; ++b) {
-    const char* rb = wk.band[b];
-    if constexpr (VEC) {
-      if constexpr (sizeof(T) == 2)
-        r.v[b] = *(const uint2*)(rb + (ro + wk.vcol));
-      else
-        r.v[b] = *(const uint32_t*)(rb + (ro + wk.vcol));
-    } else {
-      uint32_t e[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) e[j] = *(const T*)(rb + (ro + wk.coff[j]));
-      if constexpr (sizeof(T) == 2)
-        r.v[b] = make_uint2(e[0] | (e[1] << 16), e[2] | (e[3] << 16));
-      else
-        r.v[b] = e[0] | (e[1] << 8) | (e[2] << 16) | (e[3] << 24);
-    }
-    r.h[b] = *(const T*)(rb + (ro + wk.hoff));
-  }
-}
-
-// The first kPrefetch rows of a walk (the loads phase 1 starts with).
-template <typename T>
-__device__ __forceinline__ void walk_prefetch(const Walk<T>& wk, Raw<T> (&ring)[kPrefetch]) {
-#pragma unroll
-  for (int p = 0; p < kPrefetch; ++p) load_step<T, true>(wk, p, ring[p]);
-}
-
-// One step of a wave's walk: take row `cur` into the three-row window of
-// band maxima (horizontal neighbours from the adjacent lanes, the chip's halo
-// columns from lanes 0 and 63); from step 2 on, the window's middle row gives
-// an output row: 3x3 median, rescale, histogram (adding inc & rowmask per
-// pixel: 1 for pixels inside the chip), and the packed 8-bit medians.
-template <typename T, bool FAST24, bool PERM>
-__device__ __forceinline__ uint32_t walk_row(const Shared& sh, FilterLds& s, const Raw<T>& cur,
-                                             const uint32_t* sel, uint32_t (&w0)[6],
-                                             uint32_t (&w1)[6], uint32_t (&w2)[6], bool out,
-                                             uint32_t rowmask, const uint32_t inc[4],
-                                             uint32_t hist_lane) {
-  uint32_t x[4];
-  max_bands<T, PERM>(cur, x, sel);
-  // lane 0 takes the left halo, lane 63 the right one (as the DPP fill value)
-  const uint32_t hv = max3u(cur.h[0], cur.h[1], cur.h[2]);
-#pragma unroll
-  for (int c = 0; c < 6; ++c) {
-    w0[c] = w1[c];
-    w1[c] = w2[c];
-  }
-  w2[0] = from_left(x[3], hv);
-  w2[1] = x[0];
-  w2[2] = x[1];
-  w2[3] = x[2];
-  w2[4] = x[3];
-  w2[5] = from_right(x[0], hv);
-  if (!out) return 0;
-
-  uint32_t lo[6], mi[6], hi[6];
-#pragma unroll
-  for (int c = 0; c < 6; ++c) {
-    lo[c] = vmin3(w0[c], w1[c], w2[c]);
-    mi[c] = vmed3(w0[c], w1[c], w2[c]);
-    hi[c] = vmax3(w0[c], w1[c], w2[c]);
-  }
-  uint32_t packed = 0;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    uint32_t m = vmed3(vmax3(lo[j], lo[j + 1], lo[j + 2]), vmed3(mi[j], mi[j + 1], mi[j + 2]),
-                       vmin3(hi[j], hi[j + 1], hi[j + 2]));
-    uint32_t v = rescale<T>(m, sh, FAST24);
-    atomicAdd(&s.hist[(v << 5) | hist_lane], inc[j] & rowmask);
-    packed |= v << (8 * j);
-  }
-  return packed;
-}
-
-// Phase 1 for one wave: walk 34 rows, median, rescale, histogram, keep the
-// packed 8-bit medians in vm[].  `wave` is wave-uniform.
-//
-// Aligned scenes take the vector walk, fully unrolled with a 3-row prefetch
-// ring that holds the first rows on entry (walk_prefetch); at the scene's
-// right edge the loads move left and `sel` clamps the columns.  Scenes whose
-// base or pitch is not aligned take the element walk: a rolled loop of element
-// loads that waits for each row, slower but small.
-template <typename T, bool FAST24>
-__device__ __forceinline__ void filter_phase1(const Shared& sh, const Walk<T>& wk, bool vec,
-                                              FilterLds& s, int32_t ch, int32_t cw, int wave,
-                                              int lane, uint32_t vm[kRowsPerWave],
-                                              Raw<T> (&ring)[kPrefetch]) {
-  const bool down = wk.down;
-  const int32_t wy0 = wave * kRowsPerWave;
-  // histogram increments of the lane's 4 columns: 1 inside the chip, else 0
-  uint32_t inc[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) inc[j] = 4 * lane + j < cw ? 1u : 0u;
-  const uint32_t hist_lane = (uint32_t)(lane & (kCopies - 1));
-  // rows of output step k inside the chip (wave-uniform)
-  auto rowmask = [&](int k) {
-    return wy0 + (down ? k : kRowsPerWave - 1 - k) < ch ? ~0u : 0u;
-  };
-  uint32_t w0[6], w1[6] = {0, 0, 0, 0, 0, 0}, w2[6] = {0, 0, 0, 0, 0, 0};
-
-  if (vec) {
-#pragma unroll
-    for (int st = 0; st < kRowsPerWave + 2; ++st) {
-      const Raw<T> cur = ring[st % kPrefetch];
-      if (st + kPrefetch < kRowsPerWave + 2)
-        load_step<T, true>(wk, st + kPrefetch, ring[st % kPrefetch]);
-      const uint32_t packed = walk_row<T, FAST24, true>(
-          sh, s, cur, wk.sel, w0, w1, w2, st >= 2, st >= 2 ? rowmask(st - 2) : 0u, inc, hist_lane);
-      if (st >= 2) vm[st - 2] = packed;
-    }
-  } else {
-#pragma unroll 1
-    for (int st = 0; st < kRowsPerWave + 2; ++st) {
-      Raw<T> cur;
-      load_step<T, false>(wk, st, cur);
-      const uint32_t packed = walk_row<T, FAST24, false>(
-          sh, s, cur, nullptr, w0, w1, w2, st >= 2, st >= 2 ? rowmask(st - 2) : 0u, inc, hist_lane);
-      if (st >= 2) {
-        // static register indices in a rolled loop: shift the medians down
-#pragma unroll
-        for (int k = 0; k + 1 < kRowsPerWave; ++k) vm[k] = vm[k + 1];
-        vm[kRowsPerWave - 1] = packed;
-      }
-    }
-  }
-}
 
 // Phase 2: exact chip statistics in one wave; writes the class table.
 __device__ void filter_phase2(const Shared& sh, const Scene& sc, FilterLds& s, int chip_id,
@@ -743,7 +461,9 @@ __device__ __forceinline__ void filter_chip(const Shared& sh, const ChipAt& c, F
 
   // the walk's first rows are in flight while the histogram is cleared
   Raw<T> ring[kPrefetch];
-  const Walk<T> wk(sc, y0, x0, wave, lane);
+  const char* const planes[3] = {sc.scene + sc.off[0], sc.scene + sc.off[1],
+                                 sc.scene + sc.off[2]};
+  const Walk<T> wk(planes, sc.pitch, sc.H, sc.W, y0, x0, wave, lane);
   if (active && vec) walk_prefetch<T>(wk, ring);
   zero_hist(s, threadIdx.x, kThreads);
   if (pix_lds)
@@ -751,7 +471,9 @@ __device__ __forceinline__ void filter_chip(const Shared& sh, const ChipAt& c, F
   __syncthreads();
 
   uint32_t vm[kRowsPerWave];
-  if (active) filter_phase1<T, FAST24>(sh, wk, vec, s, ch, cw, wave, lane, vm, ring);
+  if (active)
+    walk_wave<T>(wk, vec, s.hist, ch, cw, wave, lane, vm, ring,
+                 [&](uint32_t m) { return rescale<T>(m, sh, FAST24); });
   __syncthreads();
 
   if (threadIdx.x < 256) {
@@ -902,69 +624,6 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
 // ---- host side ----------------------------------------------------------------
 
 static_assert(sizeof(Batch) + sizeof(Shared) <= 3584, "kernel arguments must stay under 4 KiB");
-
-// Host copy of the 16->8-bit rescale, used only to derive kernel constants.
-uint32_t host_rescale(uint32_t x, uint32_t d) {
-  uint64_t q = ((uint64_t)x * 255u + d / 2u) / d;
-  return q > 255u ? 255u : (uint32_t)q;
-}
-
-struct RescaleConst {
-  uint32_t d = 0, x_sat = 0, half = 0, magic = 0, shift = 0;
-  bool fast24 = false;
-};
-
-// Division by refl_max as a multiply-shift (Granlund & Montgomery, "Division
-// by invariant integers using multiplication", 1994), verified over every
-// reachable numerator.
-bool derive_rescale(uint32_t d, RescaleConst* rc) {
-  static std::mutex mu;
-  static RescaleConst cache;
-  std::lock_guard<std::mutex> g(mu);
-  if (cache.d == d) {
-    *rc = cache;
-    return true;
-  }
-  RescaleConst r;
-  r.d = d;
-  r.half = d / 2u;
-  uint32_t xs = 0;
-  while (xs < 65535u && host_rescale(xs, d) < 255u) ++xs;
-  r.x_sat = xs;
-  const uint64_t nmax = (uint64_t)xs * 255u + r.half;
-  int nb = 0;
-  while ((nmax >> nb) != 0) ++nb;
-  int l = 0;
-  while ((1ull << l) < d) ++l;
-  auto check = [&](uint64_t m, int s) {
-    for (uint32_t x = 0; x <= xs; ++x) {
-      uint64_t n = (uint64_t)x * 255u + r.half;
-      if (((n * m) >> s) != n / d) return false;
-    }
-    return true;
-  };
-  // prefer a 24-bit magic with shift >= 32 (full-rate 24-bit multiplies and
-  // the product's high word on the device)
-  for (int s = nb + l; s < 64 && !r.fast24; ++s) {
-    uint64_t m = ((1ull << s) + d - 1) / d;
-    if (m >= (1ull << 24)) break;
-    if (s >= 32 && nmax < (1ull << 24) && check(m, s)) {
-      r.magic = (uint32_t)m;
-      r.shift = (uint32_t)s;
-      r.fast24 = true;
-    }
-  }
-  if (!r.fast24) {
-    int s = nb + l;
-    uint64_t m = ((1ull << s) + d - 1) / d;
-    if (m >= (1ull << 32) || !check(m, s)) return false;
-    r.magic = (uint32_t)m;
-    r.shift = (uint32_t)s;
-  }
-  cache = r;
-  *rc = r;
-  return true;
-}
 
 int v_class_table(const sil_params* p, int cls[256]) {
   for (int v = 0; v < 256; ++v) {
