@@ -31,7 +31,9 @@ H = W = 10980
 PITCH = 10980
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_filter_tile10980_traffic.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_2403_13135_amd", "csrc", "sil.hip")
+# the labeller kernel's sources: the kernel file and the headers it includes
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2403_13135_amd", "csrc", n)
+               for n in ("sil.hip", "chip_walk.h", "rescale.h")]
 
 
 def algorithmic_bytes(H, W, ny, nx, in_bytes_per_px=6):
@@ -39,8 +41,11 @@ def algorithmic_bytes(H, W, ny, nx, in_bytes_per_px=6):
 
 
 def kernel_src_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def read_traffic():
