@@ -38,6 +38,7 @@
 #include <string.h>
 
 #include <mutex>
+#include <type_traits>
 
 #include "sil.h"
 
@@ -615,6 +616,86 @@ __global__ __launch_bounds__(kThreads, 4) void k_thresh(Shared sh, Scene sc, int
   }
 }
 
+// filter = 0 with patches that tile-align (each 256 x 256 tile lies in one
+// patch): the tile's rows through the chip walk's loads (32 rows per wave,
+// 3-row prefetch ring, clamped right edge), the class of each pixel from its
+// raw V against the two boundaries, nontemporal label stores, and the tile's
+// class totals from per-lane counters.  STORE: the patch is the tile (plain
+// stores); otherwise atomics into counts the host cleared.
+template <typename T, bool STORE>
+__global__ __launch_bounds__(kThreads, 4) void k_thresh_walk(Shared sh, Scene sc, int per_xcd) {
+  __shared__ uint32_t s_tot[3];
+  const int tile_id = xcd_work_index(per_xcd);
+  if (tile_id >= sc.nchips) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int32_t ty = tile_id / sc.ncx, tx = tile_id - ty * sc.ncx;
+  const int32_t y0 = ty * kTile, x0 = tx * kTile;
+  const int32_t ch = min(kTile, sc.H - y0), cw = min(kTile, sc.W - x0);
+  if (threadIdx.x < 3) s_tot[threadIdx.x] = 0;
+  __syncthreads();
+
+  const int32_t wy0 = wave * kRowsPerWave;
+  if (wy0 < ch) {
+    const char* const planes[3] = {sc.scene + sc.off[0], sc.scene + sc.off[1],
+                                   sc.scene + sc.off[2]};
+    const Walk<T> wk(planes, sc.pitch, sc.H, sc.W, y0, x0, wave, lane);
+    const int nv = min(max(cw - 4 * lane, 0), 4);
+    const uint32_t loff = (uint32_t)(x0 + 4 * lane);
+    const bool vec4 = sc.label_vec != 0;
+    uint32_t cnt = 0;  // three 10-bit class counters (at most 128 pixels per lane)
+    // walk steps 1..32 are the band's rows 0..31 (down) or 31..0 (up)
+    auto one_row = [&](int st, const Raw<T>& cur, auto perm) {
+      uint32_t x[4];
+      max_bands<T, decltype(perm)::value>(cur, x, wk.sel);
+      const int32_t r = wy0 + (wk.down ? st - 1 : kRowsPerWave - st);
+      if (r >= ch) return;  // wave-uniform
+      uint32_t packed = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t c = (x[j] >= sh.X1) + (x[j] >= sh.X2);
+        packed |= c << (8 * j);
+        cnt += j < nv ? 1u << (10 * c) : 0u;
+      }
+      if (nv > 0) store_labels(sc.labels + (int64_t)(y0 + r) * sc.lpitch, loff, nv, vec4, packed);
+    };
+    if (sc.vec) {
+      Raw<T> ring[kPrefetch];
+#pragma unroll
+      for (int p = 0; p < kPrefetch; ++p) load_step<T, true>(wk, 1 + p, ring[p]);
+#pragma unroll
+      for (int st = 1; st <= kRowsPerWave; ++st) {
+        const Raw<T> cur = ring[(st - 1) % kPrefetch];
+        if (st + kPrefetch <= kRowsPerWave)
+          load_step<T, true>(wk, st + kPrefetch, ring[(st - 1) % kPrefetch]);
+        one_row(st, cur, std::true_type{});
+      }
+    } else {
+#pragma unroll 1
+      for (int st = 1; st <= kRowsPerWave; ++st) {
+        Raw<T> cur;
+        load_step<T, false>(wk, st, cur);
+        one_row(st, cur, std::false_type{});
+      }
+    }
+    const uint32_t c0 = wave_sum32(cnt & 1023u), c1 = wave_sum32((cnt >> 10) & 1023u),
+                   c2 = wave_sum32(cnt >> 20);
+    if (lane == 0) {
+      atomicAdd(&s_tot[0], c0);
+      atomicAdd(&s_tot[1], c1);
+      atomicAdd(&s_tot[2], c2);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    uint32_t* dst = &sc.hist[((int64_t)(y0 / sh.ph) * sc.nx + x0 / sh.pw) * 3 + threadIdx.x];
+    if (STORE)
+      *dst = s_tot[threadIdx.x];
+    else
+      atomicAdd(dst, s_tot[threadIdx.x]);
+  }
+}
+
 __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -768,6 +849,10 @@ void launch_single(const Shared& sh, const Scene& sc, bool fast24, int filter, i
       hipLaunchKernelGGL((k_filter<T, false, false>), grid, block, 0, stream, sh, sc, per_xcd);
     else
       hipLaunchKernelGGL((k_filter<T, false, true>), grid, block, 0, stream, sh, sc, per_xcd);
+  } else if (sh.count_mode == CM_HIST_STORE) {
+    hipLaunchKernelGGL((k_thresh_walk<T, true>), grid, block, 0, stream, sh, sc, per_xcd);
+  } else if (sh.count_mode == CM_HIST_ATOMIC) {
+    hipLaunchKernelGGL((k_thresh_walk<T, false>), grid, block, 0, stream, sh, sc, per_xcd);
   } else {
     hipLaunchKernelGGL((k_thresh<T>), grid, block, 0, stream, sh, sc, per_xcd);
   }
@@ -857,10 +942,14 @@ int sil_label(const void* scene, int32_t nbands, const int32_t sel[3], int32_t H
 
   // how the per-patch counts are produced
   bool zero_hist;
-  if (p->filter == 1 && sh.ph == tile && sh.pw == tile) {
+  // (filter = 0: the tile's totals when patches tile-align, from k_thresh_walk;
+  // its walk addresses 34 rows with 32-bit offsets, checked for filter = 1 by
+  // validate and here for filter = 0)
+  const bool walk_ok = p->filter == 1 || sc.pitch * (kRowsPerWave + 2) <= (int64_t)UINT32_MAX;
+  if (walk_ok && sh.ph == tile && sh.pw == tile) {
     sh.count_mode = CM_HIST_STORE;
     zero_hist = false;
-  } else if (p->filter == 1 && sh.ph % tile == 0 && sh.pw % tile == 0) {
+  } else if (walk_ok && sh.ph % tile == 0 && sh.pw % tile == 0) {
     sh.count_mode = CM_HIST_ATOMIC;
     zero_hist = true;
   } else {

@@ -131,6 +131,11 @@ RNG_CASES = [
     (333, 777, "u16", 64, 64, 64, 1, 3, 0, 0, 0),
     (70, 4, "u16", 256, 256, 256, 1, 0, 0, 0, 0),
     (90, 5, "u8", 3, 256, 256, 1, 3, 0, 0, 0),
+    # filter off with patches that tile-align: tile totals, stored or added
+    (700, 1300, "u16", 256, 512, 768, 0, 3, 0, 0, 0),
+    (600, 1100, "u8", 256, 256, 512, 0, 0, 0, 0, 0),
+    (513, 1001, "u16", 256, 256, 256, 0, 3, 0, 0, 0),
+    (300, 299, "u16", 256, 256, 256, 0, 1, 0, 3, 1),
 ]
 
 
