@@ -242,16 +242,18 @@ def test_full_tile_bitexact(sil):
     _say("case full tile: generating")
     s = synth.generate(spec)
     fields = dict(dtype=R.U16)
-    _say("case full tile: gpu pitch 10980")
-    g = run_gpu(sil, s, fields)
+    # label rows 11008 bytes apart (128-byte aligned), as the benchmark allocates them
+    _say("case full tile: gpu pitch 10980, label pitch 11008")
+    g = run_gpu(sil, s, fields, label_pad=11008 - 10980)
     _say("case full tile: oracle")
     o = run_oracle(s, fields)
     assert_same(g, o, "full tile")
     del o
-    # the same scene with padded (16-byte aligned) rows gives the same result
+    # the same scene with padded (16-byte aligned) rows and unpadded label rows
+    # gives the same result
     spec.pitch = 10984
     sp = synth.generate(spec)
-    _say("case full tile: gpu pitch 10984")
+    _say("case full tile: gpu pitch 10984, label pitch 10980")
     g2 = run_gpu(sil, sp, fields, W=10980)
     assert (g2[0] == g[0]).all() and (g2[1] == g[1]).all()
 
