@@ -22,7 +22,10 @@
 #endif
 
 constexpr int kWalkRows = 32;             // output rows per wave
-constexpr int kWalkCopies = 32;           // LDS histogram copies (copy = lane % 32)
+#ifndef SIL_HIST_COPIES
+#define SIL_HIST_COPIES 32
+#endif
+constexpr int kWalkCopies = SIL_HIST_COPIES;  // LDS histogram copies (copy = lane % copies)
 constexpr int kWalkPrefetch = SIL_PREFETCH;  // rows of loads in flight per wave
 
 // The three order statistics as single VOP3 instructions.  Written out so that
@@ -243,7 +246,7 @@ __device__ __forceinline__ uint32_t walk_row(const Raw<T>& cur, const uint32_t* 
     uint32_t m = vmed3(vmax3(lo[j], lo[j + 1], lo[j + 2]), vmed3(mi[j], mi[j + 1], mi[j + 2]),
                        vmin3(hi[j], hi[j + 1], hi[j + 2]));
     uint32_t v = rescale(m);
-    atomicAdd(&hist[(v << 5) | hist_lane], inc[j] & rowmask);
+    atomicAdd(&hist[v * kWalkCopies + hist_lane], inc[j] & rowmask);
     packed |= v << (8 * j);
   }
   return packed;

@@ -333,7 +333,8 @@ __global__ __launch_bounds__(kWalkThreads, 4) void k_ex_walk(ExArgs a, int32_t t
     const uint32_t bin = threadIdx.x;
     uint32_t sum = 0;
 #pragma unroll 8
-    for (uint32_t k = 0; k < kWalkCopies; ++k) sum += hist[(bin << 5) | ((k + bin) & 31u)];
+    for (uint32_t k = 0; k < kWalkCopies; ++k)
+      sum += hist[bin * kWalkCopies + ((k + bin) & (kWalkCopies - 1))];
     if (sum) atomicAdd(&a.hist[(int64_t)chip_id * 256 + bin], sum);
   }
 }

@@ -481,7 +481,7 @@ __device__ __forceinline__ void filter_chip(const Shared& sh, const ChipAt& c, F
     const uint32_t bin = threadIdx.x;
     uint32_t sum = 0;
 #pragma unroll 8
-    for (uint32_t k = 0; k < kCopies; ++k) sum += s.hist[(bin << 5) | ((k + bin) & (kCopies - 1))];
+    for (uint32_t k = 0; k < kCopies; ++k) sum += s.hist[bin * kCopies + ((k + bin) & (kCopies - 1))];
     s.hsum[bin] = sum;
   }
   __syncthreads();
