@@ -6,19 +6,14 @@
 //
 // Work decomposition (filter = 1): one 512-thread workgroup per chip
 // (<= 256 x 256 pixels).  Wave w owns chip rows [32w, 32w + 32); lane l owns
-// columns [4l, 4l + 4).  Each wave walks its 34 input rows (one halo row
-// above and below) once, keeping a three-row window of V = max(B,G,R) in
-// registers; horizontal neighbours come from the adjacent lanes through DPP
-// wave shifts and the two chip-edge halo columns are fetched with each row,
-// at the point of the walk where the neighbouring chip reads those lines.
-// Even waves walk down and odd waves walk up, so the halo row two adjacent
-// waves share is read by both at about the same time (one HBM fetch).
-//   phase 1: 3x3 median (column sort + median of three triples, exact), the
-//            16->8-bit rescale (applied after the median: order statistics
-//            commute with a non-decreasing map), a 32-copy LDS histogram
-//            (copy = lane % 32, so the 64 lanes of an atomic never share a
-//            bank except across the two half-waves), and the 8-bit medians
-//            kept packed in 32 registers per lane;
+// columns [4l, 4l + 4).
+//   phase 1: each wave's walk over its 34 input rows (chip_walk.h): V =
+//            max(B,G,R), the exact 3x3 median (column sort + median of three
+//            triples), the 16->8-bit rescale (rescale.h; after the median:
+//            order statistics commute with a non-decreasing map), a 32-copy
+//            LDS histogram (copy = lane % 32, so the 64 lanes of an atomic
+//            never share a bank except across the two half-waves), and the
+//            8-bit medians kept packed in 32 registers per lane;
 //   phase 2: one wave reduces the histogram and runs exact Otsu (128-bit
 //            cross-multiplied comparisons), the eta gate, rank-k truncation
 //            levels and the stretch, folded with the class limits into a
@@ -108,16 +103,6 @@ struct Batch {
   int32_t n;
   int32_t per_xcd;
 };
-
-__device__ __forceinline__ uint32_t min3u(uint32_t a, uint32_t b, uint32_t c) {
-  return min(min(a, b), c);
-}
-__device__ __forceinline__ uint32_t max3u(uint32_t a, uint32_t b, uint32_t c) {
-  return max(max(a, b), c);
-}
-__device__ __forceinline__ uint32_t med3u(uint32_t a, uint32_t b, uint32_t c) {
-  return max(min(a, b), min(max(a, b), c));
-}
 
 // Workgroup id -> logical work index: XCD k = id % 8 gets the contiguous run
 // [k * per_xcd, (k+1) * per_xcd) in order.
