@@ -400,7 +400,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"full-tile labelling, {H}x{W} uint16 x 3 bands "
                                f"(pitch {args.pitch}), cloud/shadow filter on, chip 256, "
-                               f"per-256x256-patch counts",
+                               f"per-256x256-patch counts, label rows "
+                               f"{sil.label_pitch_for(W)} bytes apart",
                    "global_batch": 1, "pixels_per_step": npx, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
