@@ -522,6 +522,13 @@ struct GemmTN {
 constexpr int kXRow = kCIH * kCTW + 8;  // u16 per staged x^T channel row (padded)
 constexpr int kARow = kCTH * kCTW + 8;  // u16 per staged dy^T channel row (padded)
 
+// Column of a staged channel row, swizzled: channel rows 16-31 exchange
+// 64-byte halves of each 128 bytes.  The staging writes of a wave cover 64
+// bytes of four channel rows 8 apart, and rows 16 apart meet in the same LDS
+// banks with the padded stride; the MFMA reads (16 bytes of 16 consecutive
+// rows, all on one side of row 16) are unchanged in bank spread.
+__device__ __forceinline__ int swz(int row, int col) { return col ^ (((row >> 4) & 1) << 5); }
+
 __global__ __launch_bounds__(kGT) void k_wgrad3_lds(GemmTN g) {
   constexpr int A_SLOTS = (kCTH * kCTW / 2) * 4;   // pixel pairs x 4 channel groups = 512
   constexpr int A_R = A_SLOTS / kGT;               // 2
@@ -581,8 +588,9 @@ __global__ __launch_bounds__(kGT) void k_wgrad3_lds(GemmTN g) {
       const uint32_t w1[4] = {ra[r][1].x, ra[r][1].y, ra[r][1].z, ra[r][1].w};
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        *(uint32_t*)&Sa[8 * grp + 2 * t][col] = (w0[t] & 0xffffu) | (w1[t] << 16);
-        *(uint32_t*)&Sa[8 * grp + 2 * t + 1][col] = (w0[t] >> 16) | (w1[t] & 0xffff0000u);
+        const int ra0 = 8 * grp + 2 * t;
+        *(uint32_t*)&Sa[ra0][swz(ra0, col)] = (w0[t] & 0xffffu) | (w1[t] << 16);
+        *(uint32_t*)&Sa[ra0 + 1][swz(ra0 + 1, col)] = (w0[t] >> 16) | (w1[t] & 0xffff0000u);
       }
     }
 #pragma unroll
@@ -599,19 +607,20 @@ __global__ __launch_bounds__(kGT) void k_wgrad3_lds(GemmTN g) {
         const uint32_t hi = (w0[t] >> 16) | (w1[t] & 0xffff0000u);     // channel 2t+1
         const int ch0 = 8 * grp + 2 * t;
         // copy d holds halo column c + d at column c
+        const int c0 = hr * kCTW + 2 * hp;
         if (hp <= 15) {
-          *(uint32_t*)&Sx[0][ch0][hr * kCTW + 2 * hp] = lo;
-          *(uint32_t*)&Sx[0][ch0 + 1][hr * kCTW + 2 * hp] = hi;
+          *(uint32_t*)&Sx[0][ch0][swz(ch0, c0)] = lo;
+          *(uint32_t*)&Sx[0][ch0 + 1][swz(ch0 + 1, c0)] = hi;
         }
         if (hp >= 1) {
-          *(uint32_t*)&Sx[2][ch0][hr * kCTW + 2 * hp - 2] = lo;
-          *(uint32_t*)&Sx[2][ch0 + 1][hr * kCTW + 2 * hp - 2] = hi;
-          Sx[1][ch0][hr * kCTW + 2 * hp - 1] = (u16)(lo & 0xffffu);
-          Sx[1][ch0 + 1][hr * kCTW + 2 * hp - 1] = (u16)(hi & 0xffffu);
+          *(uint32_t*)&Sx[2][ch0][swz(ch0, c0 - 2)] = lo;
+          *(uint32_t*)&Sx[2][ch0 + 1][swz(ch0 + 1, c0 - 2)] = hi;
+          Sx[1][ch0][swz(ch0, c0 - 1)] = (u16)(lo & 0xffffu);
+          Sx[1][ch0 + 1][swz(ch0 + 1, c0 - 1)] = (u16)(hi & 0xffffu);
         }
         if (hp <= 15) {
-          Sx[1][ch0][hr * kCTW + 2 * hp] = (u16)(lo >> 16);
-          Sx[1][ch0 + 1][hr * kCTW + 2 * hp] = (u16)(hi >> 16);
+          Sx[1][ch0][swz(ch0, c0)] = (u16)(lo >> 16);
+          Sx[1][ch0 + 1][swz(ch0 + 1, c0)] = (u16)(hi >> 16);
         }
       }
     }
@@ -634,10 +643,11 @@ __global__ __launch_bounds__(kGT) void k_wgrad3_lds(GemmTN g) {
       for (int k = 0; k < 9; ++k) {
         const int b = wave + 4 * k, tap = b >> 2, mi = (b >> 1) & 1, nj = b & 1;
         const int dy = tap / 3, dx = tap % 3;
+        const int ar = 16 * mi + (lane & 15), xr = 16 * nj + (lane & 15);
         const bf16x8 av = __builtin_bit_cast(
-            bf16x8, *(const uint4*)&Sa[16 * mi + (lane & 15)][kCTW * r + 8 * (lane >> 4)]);
+            bf16x8, *(const uint4*)&Sa[ar][swz(ar, kCTW * r + 8 * (lane >> 4))]);
         const bf16x8 bv = __builtin_bit_cast(
-            bf16x8, *(const uint4*)&Sx[dx][16 * nj + (lane & 15)][kCTW * (r + dy) + 8 * (lane >> 4)]);
+            bf16x8, *(const uint4*)&Sx[dx][xr][swz(xr, kCTW * (r + dy) + 8 * (lane >> 4))]);
         acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[k], 0, 0, 0);
       }
     }
