@@ -214,8 +214,49 @@ __global__ __launch_bounds__(kGT) void k_gemm_nt(GemmNT g) {
 
     // epilogue: acc[i][j][t] is C[row][col], row = wave rows + 16i + 4*(lane/16) + t,
     // col = wave cols + 16j + lane%16
+    if constexpr (EM == E_UPSCATTER) {
+      // column -> (quadrant q, channel co) once per column; row -> (img, h, w)
+      // once per 4 consecutive rows, then advanced without divisions
+      int32_t qoff[NJ], cov[NJ];
+      float bias[NJ];
+      bool cok[NJ];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
+      for (int j = 0; j < NJ; ++j) {
+        const int32_t col = n0 + wn * 16 * NJ + 16 * j + (lane & 15);
+        cok[j] = col < g.N;
+        const int32_t q = cok[j] ? col / g.up_cout : 0;
+        cov[j] = cok[j] ? col - q * g.up_cout : 0;
+        qoff[j] = (q >> 1) * (2 * g.W) + (q & 1);
+        bias[j] = cok[j] ? g.bias[cov[j]] : 0.f;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int32_t row0 = m0 + wm * 64 + 16 * i + 4 * (lane >> 4);
+        const int32_t r0 = min(row0, g.M - 1);
+        int32_t img = r0 / (g.H * g.W);
+        const int32_t rem = r0 - img * g.H * g.W;
+        int32_t h = rem / g.W, w = rem - h * g.W;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          if (row0 + t < g.M) {
+            const int64_t base = ((int64_t)img * 2 * g.H + 2 * h) * (2 * g.W) + 2 * w;
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+              if (cok[j])
+                g.y0[(base + qoff[j]) * g.up_cout + cov[j]] = f2bf(acc[i][j][t] + bias[j]);
+          }
+          if (++w == g.W) {
+            w = 0;
+            if (++h == g.H) {
+              h = 0;
+              ++img;
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NJ && EM != E_UPSCATTER; ++j) {
       const int32_t col = n0 + wn * 16 * NJ + 16 * j + (lane & 15);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
@@ -236,13 +277,6 @@ __global__ __launch_bounds__(kGT) void k_gemm_nt(GemmNT g) {
               g.y0[(int64_t)row * g.split + col] = f2bf(v);
             else
               g.y1[(int64_t)row * (g.N - g.split) + (col - g.split)] = f2bf(v);
-          } else {
-            const int32_t q = col / g.up_cout, co = col - q * g.up_cout;
-            const int32_t img = row / (g.H * g.W), rem = row - img * g.H * g.W;
-            const int32_t h = rem / g.W, w = rem - h * g.W;
-            const int64_t pix =
-                ((int64_t)img * 2 * g.H + 2 * h + (q >> 1)) * (2 * g.W) + 2 * w + (q & 1);
-            g.y0[pix * g.up_cout + co] = f2bf(v + g.bias[co]);
           }
         }
     }
