@@ -958,22 +958,41 @@ __global__ void k_bn_stats(const float* stats, int32_t C, int64_t count, float e
 }
 
 // BN + ReLU, 8 channels per thread (C % 8 == 0)
+// The element-wise BN kernels walk [P][C] in 16-byte groups of 8 channels
+// with a grid stride of gridDim.x * 256 groups.  C divides 256, so the stride
+// (a multiple of 2048 elements) is a multiple of C and each thread keeps the
+// same 8 channels: their parameters are loaded once, and two groups are in
+// flight per iteration.
 __global__ void k_bn_relu(const u16* z, const float* mr, const float* gamma, const float* beta,
                           u16* out, int64_t n, int32_t C) {
-  const int64_t n8 = n / 8;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n8;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t c0 = (int32_t)((i * 8) % C);
+  const int64_t n8 = n / 8, i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int32_t c0 = (int32_t)((i0 * 8) % C);
+  float mean[8], rstd[8], gm[8], bt[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    mean[j] = mr[c0 + j];
+    rstd[j] = mr[C + c0 + j];
+    gm[j] = gamma[c0 + j];
+    bt[j] = beta[c0 + j];
+  }
+  auto one = [&](const uint4 zin) {
     float f[8];
-    unpack8(((const uint4*)z)[i], f);
+    unpack8(zin, f);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const int c = c0 + j;
-      const float v = (f[j] - mr[c]) * mr[C + c] * gamma[c] + beta[c];
+      const float v = (f[j] - mean[j]) * rstd[j] * gm[j] + bt[j];
       f[j] = v > 0.f ? v : 0.f;
     }
-    ((uint4*)out)[i] = pack8(f);
+    return pack8(f);
+  };
+  int64_t i = i0;
+  for (; i + stride < n8; i += 2 * stride) {
+    const uint4 a = ((const uint4*)z)[i], b = ((const uint4*)z)[i + stride];
+    ((uint4*)out)[i] = one(a);
+    ((uint4*)out)[i + stride] = one(b);
   }
+  if (i < n8) ((uint4*)out)[i] = one(((const uint4*)z)[i]);
 }
 
 // Per-channel sums over [P][C] for the BN backward: thread t owns channel
@@ -1034,35 +1053,58 @@ __global__ void k_bn_bwd_reduce(const u16* dout, const u16* z, const float* mr,
 __global__ void k_bn_bwd_apply(const u16* dout, const u16* z, const float* mr, const float* gamma,
                                const float* beta, const float* red, u16* dz, int64_t n, int32_t C,
                                float inv_count) {
-  const int64_t n8 = n / 8;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n8;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t c0 = (int32_t)((i * 8) % C);
+  const int64_t n8 = n / 8, i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int32_t c0 = (int32_t)((i0 * 8) % C);  // fixed per thread (see k_bn_relu)
+  float mean[8], rstd[8], gm[8], bt[8], r1[8], r2[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    mean[j] = mr[c0 + j];
+    rstd[j] = mr[C + c0 + j];
+    gm[j] = gamma[c0 + j];
+    bt[j] = beta[c0 + j];
+    r1[j] = red[c0 + j];
+    r2[j] = red[C + c0 + j];
+  }
+  auto one = [&](const uint4 zin, const uint4 din) {
     float fz[8], fd[8], o[8];
-    unpack8(((const uint4*)z)[i], fz);
-    unpack8(((const uint4*)dout)[i], fd);
+    unpack8(zin, fz);
+    unpack8(din, fd);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const int c = c0 + j;
-      const float zh = (fz[j] - mr[c]) * mr[C + c];
-      const float d = zh * gamma[c] + beta[c] > 0.f ? fd[j] : 0.f;
-      o[j] = gamma[c] * mr[C + c] * (d - (red[c] + zh * red[C + c]) * inv_count);
+      const float zh = (fz[j] - mean[j]) * rstd[j];
+      const float d = zh * gm[j] + bt[j] > 0.f ? fd[j] : 0.f;
+      o[j] = gm[j] * rstd[j] * (d - (r1[j] + zh * r2[j]) * inv_count);
     }
-    ((uint4*)dz)[i] = pack8(o);
+    return pack8(o);
+  };
+  int64_t i = i0;
+  for (; i + stride < n8; i += 2 * stride) {
+    const uint4 za = ((const uint4*)z)[i], da = ((const uint4*)dout)[i];
+    const uint4 zb = ((const uint4*)z)[i + stride], db = ((const uint4*)dout)[i + stride];
+    ((uint4*)dz)[i] = one(za, da);
+    ((uint4*)dz)[i + stride] = one(zb, db);
   }
+  if (i < n8) ((uint4*)dz)[i] = one(((const uint4*)z)[i], ((const uint4*)dout)[i]);
 }
 
 __global__ void k_affine_relu(const u16* z, const float* scale, const float* shift, u16* out,
                               int64_t n, int32_t C) {
-  const int64_t n8 = n / 8;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n8;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t c0 = (int32_t)((i * 8) % C);
+  const int64_t n8 = n / 8, i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int32_t c0 = (int32_t)((i0 * 8) % C);  // fixed per thread (see k_bn_relu)
+  float sc[8], sh[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    sc[j] = scale[c0 + j];
+    sh[j] = shift[c0 + j];
+  }
+  for (int64_t i = i0; i < n8; i += stride) {
     float f[8];
     unpack8(((const uint4*)z)[i], f);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const float v = f[j] * scale[c0 + j] + shift[c0 + j];
+      const float v = f[j] * sc[j] + sh[j];
       f[j] = v > 0.f ? v : 0.f;
     }
     ((uint4*)out)[i] = pack8(f);
