@@ -1694,7 +1694,8 @@ int sil_unet_up_t(const void* w, void* wt, int32_t cin, int32_t cout, void* stre
 int sil_unet_bn_relu(const void* z, const float* stats, const float* gamma, const float* beta,
                      float eps, int64_t count, void* out, float* mr, int64_t P, int32_t C,
                      void* stream) {
-  if (!z || !stats || !gamma || !beta || !out || !mr || count <= 0 || P <= 0 || C <= 0 || C % 8)
+  if (!z || !stats || !gamma || !beta || !out || !mr || count <= 0 || P <= 0 || C < 8 ||
+      C > 256 || 256 % C)
     return SIL_EINVAL;
   (void)hipGetLastError();
   hipStream_t st = (hipStream_t)stream;
@@ -1708,7 +1709,7 @@ int sil_unet_bn_relu(const void* z, const float* stats, const float* gamma, cons
 
 int sil_unet_affine_relu(const void* z, const float* scale, const float* shift, void* out,
                          int64_t P, int32_t C, void* stream) {
-  if (!z || !scale || !shift || !out || P <= 0 || C <= 0 || C % 8) return SIL_EINVAL;
+  if (!z || !scale || !shift || !out || P <= 0 || C < 8 || C > 256 || 256 % C) return SIL_EINVAL;
   (void)hipGetLastError();
   const int64_t n = P * C;
   hipLaunchKernelGGL(k_affine_relu, dim3(grid_for(n / 8)), dim3(256), 0, (hipStream_t)stream,

@@ -191,3 +191,19 @@ def test_workspace_sizes():
     m = sil.workspace_bytes(10980, 10980, sil.Params())
     assert m >= 10980 * 10980 + 43 * 43 * 256 * 5
 
+
+
+@needs_lib
+def test_unet_bn_channel_rule():
+    """Batch-norm entry points take channel counts that divide 256 and refuse
+    others before touching any buffer (the element-wise kernels keep one
+    group of 8 channels per thread across their grid stride)."""
+    lib = ctypes.CDLL(GPU_LIB)
+    vp, f32, i64, i32 = ctypes.c_void_p, ctypes.c_float, ctypes.c_int64, ctypes.c_int32
+    lib.sil_unet_bn_relu.argtypes = [vp, vp, vp, vp, f32, i64, vp, vp, i64, i32, vp]
+    lib.sil_unet_affine_relu.argtypes = [vp, vp, vp, vp, i64, i32, vp]
+    dummy = ctypes.c_void_p(16)
+    for C in (24, 40, 512, 4, 0):
+        assert lib.sil_unet_bn_relu(dummy, dummy, dummy, dummy, 1e-5, 10, dummy, dummy, 10, C,
+                                    None) == -1, C
+        assert lib.sil_unet_affine_relu(dummy, dummy, dummy, dummy, 10, C, None) == -1, C
