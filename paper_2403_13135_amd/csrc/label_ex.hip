@@ -99,6 +99,15 @@ __device__ __forceinline__ uint32_t div_small(uint32_t n, uint32_t d, float rd) 
   return r < 0 ? q - 1 : (r >= (int32_t)d ? q + 1 : q);
 }
 
+// floor(n / d) for n < 2^20, given rd within two ulps of 1/d and hrd = rd / 2
+// (exact): (n + 1/2) / d sits at least 1/(2d) from either neighbouring
+// integer, and the single-rounding product (n + 1/2) * rd is off from it by a
+// relative 2^-21.6 at most, which for n < 2^20 is less than that margin; so
+// truncation gives the quotient with no correction step.
+__device__ __forceinline__ uint32_t div_fma(uint32_t n, float rd, float hrd) {
+  return (uint32_t)__builtin_fmaf((float)n, rd, hrd);
+}
+
 // 16-bit reflectance to 8 bit: round-half-up of x * 255 / refl_max,
 // saturating.  n < 2^24; below the saturation point the quotient is < 255.
 template <bool U16>
@@ -527,11 +536,13 @@ __global__ __launch_bounds__(64) void k_ex_stats(ExArgs a) {
 // ---- pass C: masks, filtered colour, counts --------------------------------------
 
 // 8-bit HSV hue (degrees / 2, 0..179) and saturation (0..255) of (r, g, b),
-// rounded half up; red wins a tie for the maximum, then green.
-__device__ __forceinline__ void hue_sat(uint32_t r, uint32_t g, uint32_t b, uint32_t& H,
-                                        uint32_t& S) {
-  const uint32_t V = max3u(r, g, b), mn = min3u(r, g, b), d = V - mn;
-  S = V == 0 ? 0u : div_small(510u * d + V, 2u * V, __builtin_amdgcn_rcpf((float)(2u * V)));
+// rounded half up; red wins a tie for the maximum, then green.  rv = 1 / V
+// (to within an ulp) when V > 0; numerators stay below 2^18.
+__device__ __forceinline__ void hue_sat(uint32_t r, uint32_t g, uint32_t b, uint32_t V, float rv,
+                                        uint32_t& H, uint32_t& S) {
+  const uint32_t mn = min3u(r, g, b), d = V - mn;
+  // S = floor((510 d + V) / (2V)); 1 / (2V) = rv / 2 exactly
+  S = V == 0 ? 0u : div_fma(510u * d + V, 0.5f * rv, 0.25f * rv);
   if (d == 0) {
     H = 0;
     return;
@@ -541,7 +552,8 @@ __device__ __forceinline__ void hue_sat(uint32_t r, uint32_t g, uint32_t b, uint
   const int32_t num = V == r ? ig - ib : (V == g ? 2 * id + ib - ir : 4 * id + ir - ig);
   // hue / 2 = floor((60 num + d) / (2d)); adding 360 d to the numerator adds 180
   const uint32_t top = (uint32_t)(60 * num + 361 * (int32_t)d);
-  const uint32_t q = div_small(top, 2u * d, __builtin_amdgcn_rcpf((float)(2u * d)));
+  const float rd2 = 0.5f * __builtin_amdgcn_rcpf((float)d);
+  const uint32_t q = div_fma(top, rd2, 0.5f * rd2);
   H = q >= 360u ? q - 360u : (q >= 180u ? q - 180u : q);
 }
 
@@ -549,8 +561,18 @@ __device__ __forceinline__ void hue_sat(uint32_t r, uint32_t g, uint32_t b, uint
 // loads are issued before any use; the chips' median -> filtered-value tables
 // of the tile are staged in LDS (when the tile touches at most kMaxTileChips
 // chips, else read from the workspace).
-template <bool U16, bool FILTER, bool HSALL>
-__global__ __launch_bounds__(kThreads) void k_ex_apply(ExArgs a, int32_t ntx, int64_t ntiles) {
+// IN: 0 = 8-bit bands, 1 = 16-bit bands rescaled by to8, 2 = 16-bit bands
+// rescaled by the 24-bit multiply-shift (when its constants exist).
+// At most 80 VGPRs (six waves per SIMD, three workgroups per CU): the filter
+// variants otherwise take a few more and drop to two workgroups per CU.
+template <int IN, bool FILTER, bool HSALL>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_ex_apply(
+    ExArgs a, int32_t ntx, int64_t ntiles) {
+  constexpr bool U16 = IN != 0;
+  const auto rescale = [&](uint32_t x) -> uint32_t {
+    if (IN == 2) return rescale24(x, a.x_sat, a.half, a.magic24, a.shift24);
+    return to8<U16>(x, a);
+  };
   __shared__ uint32_t scnt[kMaxTilePatches][3];
   __shared__ uint32_t slut[kMaxTileChips][64];
   // which masks admit each hue, saturation and filtered value (bit c = mask c)
@@ -568,7 +590,6 @@ __global__ __launch_bounds__(kThreads) void k_ex_apply(ExArgs a, int32_t ntx, in
     tS[tid] = (uint8_t)bs;
     tV[tid] = (uint8_t)bv;
   }
-  const uint8_t* const slb = (const uint8_t*)&slut[0][0];
   const int32_t c0 = 4 * tid;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int32_t ty = (int32_t)(tile / ntx) * kTRC, tx = (int32_t)(tile % ntx) * kTW;
@@ -682,15 +703,18 @@ __global__ __launch_bounds__(kThreads) void k_ex_apply(ExArgs a, int32_t ntx, in
         int32_t key = -1;
         uint32_t bits = 0;
         if (j < nv) {
-          const uint32_t bl = to8<U16>(raw[r][0][j], a), gr = to8<U16>(raw[r][1][j], a),
-                         rd = to8<U16>(raw[r][2][j], a);
+          const uint32_t bl = rescale(raw[r][0][j]), gr = rescale(raw[r][1][j]),
+                         rd = rescale(raw[r][2][j]);
           const uint32_t V = max3u(bl, gr, rd);
+          const float rv = __builtin_amdgcn_rcpf((float)V);  // +inf at V = 0, never used
           uint32_t vc = V;
           if (FILTER) {
             const uint32_t m = (vmw[r] >> (8 * j)) & 255u;
             if (a.lut_lds) {
+              // a word read: a byte read here and the global one below would
+              // be merged into one flat load, which waits on every load in flight
               const int32_t k = (cyi - cy0) * ncx_t + ((x + j) / a.chip - cx0);
-              vc = slb[k * 256 + m];
+              vc = (slut[k][m >> 2] >> (8 * (m & 3))) & 255u;
             } else {
               const int64_t chip_id = (int64_t)cyi * a.ncx + (j ? (x + j) / a.chip : cxi);
               vc = a.lut[chip_id * 256 + m];
@@ -700,16 +724,17 @@ __global__ __launch_bounds__(kThreads) void k_ex_apply(ExArgs a, int32_t ntx, in
             bits = tV[vc];
           } else {
             uint32_t Hh, Ss;
-            hue_sat(rd, gr, bl, Hh, Ss);
+            hue_sat(rd, gr, bl, V, rv, Hh, Ss);
             bits = (uint32_t)tH[Hh] & tS[Ss] & tV[vc];
           }
           bits4 |= bits << (8 * j);
           if (a.rgb) {
-            const float rv = V ? __builtin_amdgcn_rcpf((float)V) : 0.f;
+            // round(c vc / V): numerators below 2^17
             const uint32_t cband[3] = {bl, gr, rd};
+            const float hrv = 0.5f * rv;
 #pragma unroll
             for (int i = 0; i < 3; ++i)
-              rgbw[i] |= (V ? div_small(cband[i] * vc + V / 2u, V, rv) : 0u) << (8 * j);
+              rgbw[i] |= (V ? div_fma(__umul24(cband[i], vc) + V / 2u, rv, hrv) : 0u) << (8 * j);
           }
           if (a.counts) {
             if (a.cnt_lds) {
@@ -999,9 +1024,11 @@ int sil_label_ex(const void* scene, int32_t nbands, const int32_t sel[3], int32_
   const int32_t ntx = (W + kTW - 1) / kTW;
   const int64_t ntiles = (int64_t)((H + kTRC - 1) / kTRC) * ntx;
   const dim3 cgrid((unsigned)std::min<int64_t>(ntiles, 8192));
-#define SIL_EX_APPLY(U, F, HS)                                                             \
-  if (a.u16 == U && a.filter == F && a.hs_all == HS)                                       \
-    hipLaunchKernelGGL((k_ex_apply<U, F, HS>), cgrid, dim3(kThreads), 0, st, a, ntx, ntiles);
+  const int in = a.u16 ? (a.fast24 ? 2 : 1) : 0;
+#define SIL_EX_APPLY(I, F, HS)                                                             \
+  if (in == I && a.filter == F && a.hs_all == HS)                                          \
+    hipLaunchKernelGGL((k_ex_apply<I, F, HS>), cgrid, dim3(kThreads), 0, st, a, ntx, ntiles);
+  SIL_EX_APPLY(2, 1, 1) SIL_EX_APPLY(2, 1, 0) SIL_EX_APPLY(2, 0, 1) SIL_EX_APPLY(2, 0, 0)
   SIL_EX_APPLY(1, 1, 1) SIL_EX_APPLY(1, 1, 0) SIL_EX_APPLY(1, 0, 1) SIL_EX_APPLY(1, 0, 0)
   SIL_EX_APPLY(0, 1, 1) SIL_EX_APPLY(0, 1, 0) SIL_EX_APPLY(0, 0, 1) SIL_EX_APPLY(0, 0, 0)
 #undef SIL_EX_APPLY
