@@ -535,24 +535,35 @@ __global__ __launch_bounds__(64) void k_ex_stats(ExArgs a) {
 
 // ---- pass C: masks, filtered colour, counts --------------------------------------
 
+// 24-bit multiply(-add): full-rate forms the compiler does not pick by itself
+// when it cannot see that the operands are 8-bit values.
+__device__ __forceinline__ uint32_t mad24(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+__device__ __forceinline__ uint32_t mul24(uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm("v_mul_u32_u24 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
 // 8-bit HSV hue (degrees / 2, 0..179) and saturation (0..255) of (r, g, b),
-// rounded half up; red wins a tie for the maximum, then green.  rv = 1 / V
-// (to within an ulp) when V > 0; numerators stay below 2^18.
+// rounded half up; red wins a tie for the maximum, then green.  rv = 1 / max(V, 1)
+// to within an ulp; numerators stay below 2^18.  No branches: V = 0 and d = 0
+// give zero numerators, hence S = 0 and H = 0.
 __device__ __forceinline__ void hue_sat(uint32_t r, uint32_t g, uint32_t b, uint32_t V, float rv,
                                         uint32_t& H, uint32_t& S) {
   const uint32_t mn = min3u(r, g, b), d = V - mn;
   // S = floor((510 d + V) / (2V)); 1 / (2V) = rv / 2 exactly
-  S = V == 0 ? 0u : div_fma(510u * d + V, 0.5f * rv, 0.25f * rv);
-  if (d == 0) {
-    H = 0;
-    return;
-  }
-  // sector position times d (selects, no divergent branches)
-  const int32_t ir = (int32_t)r, ig = (int32_t)g, ib = (int32_t)b, id = (int32_t)d;
-  const int32_t num = V == r ? ig - ib : (V == g ? 2 * id + ib - ir : 4 * id + ir - ig);
-  // hue / 2 = floor((60 num + d) / (2d)); adding 360 d to the numerator adds 180
-  const uint32_t top = (uint32_t)(60 * num + 361 * (int32_t)d);
-  const float rd2 = 0.5f * __builtin_amdgcn_rcpf((float)d);
+  S = div_fma(mad24(d, 510u, V), 0.5f * rv, 0.25f * rv);
+  // the sector position plus d (in [0, 6d]) for each possible maximum, then a select
+  const uint32_t nr = d + g - b, ng = mad24(d, 3u, b) - r, nb = mad24(d, 5u, r) - g;
+  const uint32_t np = V == r ? nr : (V == g ? ng : nb);
+  // hue / 2 = floor((60 (np - d) + d) / (2d)), plus 180 to keep the numerator
+  // non-negative: 60 np + 301 d
+  const uint32_t top = mad24(np, 60u, mul24(d, 301u));
+  const float rd2 = 0.5f * __builtin_amdgcn_rcpf((float)max(d, 1u));
   const uint32_t q = div_fma(top, rd2, 0.5f * rd2);
   H = q >= 360u ? q - 360u : (q >= 180u ? q - 180u : q);
 }
@@ -706,7 +717,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) v
           const uint32_t bl = rescale(raw[r][0][j]), gr = rescale(raw[r][1][j]),
                          rd = rescale(raw[r][2][j]);
           const uint32_t V = max3u(bl, gr, rd);
-          const float rv = __builtin_amdgcn_rcpf((float)V);  // +inf at V = 0, never used
+          const float rv = __builtin_amdgcn_rcpf((float)max(V, 1u));
           uint32_t vc = V;
           if (FILTER) {
             const uint32_t m = (vmw[r] >> (8 * j)) & 255u;
@@ -729,12 +740,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) v
           }
           bits4 |= bits << (8 * j);
           if (a.rgb) {
-            // round(c vc / V): numerators below 2^17
+            // round(c vc / V): numerators below 2^17 (all zero when V = 0)
             const uint32_t cband[3] = {bl, gr, rd};
             const float hrv = 0.5f * rv;
 #pragma unroll
             for (int i = 0; i < 3; ++i)
-              rgbw[i] |= (V ? div_fma(__umul24(cband[i], vc) + V / 2u, rv, hrv) : 0u) << (8 * j);
+              rgbw[i] |= div_fma(mad24(cband[i], vc, V >> 1), rv, hrv) << (8 * j);
           }
           if (a.counts) {
             if (a.cnt_lds) {
