@@ -565,7 +565,7 @@ __device__ __forceinline__ void hue_sat(uint32_t r, uint32_t g, uint32_t b, uint
   const uint32_t top = mad24(np, 60u, mul24(d, 301u));
   const float rd2 = 0.5f * __builtin_amdgcn_rcpf((float)max(d, 1u));
   const uint32_t q = div_fma(top, rd2, 0.5f * rd2);
-  H = q >= 360u ? q - 360u : (q >= 180u ? q - 180u : q);
+  H = min(q, q - 180u);  // q is in [150, 330]; below 180 the difference wraps high
 }
 
 // Tiles of 8 x 1024 pixels; thread t owns columns 4t .. 4t+3.  All rows'
@@ -586,8 +586,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) v
   };
   __shared__ uint32_t scnt[kMaxTilePatches][3];
   __shared__ uint32_t slut[kMaxTileChips][64];
-  // which masks admit each hue, saturation and filtered value (bit c = mask c)
-  __shared__ uint8_t tH[180], tS[256], tV[256];
+  // which masks admit each hue, saturation and filtered value: bit c = mask c,
+  // and again as a 1 in byte c + 1, so that adding entries counts per mask
+  __shared__ uint32_t tH[180], tS[256], tV[256];
   const int tid = threadIdx.x, lane = tid & 63;
   {
     uint32_t bh = 0, bs = 0, bv = 0;
@@ -597,9 +598,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) v
       bs |= (uint32_t)(a.lo[c][1] <= tid && tid <= a.hi[c][1]) << c;
       bv |= (uint32_t)(a.lo[c][2] <= tid && tid <= a.hi[c][2]) << c;
     }
-    if (tid < 180) tH[tid] = (uint8_t)bh;
-    tS[tid] = (uint8_t)bs;
-    tV[tid] = (uint8_t)bv;
+    const auto spread = [](uint32_t b) {
+      return b | (b & 1u) << 8 | (b & 2u) << 15 | (b & 4u) << 22;
+    };
+    if (tid < 180) tH[tid] = spread(bh);
+    tS[tid] = spread(bs);
+    tV[tid] = spread(bv);
   }
   const int32_t c0 = 4 * tid;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -634,11 +638,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) v
     int32_t ppx[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) ppx[j] = a.counts ? (x + j) / a.pw : 0;
+    // a thread's counts for its current patch: mask c in byte c + 1 of run (a
+    // thread adds at most 4 x kTRC entries per tile, so no byte carries; byte 0
+    // sums the entries' mask bits and is ignored)
+    static_assert(4 * kTRC * 7 < 256, "per-tile counts must fit a byte");
     int32_t run_key = -1;
-    uint32_t run[3] = {0, 0, 0};
+    uint32_t packed_run = 0;
     auto flush = [&]() {
       // the counts of this thread's current patch go to LDS; lanes of a wave
       // that share the patch are summed first
+      uint32_t run[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) run[c] = (packed_run >> (8 * c + 8)) & 255u;
       const bool uni = __all(run_key == __shfl(run_key, 0));
       if (uni) {
 #pragma unroll
@@ -652,7 +663,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) v
         for (int c = 0; c < 3; ++c)
           if (run[c]) atomicAdd(&scnt[run_key][c], run[c]);
       }
-      run[0] = run[1] = run[2] = 0;
+      packed_run = 0;
     };
 
     // rows in batches of kRB: every load of a batch is in flight before its
@@ -736,9 +747,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) v
           } else {
             uint32_t Hh, Ss;
             hue_sat(rd, gr, bl, V, rv, Hh, Ss);
-            bits = (uint32_t)tH[Hh] & tS[Ss] & tV[vc];
+            bits = tH[Hh] & tS[Ss] & tV[vc];
           }
-          bits4 |= bits << (8 * j);
+          // byte 0 of the entry (the mask bits) into byte j of bits4
+          bits4 = __builtin_amdgcn_perm(bits, bits4, 0x03020100u + (4u << (8 * j)) - (j << (8 * j)));
           if (a.rgb) {
             // round(c vc / V): numerators below 2^17 (all zero when V = 0)
             const uint32_t cband[3] = {bl, gr, rd};
@@ -762,8 +774,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) v
           // wave-uniform test: every lane takes part in flush()
           if (__any(key != run_key && run_key >= 0 && key >= 0)) flush();
           if (key >= 0) run_key = key;
-#pragma unroll
-          for (int c = 0; c < 3; ++c) run[c] += bits >> c & 1u;
+          packed_run += bits;
         }
       }
       if (nv > 0) {

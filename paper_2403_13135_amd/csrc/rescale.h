@@ -80,8 +80,9 @@ __device__ __forceinline__ uint32_t rescale24(uint32_t x, uint32_t x_sat, uint32
                                               uint32_t magic, uint32_t shift) {
   uint32_t n;
   asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(n) : "v"(min(x, x_sat)), "v"(255u), "v"(half));
-  const uint64_t p = (uint64_t)(n & 0xFFFFFFu) * (uint64_t)(magic & 0xFFFFFFu);
-  return (uint32_t)(p >> 32) >> (shift - 32u);
+  uint32_t hi;
+  asm("v_mul_hi_u32_u24 %0, %1, %2" : "=v"(hi) : "s"(magic), "v"(n));
+  return hi >> (shift - 32u);
 }
 
 #endif  // SIL_RESCALE_H
