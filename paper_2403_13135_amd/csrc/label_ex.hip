@@ -22,7 +22,8 @@
 //      multiplied comparisons (chips up to 2^27 pixels), the eta gate, rank-k
 //      truncation levels and the stretch, written as a 256-entry table
 //      median -> filtered value.
-//   C. k_ex_apply: 8 x 1024 tiles, four pixels per thread, row by row; per
+//   C. k_ex_apply: 8 x 1024 tiles, four pixels per thread, row by row with
+//      the next row's loads in flight during the current row's work; per
 //      pixel the three 8-bit bands, V, the filtered Vc from the chip tables
 //      (staged in LDS), H and S, the masks, the filtered colour and per-patch
 //      mask counts (per-thread runs, wave-reduced when
@@ -50,8 +51,6 @@ constexpr int kThreads = 256;     // threads per block of passes A and C
 constexpr int kTR = 16;           // pass A tile rows
 constexpr int kTW = 4 * kThreads; // tile columns: 4 per thread
 constexpr int kTRC = 8;           // pass C tile rows
-constexpr int kRB = 1;            // pass C rows per load batch (1 measured fastest: batching
-                                  // more rows costs occupancy and SGPR spills)
 constexpr int kMaxTilePatches = 128;
 constexpr int kMaxTileChips = 16; // per-chip tables a pass C tile stages in LDS
 constexpr int64_t kMaxChipPixels = int64_t(1) << 27;
@@ -666,58 +665,62 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) v
       packed_run = 0;
     };
 
-    // rows in batches of kRB: every load of a batch is in flight before its
-    // first use; inner loops fully unrolled so raw[][][] stays in registers
-#pragma unroll 1
-    for (int rb = 0; rb < rows; rb += kRB) {
-      const bool vec = a.in_vec && nv == 4;
-      uint32_t raw[kRB][3][4], vmw[kRB];
+    // one row's inputs, packed as loaded: the three bands (U16: two words of
+    // two pixels each; 8-bit: one word of four) and four median bytes
+    struct RowIn {
+      uint32_t w[3][2];
+      uint32_t vm;
+    };
+    const bool vec = a.in_vec && nv == 4;
+    const auto load_row = [&](int32_t y, RowIn& o) {
 #pragma unroll
-      for (int r = 0; r < kRB; ++r) {
-        vmw[r] = 0;
+      for (int i = 0; i < 3; ++i) o.w[i][0] = o.w[i][1] = 0;
+      o.vm = 0;
+      if (nv <= 0) return;
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) raw[r][i][j] = 0;
-        if (rb + r < rows && nv > 0) {
-          const int32_t y = ty + rb + r;
-#pragma unroll
-          for (int i = 0; i < 3; ++i) {
-            const uint8_t* row = a.band[i] + (int64_t)y * a.pitch_b;
-            if (vec) {
-              if (U16) {
-                const uint2 w = *(const uint2*)(row + 2 * (int64_t)x);
-                raw[r][i][0] = w.x & 0xffffu;
-                raw[r][i][1] = w.x >> 16;
-                raw[r][i][2] = w.y & 0xffffu;
-                raw[r][i][3] = w.y >> 16;
-              } else {
-                const uint32_t w = *(const uint32_t*)(row + x);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) raw[r][i][j] = (w >> (8 * j)) & 255u;
-              }
-            } else {
-#pragma unroll
-              for (int j = 0; j < 4; ++j)
-                if (j < nv) raw[r][i][j] = raw_at<U16>(a, i, y, x + j);
-            }
+      for (int i = 0; i < 3; ++i) {
+        const uint8_t* row = a.band[i] + (int64_t)y * a.pitch_b;
+        if (vec) {
+          if (U16) {
+            const uint2 w = *(const uint2*)(row + 2 * (int64_t)x);
+            o.w[i][0] = w.x;
+            o.w[i][1] = w.y;
+          } else {
+            o.w[i][0] = *(const uint32_t*)(row + x);
           }
-          if (FILTER) {
-            const uint8_t* vrow = a.vm + (int64_t)y * a.vm_pitch + x;
-            if (nv == 4) {
-              vmw[r] = *(const uint32_t*)vrow;
-            } else {
-              for (int j = 0; j < nv; ++j) vmw[r] |= (uint32_t)vrow[j] << (8 * j);
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (j < nv) {
+              const uint32_t v = raw_at<U16>(a, i, y, x + j);
+              if (U16)
+                o.w[i][j >> 1] |= v << (16 * (j & 1));
+              else
+                o.w[i][0] |= v << (8 * j);
             }
-          }
         }
       }
+      if (FILTER) {
+        const uint8_t* vrow = a.vm + (int64_t)y * a.vm_pitch + x;
+        if (nv == 4) {
+          o.vm = *(const uint32_t*)vrow;
+        } else {
+          for (int j = 0; j < nv; ++j) o.vm |= (uint32_t)vrow[j] << (8 * j);
+        }
+      }
+    };
+    const auto band_px = [](const RowIn& in, int i, int j) -> uint32_t {
+      if (U16) return (in.w[i][j >> 1] >> (16 * (j & 1))) & 0xffffu;
+      return (in.w[i][0] >> (8 * j)) & 255u;
+    };
 
-
-#pragma unroll
-    for (int r = 0; r < kRB; ++r) {
-      if (rb + r >= rows) break;
-      const int32_t y = ty + rb + r;
+    // the next row's loads are issued before the current row is computed
+    RowIn cur, nxt;
+    load_row(ty, cur);
+#pragma unroll 1
+    for (int r = 0; r < rows; ++r) {
+      const int32_t y = ty + r;
+      if (r + 1 < rows) load_row(y + 1, nxt);
       const int32_t cyi = FILTER ? y / a.chip : 0;
       uint32_t bits4 = 0, rgbw[3] = {0, 0, 0};
 #pragma unroll
@@ -725,13 +728,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) v
         int32_t key = -1;
         uint32_t bits = 0;
         if (j < nv) {
-          const uint32_t bl = rescale(raw[r][0][j]), gr = rescale(raw[r][1][j]),
-                         rd = rescale(raw[r][2][j]);
+          const uint32_t bl = rescale(band_px(cur, 0, j)), gr = rescale(band_px(cur, 1, j)),
+                         rd = rescale(band_px(cur, 2, j));
           const uint32_t V = max3u(bl, gr, rd);
           const float rv = __builtin_amdgcn_rcpf((float)max(V, 1u));
           uint32_t vc = V;
           if (FILTER) {
-            const uint32_t m = (vmw[r] >> (8 * j)) & 255u;
+            const uint32_t m = (cur.vm >> (8 * j)) & 255u;
             if (a.lut_lds) {
               // a word read: a byte read here and the global one below would
               // be merged into one flat load, which waits on every load in flight
@@ -796,8 +799,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) v
           }
         }
       }
+      cur = nxt;
     }
-    }  // row batches
     if (a.counts && a.cnt_lds) {
       flush();
       __syncthreads();
