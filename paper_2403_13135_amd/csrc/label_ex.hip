@@ -29,8 +29,10 @@
 //      mask counts (per-thread runs, wave-reduced when
 //      the wave shares a patch, LDS counters per tile, one global atomic per
 //      nonzero counter and tile).
-// Divisions by small run-time divisors use a float estimate corrected by one
-// integer step, which is exact for the operand ranges involved.
+// Divisions by small run-time divisors are exact in float: the hue,
+// saturation and colour quotients truncate one fma, (n + 1/2) * rcp(d), whose
+// error stays inside the margin of the quotient for numerators below 2^20;
+// the general rescale uses a float estimate corrected by one integer step.
 
 #include <hip/hip_runtime.h>
 
@@ -633,10 +635,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) v
     }
     __syncthreads();
 
-    const int32_t cxi = FILTER ? x / a.chip : 0;
-    int32_t ppx[4];
+    // this thread's pixels' chip column among the tile's staged tables and
+    // patch column among its counters, a byte each (both below 128 when staged;
+    // pixels past the edge are masked and never used)
+    uint32_t kcol4 = 0, pcol4 = 0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) ppx[j] = a.counts ? (x + j) / a.pw : 0;
+    for (int j = 0; j < 4; ++j) {
+      if (FILTER && a.lut_lds) kcol4 |= ((uint32_t)((x + j) / a.chip - cx0) & 255u) << (8 * j);
+      if (a.counts && a.cnt_lds) pcol4 |= ((uint32_t)((x + j) / a.pw - px0) & 255u) << (8 * j);
+    }
     // a thread's counts for its current patch: mask c in byte c + 1 of run (a
     // thread adds at most 4 x kTRC entries per tile, so no byte carries; byte 0
     // sums the entries' mask bits and is ignored)
@@ -738,10 +745,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) v
             if (a.lut_lds) {
               // a word read: a byte read here and the global one below would
               // be merged into one flat load, which waits on every load in flight
-              const int32_t k = (cyi - cy0) * ncx_t + ((x + j) / a.chip - cx0);
+              const int32_t k = (cyi - cy0) * ncx_t + (int32_t)((kcol4 >> (8 * j)) & 255u);
               vc = (slut[k][m >> 2] >> (8 * (m & 3))) & 255u;
             } else {
-              const int64_t chip_id = (int64_t)cyi * a.ncx + (j ? (x + j) / a.chip : cxi);
+              const int64_t chip_id = (int64_t)cyi * a.ncx + (x + j) / a.chip;
               vc = a.lut[chip_id * 256 + m];
             }
           }
@@ -764,9 +771,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) v
           }
           if (a.counts) {
             if (a.cnt_lds) {
-              key = (y / a.ph - py0) * npx_t + (ppx[j] - px0);
+              key = (y / a.ph - py0) * npx_t + (int32_t)((pcol4 >> (8 * j)) & 255u);
             } else {
-              uint32_t* cp = a.counts + ((int64_t)(y / a.ph) * a.nx + ppx[j]) * 3;
+              uint32_t* cp = a.counts + ((int64_t)(y / a.ph) * a.nx + (x + j) / a.pw) * 3;
 #pragma unroll
               for (int c = 0; c < 3; ++c)
                 if (bits >> c & 1u) atomicAdd(&cp[c], 1u);
