@@ -131,6 +131,21 @@ def test_random_cases_bitexact(sil, case):
     assert_same(g, o, str(case))
 
 
+@pytest.mark.parametrize("refl_max", [40000, 65535, 12345])
+def test_general_rescale_with_hue_saturation(sil, refl_max):
+    """Full scales whose rescale constants need more than 24 bits (40000,
+    65535) take the per-pixel pass's 32-bit rescale, 12345 its 24-bit one;
+    each with hue/saturation-bounded limits, filter on and off, colour output."""
+    rng = np.random.default_rng(refl_max)
+    s = rng.integers(0, 65536, size=(3, 300, 1100)).astype(np.uint16)
+    for flt in (1, 0):
+        fields = dict(dtype=R.U16, refl_max=refl_max, chip=128, filter=flt, patch_h=50,
+                      patch_w=70, **_limits(2))
+        _say(f"case general rescale refl_max {refl_max} filter {flt}")
+        assert_same(run_gpu(sil, s, fields, pad=5), run_oracle(s, fields),
+                    f"refl_max {refl_max} filter {flt}")
+
+
 @pytest.mark.parametrize("chip", [64, 256, 1 << 20])
 def test_generated_scene_bitexact(sil, chip):
     """A seeded synthetic u16 scene (Voronoi ice field, haze and shadow), filter
