@@ -30,7 +30,7 @@
 //      the wave shares a patch, LDS counters per tile, one global atomic per
 //      nonzero counter and tile).
 // Divisions by small run-time divisors are exact in float: the hue,
-// saturation and colour quotients truncate one fma, (n + 1/2) * rcp(d), whose
+// saturation and colour quotients truncate one fma, (n + 1/2) * (1/d), whose
 // error stays inside the margin of the quotient for numerators below 2^20;
 // the general rescale uses a float estimate corrected by one integer step.
 
@@ -551,10 +551,10 @@ __device__ __forceinline__ uint32_t mul24(uint32_t a, uint32_t b) {
 
 // 8-bit HSV hue (degrees / 2, 0..179) and saturation (0..255) of (r, g, b),
 // rounded half up; red wins a tie for the maximum, then green.  rv = 1 / max(V, 1)
-// to within an ulp; numerators stay below 2^18.  No branches: V = 0 and d = 0
-// give zero numerators, hence S = 0 and H = 0.
+// and trcp[k] = 1 / max(k, 1), to within an ulp; numerators stay below 2^18.
+// No branches: V = 0 and d = 0 give zero numerators, hence S = 0 and H = 0.
 __device__ __forceinline__ void hue_sat(uint32_t r, uint32_t g, uint32_t b, uint32_t V, float rv,
-                                        uint32_t& H, uint32_t& S) {
+                                        const float* trcp, uint32_t& H, uint32_t& S) {
   const uint32_t mn = min3u(r, g, b), d = V - mn;
   // S = floor((510 d + V) / (2V)); 1 / (2V) = rv / 2 exactly
   S = div_fma(mad24(d, 510u, V), 0.5f * rv, 0.25f * rv);
@@ -564,7 +564,7 @@ __device__ __forceinline__ void hue_sat(uint32_t r, uint32_t g, uint32_t b, uint
   // hue / 2 = floor((60 (np - d) + d) / (2d)), plus 180 to keep the numerator
   // non-negative: 60 np + 301 d
   const uint32_t top = mad24(np, 60u, mul24(d, 301u));
-  const float rd2 = 0.5f * __builtin_amdgcn_rcpf((float)max(d, 1u));
+  const float rd2 = 0.5f * trcp[d];
   const uint32_t q = div_fma(top, rd2, 0.5f * rd2);
   H = min(q, q - 180u);  // q is in [150, 330]; below 180 the difference wraps high
 }
@@ -575,8 +575,8 @@ __device__ __forceinline__ void hue_sat(uint32_t r, uint32_t g, uint32_t b, uint
 // chips, else read from the workspace).
 // IN: 0 = 8-bit bands, 1 = 16-bit bands rescaled by to8, 2 = 16-bit bands
 // rescaled by the 24-bit multiply-shift (when its constants exist).
-// At most 80 VGPRs (six waves per SIMD, three workgroups per CU): the filter
-// variants otherwise take a few more and drop to two workgroups per CU.
+// At most 80 VGPRs (six waves per SIMD: six 256-thread workgroups per CU):
+// the filter variants otherwise take a few more and drop to five.
 template <int IN, bool FILTER, bool HSALL>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_ex_apply(
     ExArgs a, int32_t ntx, int64_t ntiles) {
@@ -590,6 +590,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) v
   // which masks admit each hue, saturation and filtered value: bit c = mask c,
   // and again as a 1 in byte c + 1, so that adding entries counts per mask
   __shared__ uint32_t tH[180], tS[256], tV[256];
+  // reciprocals of 0..255 (1 at 0) for the per-pixel quotients
+  __shared__ float trcp[256];
+  static_assert(kThreads == 256, "one table entry per thread");
   const int tid = threadIdx.x, lane = tid & 63;
   {
     uint32_t bh = 0, bs = 0, bv = 0;
@@ -602,6 +605,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) v
     const auto spread = [](uint32_t b) {
       return b | (b & 1u) << 8 | (b & 2u) << 15 | (b & 4u) << 22;
     };
+    trcp[tid] = 1.0f / (float)max(tid, 1);
     if (tid < 180) tH[tid] = spread(bh);
     tS[tid] = spread(bs);
     tV[tid] = spread(bv);
@@ -738,7 +742,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) v
           const uint32_t bl = rescale(band_px(cur, 0, j)), gr = rescale(band_px(cur, 1, j)),
                          rd = rescale(band_px(cur, 2, j));
           const uint32_t V = max3u(bl, gr, rd);
-          const float rv = __builtin_amdgcn_rcpf((float)max(V, 1u));
+          const float rv = trcp[V];
           uint32_t vc = V;
           if (FILTER) {
             const uint32_t m = (cur.vm >> (8 * j)) & 255u;
@@ -756,7 +760,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) v
             bits = tV[vc];
           } else {
             uint32_t Hh, Ss;
-            hue_sat(rd, gr, bl, V, rv, Hh, Ss);
+            hue_sat(rd, gr, bl, V, rv, trcp, Hh, Ss);
             bits = tH[Hh] & tS[Ss] & tV[vc];
           }
           // byte 0 of the entry (the mask bits) into byte j of bits4
