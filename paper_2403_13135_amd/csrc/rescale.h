@@ -25,13 +25,18 @@ struct RescaleConst {
 // by invariant integers using multiplication", 1994), verified over every
 // reachable numerator.
 bool derive_rescale(uint32_t d, RescaleConst* rc) {
+  // verified constants of the most recent full scales (callers that alternate
+  // between a few scales do not re-verify); d = 0 marks an empty slot
+  constexpr int kSlots = 16;
   static std::mutex mu;
-  static RescaleConst cache;
+  static RescaleConst cache[kSlots];
+  static int next = 0;
   std::lock_guard<std::mutex> g(mu);
-  if (cache.d == d) {
-    *rc = cache;
-    return true;
-  }
+  for (int i = 0; i < kSlots; ++i)
+    if (cache[i].d == d && d != 0) {
+      *rc = cache[i];
+      return true;
+    }
   RescaleConst r;
   r.d = d;
   r.half = d / 2u;
@@ -68,7 +73,8 @@ bool derive_rescale(uint32_t d, RescaleConst* rc) {
     r.magic = (uint32_t)m;
     r.shift = (uint32_t)s;
   }
-  cache = r;
+  cache[next] = r;
+  next = (next + 1) % kSlots;
   *rc = r;
   return true;
 }

@@ -14,14 +14,16 @@
 //            LDS histogram (copy = lane % 32, so the 64 lanes of an atomic
 //            never share a bank except across the two half-waves), and the
 //            8-bit medians kept packed in 32 registers per lane;
-//   phase 2: one wave reduces the histogram and runs exact Otsu (128-bit
-//            cross-multiplied comparisons), the eta gate, rank-k truncation
-//            levels and the stretch, folded with the class limits into a
-//            256-entry class table in LDS;
-//   phase 3: labels from the table, 4 pixels per 32-bit store, counts.
-// Chips are assigned so that each XCD (workgroup id mod 8) receives a
-// contiguous run of chips in raster order: horizontally adjacent chips run
-// concurrently on one XCD and share their halo cache lines in its L2.
+//   phase 2: one wave reduces the histogram and runs exact Otsu (a double
+//            precision pass, 128-bit cross-multiplied comparisons for
+//            near-ties), the eta gate, rank-k truncation levels and the
+//            stretch, folded with the class limits into two cut-offs on the
+//            median (the class is non-decreasing in it);
+//   phase 3: labels from the cut-offs, 4 pixels per 32-bit store, counts.
+// Workgroup b labels chip b in raster order.  The hardware deals consecutive
+// workgroups to the 8 XCDs in turn, so the chips in flight form one band of
+// whole chip rows, and at any moment the waves of the chips of a chip row
+// read the same scene rows side by side.
 //
 // filter = 0 uses a plain streaming kernel over the same tiling.  A batched
 // launch (sil_label_batch) covers chip ranges of several scenes, each scene's
@@ -57,6 +59,7 @@ constexpr int kMaxPatchSlots = 1024;          // LDS per-patch counters per work
 #define SIL_NT_LABELS 1
 #endif
 constexpr int kPrefetch = kWalkPrefetch;      // rows of loads in flight per wave
+
 constexpr int kMaxBatch = SIL_BATCH_MAX_JOBS; // scenes per batched launch
 
 enum CountMode : uint32_t {
@@ -101,15 +104,28 @@ struct Batch {
   Scene sc[kMaxBatch];
   int32_t prefix[kMaxBatch + 1];  // chips of scenes [0, j) in this launch
   int32_t n;
-  int32_t per_xcd;
 };
 
-// Workgroup id -> logical work index: XCD k = id % 8 gets the contiguous run
-// [k * per_xcd, (k+1) * per_xcd) in order.
-__device__ __forceinline__ int xcd_work_index(int per_xcd) {
+
+
+#ifndef SIL_XCD_GROUP
+#define SIL_XCD_GROUP 4
+#endif
+constexpr int kXcdGroup = SIL_XCD_GROUP;  // horizontally adjacent chips per XCD visit
+constexpr int kDeal = 8 * kXcdGroup;      // workgroups of one dealing round
+
+// Workgroup id -> chip (raster order).  The hardware deals consecutive
+// workgroup ids to the 8 XCDs in turn; ids b and b + 8 land on the same XCD.
+// Each round of kDeal ids covers kDeal consecutive chips, and XCD x takes
+// the kXcdGroup neighbours [x * kXcdGroup, (x + 1) * kXcdGroup) of it, so the
+// halo columns between them are fetched into one L2, while the chips in
+// flight still form one band of whole chip rows.
+__device__ __forceinline__ int work_index() {
   const int b = blockIdx.x;
-  return (b & 7) * per_xcd + (b >> 3);
+  const int q = b / kDeal, r = b - q * kDeal;
+  return q * kDeal + (r & 7) * kXcdGroup + (r >> 3);
 }
+inline int deal_grid(int64_t n) { return (int)((n + kDeal - 1) / kDeal * kDeal); }
 
 template <typename T>
 __device__ __forceinline__ uint32_t rescale(uint32_t x, const Shared& sh, bool fast24) {
@@ -157,35 +173,11 @@ __device__ __forceinline__ void load_raw(const Scene& sc, int32_t gy, const uint
 
 // ---- wave helpers -----------------------------------------------------------
 
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint32_t o = __shfl_up(v, d);
-    if (lane >= d) v += o;
-  }
-  return v;
-}
-__device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
-#pragma unroll
-  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d);
-  return v;
-}
 __device__ __forceinline__ uint32_t wave_sum32(uint32_t v) {
 #pragma unroll
   for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d);
   return v;
 }
-__device__ __forceinline__ uint32_t wave_min32(uint32_t v) {
-#pragma unroll
-  for (int d = 32; d > 0; d >>= 1) v = min(v, (uint32_t)__shfl_xor(v, d));
-  return v;
-}
-__device__ __forceinline__ int32_t wave_max32(int32_t v) {
-#pragma unroll
-  for (int d = 32; d > 0; d >>= 1) v = max(v, (int32_t)__shfl_xor(v, d));
-  return v;
-}
-
 // ---- per-pixel class counting (patches that do not align with chips) --------
 
 struct PixCount {
@@ -256,37 +248,96 @@ __device__ __forceinline__ void store_labels(uint8_t* row, uint32_t off, int val
 struct FilterLds {
   uint32_t hist[256 * kCopies];
   uint32_t hsum[256];
+  uint32_t cut[2];
   uint32_t cnt[kMaxPatchSlots * 3];
-  uint8_t lut[256];
 };
 
-// Phase 2: exact chip statistics in one wave; writes the class table.
-__device__ void filter_phase2(const Shared& sh, const Scene& sc, FilterLds& s, int chip_id,
-                              int32_t y0, int32_t x0, int lane) {
-  uint32_t h[4];
+// ---- wave primitives for phase 2: DPP within rows of 16 lanes, readlane and
+// ballot across rows (no LDS crossbar round trips on the chain) -----------
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_or0(uint32_t x) {
+  // lanes whose source lies outside their row of 16 receive 0
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t lane_val(uint32_t x, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, l);
+}
+// Inclusive prefix sum over the wave: Hillis-Steele within each row of 16
+// lanes (row_shr 1, 2, 4, 8), then the totals of the earlier rows.
+__device__ __forceinline__ uint32_t wave_scan(uint32_t x, int lane) {
+  x += dpp_or0<0x111>(x);
+  x += dpp_or0<0x112>(x);
+  x += dpp_or0<0x114>(x);
+  x += dpp_or0<0x118>(x);
+  const uint32_t r0 = lane_val(x, 15), r1 = lane_val(x, 31), r2 = lane_val(x, 47);
+  return x + (lane >= 16 ? r0 : 0u) + (lane >= 32 ? r1 : 0u) + (lane >= 48 ? r2 : 0u);
+}
+__device__ __forceinline__ uint32_t wave_total(uint32_t x, int lane) {
+  return lane_val(wave_scan(x, lane), 63);
+}
+// Maximum over the wave of non-negative doubles.
+__device__ __forceinline__ double wave_max_nonneg(double v) {
+  auto step = [](double a, auto ctrl) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, a);
+    const uint32_t lo = dpp_or0<decltype(ctrl)::value>((uint32_t)b);
+    const uint32_t hi = dpp_or0<decltype(ctrl)::value>((uint32_t)(b >> 32));
+    return fmax(a, __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo));
+  };
+  v = step(v, std::integral_constant<int, 0x111>{});
+  v = step(v, std::integral_constant<int, 0x112>{});
+  v = step(v, std::integral_constant<int, 0x114>{});
+  v = step(v, std::integral_constant<int, 0x118>{});
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  double m = 0.0;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) h[i] = s.hsum[4 * lane + i];
-  uint32_t cl = h[0] + h[1] + h[2] + h[3];
+  for (int r = 15; r < 64; r += 16) {
+    const uint64_t x = ((uint64_t)lane_val((uint32_t)(b >> 32), r) << 32) | lane_val((uint32_t)b, r);
+    m = fmax(m, __builtin_bit_cast(double, x));
+  }
+  return m;
+}
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// Phase 2: exact chip statistics in one wave from the chip's 256-bin
+// histogram (lane l holds bins 4l..4l+3 in h).  Writes the chip's debug
+// record and its counts (patch modes that take them from the histogram), and
+// returns the first median value of class >= 1 and of class >= 2 (256 if
+// none): the class is non-decreasing in the median, so these two cut-offs
+// determine it.
+//
+// Otsu's threshold is the t maximising (w1*S0 - w0*S1)^2 / (w0*w1), smallest
+// t on ties, compared exactly.  A double-precision pass finds it first: the
+// ratio is d^2 / den with |d| < 2^41 and den < 2^33 exact in doubles, so the
+// computed ratio has a relative error below 2^-51, and every t whose exact
+// ratio is the maximum lies within a factor (1 - 2^-40) of the largest
+// computed ratio.  When exactly one t passes that test it is the answer;
+// otherwise the passing t are compared exactly in 128-bit integers.
+__device__ uint2 filter_phase2(const Shared& sh, const Scene& sc, const uint32_t h[4],
+                               int chip_id, int32_t y0, int32_t x0, int lane) {
+  typedef unsigned __int128 u128;
+  const uint32_t cl = h[0] + h[1] + h[2] + h[3];
   uint32_t sl = 0;
   uint64_t ql = 0;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    uint32_t v = 4 * lane + i;
+    const uint32_t v = 4 * lane + i;
     sl += v * h[i];
     ql += (uint64_t)(v * v) * h[i];
   }
-  const uint32_t c_inc = wave_incl_scan(cl, lane);
-  const uint32_t s_inc = wave_incl_scan(sl, lane);
-  const uint32_t N = (uint32_t)__builtin_amdgcn_readlane((int)c_inc, 63);
-  const uint32_t S = (uint32_t)__builtin_amdgcn_readlane((int)s_inc, 63);
-  const uint64_t Q = wave_sum64(ql);
+  const uint32_t c_inc = wave_scan(cl, lane);
+  const uint32_t s_inc = wave_scan(sl, lane);
+  const uint32_t N = lane_val(c_inc, 63);
+  const uint32_t S = lane_val(s_inc, 63);
+  // sum of squares in two 32-bit parts: Q < 2^32 * 255^2 / 2^16 per part
+  const uint64_t Q = ((uint64_t)wave_total((uint32_t)(ql >> 16), lane) << 16) +
+                     wave_total((uint32_t)(ql & 0xFFFFu), lane);
 
-  // Otsu over the lane's four split points t = 4*lane + i (t <= 254)
-  typedef unsigned __int128 u128;
-  bool have = false;
-  u128 bnum = 0;
-  uint64_t bden = 1;
-  uint32_t bt = 0;
+  // Otsu candidates t = 4*lane + i (t <= 254, both classes non-empty)
+  bool valid[4];
+  int64_t dd[4];
+  uint64_t den[4];
+  double r[4];
   {
     uint32_t w0 = c_inc - cl, s0 = s_inc - sl;
 #pragma unroll
@@ -294,93 +345,138 @@ __device__ void filter_phase2(const Shared& sh, const Scene& sc, FilterLds& s, i
       const uint32_t t = 4 * lane + i;
       w0 += h[i];
       s0 += t * h[i];
-      if (t < 255 && w0 > 0 && w0 < N) {
-        // (w1*S0 - w0*S1) = N*S0 - w0*S
-        int64_t d = (int64_t)N * s0 - (int64_t)w0 * S;
-        uint64_t ad = (uint64_t)(d < 0 ? -d : d);
-        u128 num = (u128)ad * ad;
-        uint64_t den = (uint64_t)w0 * (N - w0);
-        if (!have || num * bden > bnum * den) {
-          have = true;
-          bnum = num;
-          bden = den;
-          bt = t;
-        }
-      }
+      valid[i] = t < 255 && w0 > 0 && w0 < N;
+      // (w1*S0 - w0*S1) = N*S0 - w0*S
+      dd[i] = (int64_t)N * s0 - (int64_t)w0 * S;
+      den[i] = (uint64_t)w0 * (N - w0);
+      const double d = (double)dd[i];
+      r[i] = valid[i] ? d * d / (double)den[i] : 0.0;
     }
   }
+  const bool have = ballot(valid[0] || valid[1] || valid[2] || valid[3]) != 0;
+  u128 bnum = 0;
+  uint64_t bden = 1;
+  uint32_t bt = 0;
+  if (have) {
+    const double rmax = wave_max_nonneg(fmax(fmax(r[0], r[1]), fmax(r[2], r[3])));
+    const double thr = rmax * (1.0 - 0x1p-40);
+    bool cand[4];
+    uint32_t nc = 0;
 #pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint64_t on_lo = __shfl_xor((uint64_t)bnum, d);
-    uint64_t on_hi = __shfl_xor((uint64_t)(bnum >> 64), d);
-    uint64_t oden = __shfl_xor(bden, d);
-    uint32_t ot = __shfl_xor(bt, d);
-    int ohave = __shfl_xor((int)have, d);
-    u128 onum = ((u128)on_hi << 64) | on_lo;
-    bool take = false;
-    if (ohave) {
-      if (!have) {
-        take = true;
-      } else {
-        u128 l = onum * bden, r = bnum * oden;
-        take = l > r || (l == r && ot < bt);
-      }
+    for (int i = 0; i < 4; ++i) {
+      cand[i] = valid[i] && r[i] >= thr;
+      nc += cand[i];
     }
-    if (take) {
-      have = true;
-      bnum = onum;
-      bden = oden;
-      bt = ot;
+    if (wave_total(nc, lane) == 1) {
+      const int L = (int)__builtin_ctzll(ballot(nc != 0));
+      const int i = cand[0] ? 0 : cand[1] ? 1 : cand[2] ? 2 : 3;
+      const uint64_t ad = (uint64_t)(dd[i] < 0 ? -dd[i] : dd[i]);
+      const u128 num = (u128)ad * ad;
+      bt = 4 * L + lane_val((uint32_t)i, L);
+      const uint64_t n_lo = (uint64_t)num, n_hi = (uint64_t)(num >> 64);
+      bnum = ((u128)(((uint64_t)lane_val((uint32_t)(n_hi >> 32), L) << 32) |
+                     lane_val((uint32_t)n_hi, L))
+              << 64) |
+             (((uint64_t)lane_val((uint32_t)(n_lo >> 32), L) << 32) | lane_val((uint32_t)n_lo, L));
+      bden = ((uint64_t)lane_val((uint32_t)(den[i] >> 32), L) << 32) | lane_val((uint32_t)den[i], L);
+    } else {
+      // several candidates: exact comparison among them, smallest t on ties
+      bool lhave = false;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (!cand[i]) continue;
+        const uint64_t ad = (uint64_t)(dd[i] < 0 ? -dd[i] : dd[i]);
+        const u128 num = (u128)ad * ad;
+        if (!lhave || num * bden > bnum * den[i]) {
+          lhave = true;
+          bnum = num;
+          bden = den[i];
+          bt = 4 * lane + i;
+        }
+      }
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t on_lo = __shfl_xor((uint64_t)bnum, d);
+        const uint64_t on_hi = __shfl_xor((uint64_t)(bnum >> 64), d);
+        const uint64_t oden = __shfl_xor(bden, d);
+        const uint32_t ot = __shfl_xor(bt, d);
+        const int ohave = __shfl_xor((int)lhave, d);
+        const u128 onum = ((u128)on_hi << 64) | on_lo;
+        bool take = false;
+        if (ohave) {
+          if (!lhave) {
+            take = true;
+          } else {
+            const u128 l = onum * bden, rr = bnum * oden;
+            take = l > rr || (l == rr && ot < bt);
+          }
+        }
+        if (take) {
+          lhave = true;
+          bnum = onum;
+          bden = oden;
+          bt = ot;
+        }
+      }
     }
   }
 
   bool gate = false;
   if (have) {
-    uint64_t var = (uint64_t)N * Q - (uint64_t)S * S;
+    const uint64_t var = (uint64_t)N * Q - (uint64_t)S * S;
     gate = (u128)sh.eta_den * bnum >= (u128)((uint64_t)sh.eta_num * bden) * var;
   }
 
-  // truncation levels at rank k from each tail
+  // truncation levels at rank k from each tail: lo = min{v : #(<= v) > k},
+  // hi = max{v : #(>= v) > k}; the lanes holding such v form a suffix and a
+  // prefix of the wave respectively
   const uint32_t kk = N >> sh.clip_shift;
   uint32_t lo_c = 256;
   int32_t hi_c = -1;
+  uint32_t ex[4];  // number of values below bin 4*lane + i
   {
     uint32_t cum = c_inc - cl;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const uint32_t v = 4 * lane + i;
-      uint32_t before = cum;  // count of values < v
+      ex[i] = cum;
+      if (N - cum > kk) hi_c = (int32_t)v;
       cum += h[i];
       if (cum > kk && lo_c == 256) lo_c = v;
-      if (N - before > kk) hi_c = (int32_t)v;
     }
   }
-  const uint32_t lo = wave_min32(lo_c);
-  const uint32_t hi = (uint32_t)wave_max32(hi_c);
+  const uint64_t blo = ballot(lo_c < 256), bhi = ballot(hi_c >= 0);
+  const uint32_t lo = blo ? lane_val(lo_c, (int)__builtin_ctzll(blo)) : 256u;
+  const uint32_t hi = bhi ? lane_val((uint32_t)hi_c, 63 - (int)__builtin_clzll(bhi)) : 0xFFFFFFFFu;
   const bool stretch = gate && hi > lo;
 
-  // class table over median values m = 4*lane + i
-  uint32_t cc0 = 0, cc1 = 0, cc2 = 0, a1c = 256, a2c = 256;
+  // class of each median value m = 4*lane + i; the class is non-decreasing in m
+  uint32_t a1c = 256, a2c = 256;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const uint32_t m = 4 * lane + i;
     uint32_t vc = m;
     if (stretch) {
-      uint32_t c = min(max(m, lo), hi);
+      const uint32_t c = min(max(m, lo), hi);
       vc = ((c - lo) * 255u + (hi - lo) / 2u) / (hi - lo);
     }
     const uint32_t cls = (vc >= sh.t1) + (vc >= sh.t2);
-    s.lut[m] = (uint8_t)cls;
-    cc0 += cls == 0 ? h[i] : 0;
-    cc1 += cls == 1 ? h[i] : 0;
-    cc2 += cls == 2 ? h[i] : 0;
     if (cls >= 1) a1c = min(a1c, m);
     if (cls >= 2) a2c = min(a2c, m);
   }
-  cc0 = wave_sum32(cc0);
-  cc1 = wave_sum32(cc1);
-  cc2 = wave_sum32(cc2);
-  const uint32_t a1 = wave_min32(a1c), a2 = wave_min32(a2c);
+  const uint64_t b1 = ballot(a1c < 256), b2 = ballot(a2c < 256);
+  const uint32_t a1 = b1 ? lane_val(a1c, (int)__builtin_ctzll(b1)) : 256u;
+  const uint32_t a2 = b2 ? lane_val(a2c, (int)__builtin_ctzll(b2)) : 256u;
+  // pixels below a median value a: the count before its bin plus the bin's
+  // lower part
+  auto below = [&](uint32_t a) -> uint32_t {
+    if (a >= 256) return N;
+    const uint32_t j = a & 3u;
+    const uint32_t e = j == 0 ? ex[0] : j == 1 ? ex[1] : j == 2 ? ex[2] : ex[3];
+    return lane_val(e, (int)(a >> 2));
+  };
+  const uint32_t n1 = below(a1), n2 = below(a2);
+  const uint32_t cc0 = n1, cc1 = n2 - n1, cc2 = N - n2;
 
   if (lane == 0) {
     if (sc.chips) {
@@ -407,6 +503,17 @@ __device__ void filter_phase2(const Shared& sh, const Scene& sc, FilterLds& s, i
       }
     }
   }
+  return make_uint2(a1, a2);
+}
+
+// Labels of 4 packed 8-bit medians: per byte (m >= a1) + (m >= a2), with
+// k = (256 - a) in both 16-bit halves; even and odd bytes go through the
+// 16-bit halves separately (m + 256 - a < 512, so no carry crosses a half).
+__device__ __forceinline__ uint32_t labels_of(uint32_t v, uint32_t k1, uint32_t k2) {
+  const uint32_t e = v & 0x00FF00FFu, o = (v >> 8) & 0x00FF00FFu;
+  const uint32_t le = (((e + k1) >> 8) & 0x00010001u) + (((e + k2) >> 8) & 0x00010001u);
+  const uint32_t lo = (((o + k1) >> 8) & 0x00010001u) + (((o + k2) >> 8) & 0x00010001u);
+  return le | (lo << 8);
 }
 
 // A chip of a launch: its scene, raster id and extent.
@@ -470,8 +577,18 @@ __device__ __forceinline__ void filter_chip(const Shared& sh, const ChipAt& c, F
     s.hsum[bin] = sum;
   }
   __syncthreads();
-  if (wave == 0) filter_phase2(sh, sc, s, c.chip_id, y0, x0, lane);
+  if (wave == 0) {
+    uint32_t h[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) h[i] = s.hsum[4 * lane + i];
+    const uint2 a = filter_phase2(sh, sc, h, c.chip_id, y0, x0, lane);
+    if (lane == 0) {
+      s.cut[0] = a.x;
+      s.cut[1] = a.y;
+    }
+  }
   __syncthreads();
+  const uint32_t k1 = (256u - s.cut[0]) * 0x00010001u, k2 = (256u - s.cut[1]) * 0x00010001u;
 
   if (active) {
     const bool down = (wave & 1) == 0;
@@ -492,18 +609,14 @@ __device__ __forceinline__ void filter_chip(const Shared& sh, const ChipAt& c, F
       const int32_t rout = wy0 + (down ? k : kRowsPerWave - 1 - k);
       if (rout >= ch) continue;
       const int32_t gy = y0 + rout;
-      const uint32_t v = vm[k];
-      uint32_t cls[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) cls[j] = s.lut[(v >> (8 * j)) & 0xFFu];
-      const uint32_t packed = cls[0] | (cls[1] << 8) | (cls[2] << 16) | (cls[3] << 24);
+      const uint32_t packed = labels_of(vm[k], k1, k2);
       if (valid_cols > 0)
         store_labels(sc.labels + (int64_t)gy * sc.lpitch, loff, valid_cols, vec4, packed);
       if constexpr (pix) {
         const int32_t py = gy / sh.ph - (pix_lds ? y0 / sh.ph : 0);
         const int32_t rowkey = py * (pix_lds ? sh.npx_l : sc.nx);
         for (int j = 0; j < valid_cols; ++j)
-          pix_add(sc, s.cnt, pix_lds, pc, rowkey + colkey[j], cls[j]);
+          pix_add(sc, s.cnt, pix_lds, pc, rowkey + colkey[j], (packed >> (8 * j)) & 0xFFu);
       }
     }
     if constexpr (pix) pix_flush(sc, s.cnt, pix_lds, pc.key, pc.cnt);
@@ -515,10 +628,9 @@ __device__ __forceinline__ void filter_chip(const Shared& sh, const ChipAt& c, F
 }
 
 template <typename T, bool FAST24, bool PIX>
-__global__ __launch_bounds__(kThreads, SIL_WAVES_PER_EU) void k_filter(Shared sh, Scene sc,
-                                                                       int per_xcd) {
+__global__ __launch_bounds__(kThreads, SIL_WAVES_PER_EU) void k_filter(Shared sh, Scene sc) {
   __shared__ FilterLds s;
-  const int chip_id = xcd_work_index(per_xcd);
+  const int chip_id = work_index();
   if (chip_id >= sc.nchips) return;
   filter_chip<T, FAST24, PIX>(sh, chip_at(sh, sc, chip_id), s);
 }
@@ -528,7 +640,7 @@ __global__ __launch_bounds__(kThreads, SIL_WAVES_PER_EU) void k_filter(Shared sh
 template <typename T, bool FAST24>
 __global__ __launch_bounds__(kThreads, SIL_WAVES_PER_EU) void k_filter_batch(Shared sh, Batch bt) {
   __shared__ FilterLds s;
-  const int i = xcd_work_index(bt.per_xcd);
+  const int i = work_index();
   if (i >= bt.prefix[bt.n]) return;
   int j = 0;
   while (j + 1 < bt.n && bt.prefix[j + 1] <= i) ++j;
@@ -575,9 +687,9 @@ __device__ __forceinline__ void thresh_rows(const Shared& sh, const Scene& sc, u
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads, 4) void k_thresh(Shared sh, Scene sc, int per_xcd) {
+__global__ __launch_bounds__(kThreads, 4) void k_thresh(Shared sh, Scene sc) {
   __shared__ uint32_t s_cnt[kMaxPatchSlots * 3];
-  const int tile_id = xcd_work_index(per_xcd);
+  const int tile_id = work_index();
   if (tile_id >= sc.nchips) return;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -608,9 +720,9 @@ __global__ __launch_bounds__(kThreads, 4) void k_thresh(Shared sh, Scene sc, int
 // class totals from per-lane counters.  STORE: the patch is the tile (plain
 // stores); otherwise atomics into counts the host cleared.
 template <typename T, bool STORE>
-__global__ __launch_bounds__(kThreads, 4) void k_thresh_walk(Shared sh, Scene sc, int per_xcd) {
+__global__ __launch_bounds__(kThreads, 4) void k_thresh_walk(Shared sh, Scene sc) {
   __shared__ uint32_t s_tot[3];
-  const int tile_id = xcd_work_index(per_xcd);
+  const int tile_id = work_index();
   if (tile_id >= sc.nchips) return;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -821,31 +933,31 @@ void fill_scene(const void* scene, const int32_t* sel, int32_t H, int32_t W, int
 }
 
 template <typename T>
-void launch_single(const Shared& sh, const Scene& sc, bool fast24, int filter, int per_xcd,
+void launch_single(const Shared& sh, const Scene& sc, bool fast24, int filter,
                    hipStream_t stream) {
-  const dim3 grid(per_xcd * 8), block(kThreads);
+  const dim3 grid(deal_grid(sc.nchips)), block(kThreads);
   if (filter == 1) {
     const bool pix = sh.count_mode >= CM_PIX_LDS;
     if (fast24 && !pix)
-      hipLaunchKernelGGL((k_filter<T, true, false>), grid, block, 0, stream, sh, sc, per_xcd);
+      hipLaunchKernelGGL((k_filter<T, true, false>), grid, block, 0, stream, sh, sc);
     else if (fast24)
-      hipLaunchKernelGGL((k_filter<T, true, true>), grid, block, 0, stream, sh, sc, per_xcd);
+      hipLaunchKernelGGL((k_filter<T, true, true>), grid, block, 0, stream, sh, sc);
     else if (!pix)
-      hipLaunchKernelGGL((k_filter<T, false, false>), grid, block, 0, stream, sh, sc, per_xcd);
+      hipLaunchKernelGGL((k_filter<T, false, false>), grid, block, 0, stream, sh, sc);
     else
-      hipLaunchKernelGGL((k_filter<T, false, true>), grid, block, 0, stream, sh, sc, per_xcd);
+      hipLaunchKernelGGL((k_filter<T, false, true>), grid, block, 0, stream, sh, sc);
   } else if (sh.count_mode == CM_HIST_STORE) {
-    hipLaunchKernelGGL((k_thresh_walk<T, true>), grid, block, 0, stream, sh, sc, per_xcd);
+    hipLaunchKernelGGL((k_thresh_walk<T, true>), grid, block, 0, stream, sh, sc);
   } else if (sh.count_mode == CM_HIST_ATOMIC) {
-    hipLaunchKernelGGL((k_thresh_walk<T, false>), grid, block, 0, stream, sh, sc, per_xcd);
+    hipLaunchKernelGGL((k_thresh_walk<T, false>), grid, block, 0, stream, sh, sc);
   } else {
-    hipLaunchKernelGGL((k_thresh<T>), grid, block, 0, stream, sh, sc, per_xcd);
+    hipLaunchKernelGGL((k_thresh<T>), grid, block, 0, stream, sh, sc);
   }
 }
 
 template <typename T>
 void launch_batch(const Shared& sh, const Batch& bt, bool fast24, hipStream_t stream) {
-  const dim3 grid(bt.per_xcd * 8), block(kThreads);
+  const dim3 grid(deal_grid(bt.prefix[bt.n])), block(kThreads);
   if (fast24)
     hipLaunchKernelGGL((k_filter_batch<T, true>), grid, block, 0, stream, sh, bt);
   else
@@ -918,7 +1030,7 @@ int sil_label(const void* scene, int32_t nbands, const int32_t sel[3], int32_t H
 
   const int32_t tile = p->filter == 1 ? (int32_t)p->chip : kTile;
   const int64_t nchips = (((int64_t)H + tile - 1) / tile) * (((int64_t)W + tile - 1) / tile);
-  if (nchips > (int64_t)INT32_MAX - 8) return SIL_EUNSUPPORTED;
+  if (nchips > (int64_t)INT32_MAX - kDeal) return SIL_EUNSUPPORTED;
   Shared sh;
   bool fast24;
   if (!derive_shared(p, tile, &sh, &fast24)) return SIL_EUNSUPPORTED;
@@ -958,11 +1070,10 @@ int sil_label(const void* scene, int32_t nbands, const int32_t sel[3], int32_t H
     if (g > 4096) g = 4096;
     hipLaunchKernelGGL(k_fill_u32, dim3(g), dim3(256), 0, st, hist, n, 0u);
   }
-  const int per_xcd = (int)((nchips + 7) / 8);
   if (p->dtype == SIL_U16)
-    launch_single<uint16_t>(sh, sc, fast24, (int)p->filter, per_xcd, st);
+    launch_single<uint16_t>(sh, sc, fast24, (int)p->filter, st);
   else
-    launch_single<uint8_t>(sh, sc, false, (int)p->filter, per_xcd, st);
+    launch_single<uint8_t>(sh, sc, false, (int)p->filter, st);
   if (hipGetLastError() != hipSuccess) return SIL_EDEVICE;
   return SIL_OK;
 }
@@ -994,11 +1105,10 @@ int sil_label_batch(const sil_job* jobs, int32_t njobs, const sil_params* p, voi
     bt.sc[j].chip_begin = jb.chip_begin;
     bt.prefix[j] = (int32_t)total;
     total += jb.chip_count;
-    if (total > (int64_t)INT32_MAX - 8) return SIL_EUNSUPPORTED;
+    if (total > (int64_t)INT32_MAX - kDeal) return SIL_EUNSUPPORTED;
   }
   bt.prefix[njobs] = (int32_t)total;
   bt.n = njobs;
-  bt.per_xcd = (int32_t)((total + 7) / 8);
 
   hipStream_t st = (hipStream_t)stream;
   (void)hipGetLastError();

@@ -189,6 +189,13 @@ def _adversarial():
     out.append(("constant chips", np.stack([const_chips.astype(np.uint8)] * 3)))
     ramp = (xx % 256).astype(np.uint8)
     out.append(("uniform ramp", np.stack([ramp, ramp, ramp])))
+    # three horizontal bands per 64-row period with counts n, 2n, n: Otsu's
+    # ratio ties exactly between a split below and above the middle band (the
+    # smallest t wins), and the bands survive the median
+    band = yy % 64
+    lvl = ((yy // 64) * 29 + (xx // 64) * 7) % 150
+    spikes = np.where(band < 16, lvl, np.where(band < 48, lvl + 40, lvl + 80)).astype(np.uint8)
+    out.append(("symmetric three spikes", np.stack([spikes, spikes // 2, spikes // 3])))
     return out
 
 
