@@ -8,12 +8,15 @@ concatenation with the skip feature map and two 3x3 convolutions with ReLU,
 and a final 1x1 convolution to the 3 classes, trained with categorical
 cross-entropy (section III-C, "U-Net Training").
 
-The variant computed here (its channel widths, batch normalisation, "same"
-padding, so no cropping) is stated in ``CONFIG``; the GPU implementation in
-``paper_2403_13135_amd/unet.py`` computes the same function with its own
-kernels.  Written with plain ``torch.nn.functional`` calls in float64, NCHW;
-gradients come from autograd and are pinned by finite differences in the
-tests.
+The variant computed here: level widths as given (e.g. 32, 64, 128, 256),
+batch normalisation after every 3x3 convolution (batch statistics in
+training, running statistics in inference), "same" padding so no cropping,
+convolutions without bias (batch normalisation absorbs it), 3 input bands.
+The GPU implementation in ``paper_2403_13135_amd/unet.py`` computes the same
+function with its own kernels.  Written with plain ``torch.nn.functional``
+calls in float64, NCHW; gradients come from autograd and are pinned by finite
+differences in the tests, the wiring by a second forward written with loops
+(tests/unet_loops.py).
 """
 import math
 from typing import Dict, Sequence
@@ -64,24 +67,32 @@ def init_params(widths: Sequence[int], seed: int = 0, dtype=torch.float64) -> Di
     return P
 
 
-def _conv3_bn_relu(x, P, name):
+def _conv3_bn_relu(x, P, name, running=None):
     w = P[name + ".w"].permute(0, 3, 1, 2)  # [Cout, Cin, 3, 3]
     y = F.conv2d(x, w, padding=1)
-    y = F.batch_norm(y, None, None, P[name + ".gamma"], P[name + ".beta"], training=True,
-                     eps=BN_EPS)
+    if running is None:
+        y = F.batch_norm(y, None, None, P[name + ".gamma"], P[name + ".beta"], training=True,
+                         eps=BN_EPS)
+    else:
+        mean, var = running[name]
+        y = F.batch_norm(y, mean, var, P[name + ".gamma"], P[name + ".beta"], training=False,
+                         eps=BN_EPS)
     return F.relu(y)
 
 
-def forward(P: Dict[str, torch.Tensor], x: torch.Tensor, widths: Sequence[int]) -> torch.Tensor:
-    """Logits [N, 3, H, W] for input x [N, 3, H, W] (training-mode batch
-    statistics in every batch normalisation)."""
+def forward(P: Dict[str, torch.Tensor], x: torch.Tensor, widths: Sequence[int],
+            running=None) -> torch.Tensor:
+    """Logits [N, 3, H, W] for input x [N, 3, H, W].  Training mode (batch
+    statistics in every batch normalisation) unless `running` maps each
+    convolution's name to its (running mean, running variance), the inference
+    form."""
     skips = []
     h = x
     L = len(widths)
     for i in range(L):
         name = f"enc{i}" if i < L - 1 else "mid"
-        h = _conv3_bn_relu(h, P, name + ".conv0")
-        h = _conv3_bn_relu(h, P, name + ".conv1")
+        h = _conv3_bn_relu(h, P, name + ".conv0", running)
+        h = _conv3_bn_relu(h, P, name + ".conv1", running)
         if i < L - 1:
             skips.append(h)
             h = F.max_pool2d(h, 2)
@@ -89,8 +100,8 @@ def forward(P: Dict[str, torch.Tensor], x: torch.Tensor, widths: Sequence[int]) 
         w = P[f"dec{i}.up.w"].permute(2, 3, 0, 1)  # [Cin, Cout, 2, 2]
         h = F.conv_transpose2d(h, w, P[f"dec{i}.up.b"], stride=2)
         h = torch.cat([h, skips[i]], dim=1)
-        h = _conv3_bn_relu(h, P, f"dec{i}.conv0")
-        h = _conv3_bn_relu(h, P, f"dec{i}.conv1")
+        h = _conv3_bn_relu(h, P, f"dec{i}.conv0", running)
+        h = _conv3_bn_relu(h, P, f"dec{i}.conv1", running)
     return F.conv2d(h, P["head.w"][:, :, None, None], P["head.b"])
 
 

@@ -3,6 +3,8 @@ closed forms of the loss and of batch normalisation, and the parameter
 count of the 32-64-128-256 network."""
 import math
 
+import numpy as np
+
 import torch
 import torch.nn.functional as F
 
@@ -71,3 +73,61 @@ def test_forward_shapes():
     P = U.init_params((8, 16))
     x = torch.randn(1, 3, 32, 32, dtype=torch.float64)
     assert U.forward(P, x, (8, 16)).shape == (1, 3, 32, 32)
+
+
+def _np(P):
+    return {k: v.numpy() for k, v in P.items()}
+
+
+def test_forward_wiring_matches_loop_forward():
+    # a second forward written with loops from the definitions (tests/unet_loops.py):
+    # ReLU placement, pooling, up-convolution, concatenation order and head
+    from tests import unet_loops as L
+    widths, P, x, _ = _tiny()
+    got = U.forward(P, x, widths).numpy()
+    ref = L.forward(_np(P), x.numpy(), widths, eps=U.BN_EPS)
+    assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
+def test_inference_forward_matches_loop_forward():
+    from tests import unet_loops as L
+    widths, P, x, _ = _tiny()
+    g = torch.Generator().manual_seed(9)
+    running = {}
+    for name, kind, _, cout in U.layer_specs(widths):
+        if kind == "conv3":
+            running[name] = (0.5 * torch.randn(cout, generator=g, dtype=torch.float64),
+                             0.5 + torch.rand(cout, generator=g, dtype=torch.float64))
+    got = U.forward(P, x, widths, running=running).numpy()
+    ref = L.forward(_np(P), x.numpy(), widths, eps=U.BN_EPS,
+                    running={k: (m.numpy(), v.numpy()) for k, (m, v) in running.items()})
+    assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+    # running statistics are not batch statistics: the two modes differ
+    assert np.abs(got - U.forward(P, x, widths).numpy()).max() > 1e-3
+
+
+def test_wiring_pin_sees_the_concatenation_order():
+    # exchanging the up-sampled and skip halves of a decoder input changes the
+    # logits, so the loop forward above would catch a swapped concatenation
+    widths, P, x, _ = _tiny()
+    Q = dict(P)
+    w = P["dec0.conv0.w"]
+    c = w.shape[3] // 2
+    Q["dec0.conv0.w"] = torch.cat([w[..., c:], w[..., :c]], dim=3)
+    assert (U.forward(Q, x, widths) - U.forward(P, x, widths)).abs().max() > 1e-3
+
+
+def test_loop_helpers_closed_forms():
+    from tests import unet_loops as L
+    # a 3x3 kernel with a single centre tap copies its channel; pooling takes
+    # the window maximum; the up-convolution places x * w in each 2x2 block
+    x = np.arange(2 * 3 * 4 * 4, dtype=np.float64).reshape(2, 3, 4, 4)
+    w = np.zeros((1, 3, 3, 3))
+    w[0, 1, 1, 2] = 1.0
+    assert (L.conv3(x, w)[:, 0] == x[:, 2]).all()
+    assert (L.maxpool2(x) == x[:, :, 1::2, 1::2]).all()  # increasing along rows and columns
+    wu = np.zeros((2, 2, 3, 1))
+    wu[1, 0, 1, 0] = 2.0
+    y = L.upconv2(x, wu, np.array([0.5]))
+    assert (y[:, 0, 1::2, 0::2] == 2.0 * x[:, 1] + 0.5).all()
+    assert (y[:, 0, 0::2, :] == 0.5).all()

@@ -1,8 +1,11 @@
-"""GPU tests of the U-Net kernels: each MFMA convolution against a float32
-CPU reference of the same operation (bf16-exact inputs, so only summation
-order differs), the whole network's loss, logits and gradients against the
-float64 oracle (oracle/unet_ref.py) on an 8-16 channel variant at 32x32, and
-a few training steps lowering the loss."""
+"""GPU tests of the U-Net: each MFMA convolution against a float64 CPU
+computation of the same operation on bf16-exact inputs, element by element
+(|gpu - ref| <= 2^-8 |ref| for bf16 outputs plus the float32 summation error
+of the terms, K u sum|terms| with u = 2^-24); the whole network's loss,
+logits and gradients against the float64 oracle (oracle/unet_ref.py) and its
+bf16-storage emulation (tests/unet_bf16.py) on an 8-16 channel variant; the
+inference path against the oracle's running-statistics forward; and a few
+training steps lowering the loss."""
 import sys
 
 import numpy as np
@@ -40,6 +43,37 @@ def _rel(a, b):
     return (a - b).norm().item() / max(b.norm().item(), 1e-30)
 
 
+U32 = 2.0 ** -24
+BF = 2.0 ** -8
+
+
+def _check(got, ref, bound, what):
+    got = got.detach().double().cpu()
+    ref = ref.detach().double().cpu()
+    bound = torch.as_tensor(bound, dtype=torch.float64).cpu()
+    err = (got - ref).abs()
+    bad = err > bound
+    if bad.any():
+        i = tuple(int(v) for v in bad.nonzero()[0])
+        raise AssertionError(f"{what}: {int(bad.sum())} of {bad.numel()} elements out of bound; "
+                             f"first {i}: gpu {got[i].item():.7g} ref {ref[i].item():.7g} "
+                             f"bound {bound.expand_as(err)[i].item():.3g}")
+
+
+def _conv_refs(x, w, dy):
+    """float64 conv, its input and weight gradients, and the same with |x|,
+    |w|, |dy| (the sums of the terms' magnitudes)."""
+    out = []
+    for xx, ww, dd in ((x, w, dy), (x.abs(), w.abs(), dy.abs())):
+        xr = xx.double().permute(0, 3, 1, 2).requires_grad_(True)
+        wr = ww.double().permute(0, 3, 1, 2).requires_grad_(True)
+        yr = F.conv2d(xr, wr, padding=1)
+        yr.backward(dd.double().permute(0, 3, 1, 2))
+        out.append((yr.detach().permute(0, 2, 3, 1), xr.grad.permute(0, 2, 3, 1),
+                    wr.grad.permute(0, 2, 3, 1)))
+    return out
+
+
 # Shapes reach every tile family: narrow (32-wide) and wide outputs, ragged
 # weight-gradient N tiles (9*cin = 72), N tiles of 96/192/128 with 32-, 64- and
 # 128-row M tiles, a 256 x 256 batch whose tiles outnumber the resident blocks
@@ -59,10 +93,7 @@ def test_conv3x3_forward_and_gradients(un, N, H, W, c0, c1, cout):
     w = _bf((cout, 3, 3, c0 + c1), g, 0.1)
     dy = _bf((N, H, W, cout), g)
     x = x0 if x1 is None else torch.cat([x0, x1], dim=3)
-    xr = x.float().permute(0, 3, 1, 2).requires_grad_(True)
-    wr = w.float().permute(0, 3, 1, 2).requires_grad_(True)
-    yr = F.conv2d(xr, wr, padding=1)
-    yr.backward(dy.float().permute(0, 3, 1, 2))
+    (yref, dxref, dwref), (ya, dxa, dwa) = _conv_refs(x, w, dy)
     # device copies held in variables for the whole test (no aliasing of freed blocks)
     x0c, wc, dyc = x0.cuda(), w.cuda(), dy.cuda()
     x1c = x1.cuda() if x1 is not None else None
@@ -80,16 +111,21 @@ def test_conv3x3_forward_and_gradients(un, N, H, W, c0, c1, cout):
     un._call("sil_unet_conv3x3_wgrad", un._p(dyc), cout, un._p(x0c), c0, un._p(x1c), c1,
              un._p(dw), N, H, W, un._s())
     torch.cuda.synchronize()
-    yref = yr.detach().permute(0, 2, 3, 1)
-    assert _rel(y, yref) < 5e-3  # output rounded to bf16
-    assert _rel(stats[0], yref.sum(dim=(0, 1, 2))) < 1e-4 + 1e-3 * yref.abs().sum().item() / max(
-        yref.sum(dim=(0, 1, 2)).norm().item(), 1)
-    assert _rel(stats[1], (yref * yref).sum(dim=(0, 1, 2))) < 1e-4
-    dxr = xr.grad.permute(0, 2, 3, 1)
-    assert _rel(dx0, dxr[..., :c0]) < 5e-3
+    K = 9 * (c0 + c1)
+    _check(y, yref, BF * yref.abs() + K * U32 * ya, "conv y")
+    # per-channel sums of the float32 outputs over N*H*W pixels (blocked sums
+    # and atomics; 2^-13 of the magnitudes bounds their rounding)
+    s0, s0a = yref.sum(dim=(0, 1, 2)), yref.abs().sum(dim=(0, 1, 2)) + (K * U32 * ya).sum(dim=(0, 1, 2))
+    _check(stats[0], s0, 2.0 ** -13 * s0a, "conv stats sum")
+    s1 = (yref * yref).sum(dim=(0, 1, 2))
+    _check(stats[1], s1, 2.0 ** -13 * s1 + 2 * K * U32 * (yref.abs() * ya).sum(dim=(0, 1, 2)),
+           "conv stats sum of squares")
+    Kd = 9 * cout
+    _check(dx0, dxref[..., :c0], BF * dxref[..., :c0].abs() + Kd * U32 * dxa[..., :c0], "conv dx0")
     if c1:
-        assert _rel(dx1, dxr[..., c0:]) < 5e-3
-    assert _rel(dw, wr.grad.permute(0, 2, 3, 1)) < 1e-4
+        _check(dx1, dxref[..., c0:], BF * dxref[..., c0:].abs() + Kd * U32 * dxa[..., c0:],
+               "conv dx1")
+    _check(dw, dwref, 2.0 ** -13 * dwa, "conv dw")
 
 
 @pytest.mark.parametrize("N,H,W,c0,c1,cout", [(2, 16, 16, 8, 0, 32), (1, 9, 13, 16, 16, 8),
@@ -105,15 +141,19 @@ def test_conv3x3_affine_relu_inference(un, N, H, W, c0, c1, cout):
     scale = torch.rand(cout, generator=g) + 0.5
     shift = torch.randn(cout, generator=g) * 0.3
     x = x0 if x1 is None else torch.cat([x0, x1], dim=3)
-    ref = F.conv2d(x.float().permute(0, 3, 1, 2), w.float().permute(0, 3, 1, 2), padding=1)
-    ref = torch.relu(ref * scale.view(1, -1, 1, 1) + shift.view(1, -1, 1, 1)).permute(0, 2, 3, 1)
+    conv = F.conv2d(x.double().permute(0, 3, 1, 2), w.double().permute(0, 3, 1, 2), padding=1)
+    absc = F.conv2d(x.double().abs().permute(0, 3, 1, 2), w.double().abs().permute(0, 3, 1, 2),
+                    padding=1)
+    sc4, sh4 = scale.double().view(1, -1, 1, 1), shift.double().view(1, -1, 1, 1)
+    ref = torch.relu(conv * sc4 + sh4).permute(0, 2, 3, 1)
+    slack = ((9 * (c0 + c1) + 4) * U32 * (absc * sc4 + sh4.abs())).permute(0, 2, 3, 1)
     x0c, wc, sc, shc = x0.cuda(), w.cuda(), scale.cuda(), shift.cuda()
     x1c = x1.cuda() if x1 is not None else None
     y = torch.empty((N, H, W, cout), dtype=torch.bfloat16, device="cuda")
     un._call("sil_unet_conv3x3_affine_relu", un._p(x0c), c0, un._p(x1c), c1, un._p(wc),
              un._p(sc), un._p(shc), un._p(y), N, H, W, cout, un._s())
     torch.cuda.synchronize()
-    assert _rel(y, ref) < 5e-3
+    _check(y, ref, BF * ref + slack, "conv affine relu")
 
 
 @pytest.mark.parametrize("N,H,W,cin,cout", [(2, 8, 8, 16, 8), (1, 5, 7, 64, 32), (2, 16, 16, 256, 128)])
@@ -124,11 +164,16 @@ def test_upconv_forward_and_gradients(un, N, H, W, cin, cout):
     w = _bf((2, 2, cout, cin), g, 0.1)
     b = torch.randn(cout, generator=g)
     dy = _bf((N, 2 * H, 2 * W, cout), g)
-    xr = x.float().permute(0, 3, 1, 2).requires_grad_(True)
-    wr = w.float().permute(3, 2, 0, 1).contiguous().requires_grad_(True)  # [cin, cout, 2, 2]
-    br = b.clone().requires_grad_(True)
-    yr = F.conv_transpose2d(xr, wr, br, stride=2)
-    yr.backward(dy.float().permute(0, 3, 1, 2))
+    refs = []
+    for xx, ww, bb, dd in ((x, w, b, dy), (x.abs(), w.abs(), b.abs(), dy.abs())):
+        xr = xx.double().permute(0, 3, 1, 2).requires_grad_(True)
+        wr = ww.double().permute(3, 2, 0, 1).contiguous().requires_grad_(True)  # [cin, cout, 2, 2]
+        br = bb.double().clone().requires_grad_(True)
+        yr = F.conv_transpose2d(xr, wr, br, stride=2)
+        yr.backward(dd.double().permute(0, 3, 1, 2))
+        refs.append((yr.detach().permute(0, 2, 3, 1), xr.grad.permute(0, 2, 3, 1),
+                     wr.grad.permute(2, 3, 1, 0), br.grad))
+    (yref, dxref, dwref, dbref), (ya, dxa, dwa, dba) = refs
     y = torch.empty((N, 2 * H, 2 * W, cout), dtype=torch.bfloat16, device="cuda")
     xc, wc, bc, dyc = x.cuda(), w.cuda(), b.cuda(), dy.cuda()
     un._call("sil_unet_upconv", un._p(xc), un._p(wc), un._p(bc), un._p(y), N, H, W, cin, cout,
@@ -143,10 +188,10 @@ def test_upconv_forward_and_gradients(un, N, H, W, cin, cout):
     un._call("sil_unet_upconv_wgrad", un._p(xc), un._p(dyc), un._p(dw), un._p(db), N, H, W, cin,
              cout, un._s())
     torch.cuda.synchronize()
-    assert _rel(y, yr.detach().permute(0, 2, 3, 1)) < 5e-3
-    assert _rel(dx, xr.grad.permute(0, 2, 3, 1)) < 5e-3
-    assert _rel(dw, wr.grad.permute(2, 3, 1, 0)) < 1e-4
-    assert _rel(db, br.grad) < 1e-4
+    _check(y, yref, BF * yref.abs() + (cin + 1) * U32 * ya, "upconv y")
+    _check(dx, dxref, BF * dxref.abs() + 4 * cout * U32 * dxa, "upconv dx")
+    _check(dw, dwref, 2.0 ** -13 * dwa, "upconv dw")
+    _check(db, dbref, 2.0 ** -13 * dba, "upconv db")
 
 
 def _oracle_params(model, widths):
@@ -161,53 +206,108 @@ def _oracle_params(model, widths):
     return P
 
 
-def test_unet_matches_float64_oracle(un):
-    widths = (8, 8, 16, 16)
-    torch.manual_seed(0)
-    model = un.UNet(widths, seed=5)
-    g = torch.Generator().manual_seed(6)
+def _perturbed_model(un, widths, seed=5):
+    model = un.UNet(widths, seed=seed)
+    g = torch.Generator().manual_seed(seed + 1)
     with torch.no_grad():  # non-trivial BN affine and biases
         for k, v in model.params.items():
             if k.endswith((".gamma", ".beta", ".b")):
                 v.add_(0.2 * torch.randn(v.shape, generator=g).cuda())
-    N, H, W = 2, 32, 32
-    x3 = _bf((N, H, W, 3), g)
-    x = torch.zeros((N, H, W, 8), dtype=torch.bfloat16)
+    return model, g
+
+
+def _grad_of(model, k):
+    gg = model.params[k].grad.detach().cpu().double()
+    if k == "enc0.conv0.w":
+        gg = gg[..., :3]
+    elif k.endswith(".up.w"):
+        gg = gg.permute(0, 1, 3, 2)
+    return gg
+
+
+# Whole network, widths 8-8-16-16 on a batch of 8 images of 64 x 64: the
+# bottleneck's batch normalisation averages 8 * 8 * 8 = 512 values per channel.
+WIDTHS, NB, HB = (8, 8, 16, 16), 8, 64
+
+
+def test_unet_matches_float64_oracle_and_bf16_emulation(un):
+    model, g = _perturbed_model(un, WIDTHS)
+    x3 = _bf((NB, HB, HB, 3), g)
+    x = torch.zeros((NB, HB, HB, 8), dtype=torch.bfloat16)
     x[..., :3] = x3
-    labels = torch.randint(0, 3, (N, H, W), generator=g).to(torch.uint8)
-    _say("case unet 8-8-16-16 at 32x32 vs float64 oracle")
+    labels = torch.randint(0, 3, (NB, HB, HB), generator=g).to(torch.uint8)
+    _say(f"case unet {WIDTHS} batch {NB} at {HB}x{HB} vs float64 oracle and bf16 emulation")
     loss, logits = model.forward(x.cuda(), labels.cuda())
     loss.backward()
     torch.cuda.synchronize()
-    P = _oracle_params(model, widths)
+    P = _oracle_params(model, WIDTHS)
     xo = x3.double().permute(0, 3, 1, 2).contiguous()
-    lo, logo, go, _ = U.loss_and_grads(P, xo, labels.long(), widths)
-    assert abs(loss.item() - lo.item()) < 0.02 * lo.item()
-    assert _rel(logits.permute(0, 3, 1, 2), logo) < 0.05
-    # bf16 storage alone (float64 arithmetic, bf16 rounding at the GPU's storage
-    # points) moves the gradients by `emul`; the GPU may not do worse than about
-    # twice that, layers next to the loss must be tight, and the gradient as a
-    # whole must point the same way
-    ge = unet_bf16.grads(P, xo, labels, widths)
-    flat_g, flat_o = [], []
-    bad = {}
-    for k, v in model.params.items():
-        gg = v.grad.detach().cpu().double()
-        if k == "enc0.conv0.w":
-            gg = gg[..., :3]
-        elif k.endswith(".up.w"):
-            gg = gg.permute(0, 1, 3, 2)
-        err, emul = _rel(gg, go[k]), _rel(ge[k], go[k])
-        if err > max(0.05, 2.0 * emul):
-            bad[k] = (round(err, 4), round(emul, 4))
-        flat_g.append(gg.reshape(-1))
-        flat_o.append(go[k].reshape(-1))
+    lo, logo, go, _ = U.loss_and_grads(P, xo, labels.long(), WIDTHS)
+    ge = unet_bf16.grads(P, xo, labels, WIDTHS)
+    with torch.no_grad():
+        loge = unet_bf16.forward(P, xo, WIDTHS)
+    lg = logits.permute(0, 3, 1, 2).detach().double().cpu()
+    _say(f"loss gpu {loss.item():.6f} f64 {lo.item():.6f}; logits max |gpu-emul| "
+         f"{(lg - loge).abs().max().item():.4g} max |gpu-f64| {(lg - logo).abs().max().item():.4g} "
+         f"max |emul-f64| {(loge - logo).abs().max().item():.4g} max |f64| {logo.abs().max().item():.4g}")
+    rows = []
+    for k in model.params:
+        gg = _grad_of(model, k)
+        rows.append((k, _rel(gg, ge[k]), _rel(gg, go[k]), _rel(ge[k], go[k])))
+    for k, e_emul, e_f64, emul_f64 in rows:
+        _say(f"grad {k}: gpu-vs-emul {e_emul:.4f} gpu-vs-f64 {e_f64:.4f} emul-vs-f64 {emul_f64:.4f}")
+    # the GPU tracks the bf16-storage emulation (the same rounding points in
+    # float64 arithmetic): measured at most 0.016 relative per gradient tensor
+    # and 0.005 absolute per logit, bounded at 0.05 and 0.02 (1 + |logit|);
+    # bf16 storage alone moves deep gradients 14-58 % from float64, so float64
+    # is the reference only for the loss and the layers next to it
+    assert abs(loss.item() - lo.item()) <= 2e-3 * lo.item()
+    _check(lg, loge, 0.02 * (1 + loge.abs()), "logits vs bf16 emulation")
+    bad = {k: round(e, 4) for k, e, _, _ in rows if e > 0.05}
     assert not bad, bad
     for k in ("head.w", "head.b", "dec0.conv1.gamma", "dec0.conv1.beta"):
-        gg = model.params[k].grad.detach().cpu().double()
-        assert _rel(gg, go[k]) < 0.02, k
-    cos = F.cosine_similarity(torch.cat(flat_g), torch.cat(flat_o), dim=0).item()
-    assert cos > 0.9, cos
+        assert _rel(_grad_of(model, k), go[k]) < 0.02, k
+
+
+def test_inference_matches_running_statistics_oracle(un):
+    """infer_logits (fused conv + affine + ReLU with running statistics) on
+    new images against the oracle's inference forward with the same running
+    statistics, and against its bf16-storage emulation element by element."""
+    model, g = _perturbed_model(un, WIDTHS, seed=8)
+    opt = un.Adam(model.params, lr=1e-3)
+    x = torch.zeros((NB, HB, HB, 8), dtype=torch.bfloat16)
+    x[..., :3] = _bf((NB, HB, HB, 3), g)
+    labels = torch.randint(0, 3, (NB, HB, HB), generator=g).to(torch.uint8)
+    xc, lc = x.cuda(), labels.cuda()
+    for _ in range(4):  # a few steps so the running statistics move off their start
+        opt.zero_grad()
+        loss, _ = model.forward(xc, lc)
+        loss.backward()
+        opt.step()
+        model.update_running_stats()
+    xt = torch.zeros((2, HB, HB, 8), dtype=torch.bfloat16)
+    xt[..., :3] = _bf((2, HB, HB, 3), g)
+    _say("case unet inference with running statistics vs oracle")
+    out = model.infer_logits(xt.cuda())
+    torch.cuda.synchronize()
+    P = _oracle_params(model, WIDTHS)
+    running = {n: (rm.detach().double().cpu(), rv.detach().double().cpu())
+               for n, (rm, rv) in model.running.items()}
+    xo = xt[..., :3].double().permute(0, 3, 1, 2).contiguous()
+    ref = U.forward(P, xo, WIDTHS, running=running)
+    emul = unet_bf16.forward_infer(P, xo, WIDTHS, running)
+    og = out.permute(0, 3, 1, 2).double().cpu()
+    _say(f"infer: max |gpu-emul| {(og - emul).abs().max().item():.4g} max |gpu-f64| "
+         f"{(og - ref).abs().max().item():.4g} max |emul-f64| {(emul - ref).abs().max().item():.4g} "
+         f"max |f64| {ref.abs().max().item():.4g}; rel gpu-f64 {_rel(og, ref):.4g} "
+         f"emul-f64 {_rel(emul, ref):.4g}")
+    # measured at most 0.024 (a rounding-boundary flip that propagates), bounded at 0.05 (1 + |logit|)
+    _check(og, emul, 0.05 * (1 + emul.abs()), "inference logits vs bf16 emulation")
+    assert _rel(og, ref) <= 2 * _rel(emul, ref) + 1e-3
+    # the same chips in a batch of their own give the same logits
+    solo = model.infer_logits(xt[:1].cuda())
+    torch.cuda.synchronize()
+    assert torch.equal(solo.cpu(), out[:1].cpu())
 
 
 def test_training_steps_reduce_loss(un):
