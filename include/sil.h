@@ -241,6 +241,25 @@ int sil_label_ex(const void* scene, int32_t nbands, const int32_t sel[3], int32_
                  uint32_t* counts, uint8_t* rgb, int64_t rgb_pitch, sil_chip_info* chips,
                  void* workspace, uint64_t workspace_bytes, void* stream);
 
+/* sil_label_ex for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * Same arguments and result as sil_label_ex without the workspace: the
+ * workspace is a 32 MiB array that the library holds on each device for the
+ * life of the process (SIL_LABEL_EX_NOALLOC_MAX bytes, enough for the
+ * sil_label_ex_workspace() of e.g. a 4096 x 4096 scene with 256 x 256 chips or
+ * a 5600 x 5600 one filtered as a whole).  Every call on a device shares that
+ * array, so calls on one device must not overlap in time (their results are
+ * undefined if they do); nothing in it is kept from one call to the next.
+ * Errors: those of sil_label_ex, and SIL_EUNSUPPORTED (before anything is
+ * enqueued) when the scene needs more workspace than the array holds;
+ * SIL_EDEVICE if the array's device address cannot be obtained.  Calls no
+ * allocator. */
+#define SIL_LABEL_EX_NOALLOC_MAX (32ull << 20)
+int sil_label_ex_noalloc(const void* scene, int32_t nbands, const int32_t sel[3], int32_t H,
+                         int32_t W, int64_t pitch, const sil_params* p, uint8_t* masks,
+                         int64_t mask_pitch, uint32_t* counts, uint8_t* rgb, int64_t rgb_pitch,
+                         sil_chip_info* chips, void* stream);
+
 /* Human-readable text of a return code (static storage). */
 const char* sil_strerror(int code);
 

@@ -933,10 +933,15 @@ int sil_label_ex_workspace(int32_t H, int32_t W, const sil_params* p, uint64_t* 
   return SIL_OK;
 }
 
-int sil_label_ex(const void* scene, int32_t nbands, const int32_t sel[3], int32_t H, int32_t W,
-                 int64_t pitch, const sil_params* p, uint8_t* masks, int64_t mask_pitch,
-                 uint32_t* counts, uint8_t* rgb, int64_t rgb_pitch, sil_chip_info* chips,
-                 void* workspace, uint64_t workspace_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// The labelling of sil_label_ex with its workspace given as a device address.
+int label_ex(const void* scene, int32_t nbands, const int32_t sel[3], int32_t H, int32_t W,
+             int64_t pitch, const sil_params* p, uint8_t* masks, int64_t mask_pitch,
+             uint32_t* counts, uint8_t* rgb, int64_t rgb_pitch, sil_chip_info* chips,
+             void* workspace, uint64_t workspace_bytes, void* stream) {
   if (!scene || !masks) return SIL_EINVAL;
   int rc = validate_ex(nbands, sel, H, W, pitch, mask_pitch, p);
   if (rc != SIL_OK) return rc;
@@ -1069,6 +1074,59 @@ int sil_label_ex(const void* scene, int32_t nbands, const int32_t sel[3], int32_
   SIL_EX_APPLY(0, 1, 1) SIL_EX_APPLY(0, 1, 0) SIL_EX_APPLY(0, 0, 1) SIL_EX_APPLY(0, 0, 0)
 #undef SIL_EX_APPLY
   return hipGetLastError() == hipSuccess ? SIL_OK : SIL_EDEVICE;
+}
+
+// Workspace of sil_label_ex_noalloc: one array per device, held for the life
+// of the process.  Host code uses the device address that hipGetSymbolAddress
+// returns for the current device, never the array's own name.
+constexpr uint64_t kScratchBytes = SIL_LABEL_EX_NOALLOC_MAX;
+__device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[kMaxDevices];
+
+// The current device's scratch address, looked up once per device.
+void* device_scratch() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> g(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    scratch_ptr[dev] = ptr;
+  }
+  return scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+int sil_label_ex(const void* scene, int32_t nbands, const int32_t sel[3], int32_t H, int32_t W,
+                 int64_t pitch, const sil_params* p, uint8_t* masks, int64_t mask_pitch,
+                 uint32_t* counts, uint8_t* rgb, int64_t rgb_pitch, sil_chip_info* chips,
+                 void* workspace, uint64_t workspace_bytes, void* stream) {
+  return label_ex(scene, nbands, sel, H, W, pitch, p, masks, mask_pitch, counts, rgb, rgb_pitch,
+                  chips, workspace, workspace_bytes, stream);
+}
+
+int sil_label_ex_noalloc(const void* scene, int32_t nbands, const int32_t sel[3], int32_t H,
+                         int32_t W, int64_t pitch, const sil_params* p, uint8_t* masks,
+                         int64_t mask_pitch, uint32_t* counts, uint8_t* rgb, int64_t rgb_pitch,
+                         sil_chip_info* chips, void* stream) {
+  if (!scene || !masks) return SIL_EINVAL;
+  const int rc = validate_ex(nbands, sel, H, W, pitch, mask_pitch, p);
+  if (rc != SIL_OK) return rc;
+  const uint64_t need = (uint64_t)layout(H, W, p).total;
+  if (need > kScratchBytes) return SIL_EUNSUPPORTED;
+  void* ws = nullptr;
+  if (need) {
+    ws = device_scratch();
+    if (!ws) return SIL_EDEVICE;
+  }
+  return label_ex(scene, nbands, sel, H, W, pitch, p, masks, mask_pitch, counts, rgb, rgb_pitch,
+                  chips, ws, need, stream);
 }
 
 }  // extern "C"

@@ -107,6 +107,8 @@ def lib() -> ctypes.CDLL:
                                    ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
         L.sil_label_ex.restype = ctypes.c_int
+        L.sil_label_ex_noalloc.argtypes = L.sil_label_ex.argtypes[:-3] + [ctypes.c_void_p]
+        L.sil_label_ex_noalloc.restype = ctypes.c_int
         L.sil_strerror.argtypes = [ctypes.c_int]
         L.sil_strerror.restype = ctypes.c_char_p
         if L.sil_abi_version() != ABI_VERSION:
@@ -321,7 +323,8 @@ def workspace_bytes(H: int, W: int, params: Params) -> int:
 def label_ex(scene: torch.Tensor, params: Optional[Params] = None, sel=(0, 1, 2),
              W: Optional[int] = None, counts: bool = True, rgb: bool = False,
              chips: bool = False, workspace: Optional[torch.Tensor] = None,
-             out: Optional[dict] = None, stream: Optional[torch.cuda.Stream] = None) -> dict:
+             out: Optional[dict] = None, stream: Optional[torch.cuda.Stream] = None,
+             noalloc: bool = False) -> dict:
     """The general labeller ``sil_label_ex`` on ``scene`` ([nbands, H, pitch]
     on the GPU): full-HSV masks, any filter unit, optional filtered colour.
 
@@ -331,7 +334,9 @@ def label_ex(scene: torch.Tensor, params: Optional[Params] = None, sel=(0, 1, 2)
     ``chips`` (raw [ncy, ncx, 12] sil_chip_info bytes, if asked).  ``out`` may
     hold preallocated tensors under the same keys; ``workspace`` a uint8 GPU
     tensor of at least ``workspace_bytes`` bytes (allocated here if omitted).
-    Enqueued on ``stream`` (default: the current stream); not synchronised.
+    ``noalloc`` calls ``sil_label_ex_noalloc`` instead, whose workspace is the
+    library's own per-device array (no workspace argument).  Enqueued on
+    ``stream`` (default: the current stream); not synchronised.
     """
     if params is None:
         params = Params(dtype=U16 if scene.dtype in _SCENE_DTYPES[U16] else U8)
@@ -376,23 +381,24 @@ def label_ex(scene: torch.Tensor, params: Optional[Params] = None, sel=(0, 1, 2)
             chip_t = out["chips"] = torch.zeros(
                 ((H + C - 1) // C, (W + C - 1) // C, CHIP_INFO_BYTES), dtype=torch.uint8,
                 device=dev)
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    sel_c = (ctypes.c_int32 * 3)(*[int(v) for v in sel])
+    p = params.to_c()
+    args = [ctypes.c_void_p(scene.data_ptr()), nb, sel_c, H, W, pitch, ctypes.byref(p),
+            ctypes.c_void_p(masks.data_ptr()), masks.stride(0),
+            ctypes.c_void_p(cnt.data_ptr()) if cnt is not None else None,
+            ctypes.c_void_p(col.data_ptr()) if col is not None else None,
+            col.stride(1) if col is not None else 0,
+            ctypes.c_void_p(chip_t.data_ptr()) if chip_t is not None else None]
+    if noalloc:
+        _check(lib().sil_label_ex_noalloc(*args, ctypes.c_void_p(s.cuda_stream)))
+        return out
     need = workspace_bytes(H, W, params)
     if need and workspace is None:
         workspace = torch.empty((need,), dtype=torch.uint8, device=dev)
     if need and (workspace.dtype != torch.uint8 or workspace.numel() < need
                  or not workspace.is_cuda):
         raise ValueError(f"workspace must be a uint8 GPU tensor of >= {need} bytes")
-    s = stream if stream is not None else torch.cuda.current_stream(dev)
-    sel_c = (ctypes.c_int32 * 3)(*[int(v) for v in sel])
-    p = params.to_c()
-    rc = lib().sil_label_ex(
-        ctypes.c_void_p(scene.data_ptr()), nb, sel_c, H, W, pitch, ctypes.byref(p),
-        ctypes.c_void_p(masks.data_ptr()), masks.stride(0),
-        ctypes.c_void_p(cnt.data_ptr()) if cnt is not None else None,
-        ctypes.c_void_p(col.data_ptr()) if col is not None else None,
-        col.stride(1) if col is not None else 0,
-        ctypes.c_void_p(chip_t.data_ptr()) if chip_t is not None else None,
-        ctypes.c_void_p(workspace.data_ptr()) if need else None, need,
-        ctypes.c_void_p(s.cuda_stream))
-    _check(rc)
+    _check(lib().sil_label_ex(*args, ctypes.c_void_p(workspace.data_ptr()) if need else None,
+                              need, ctypes.c_void_p(s.cuda_stream)))
     return out
