@@ -190,14 +190,16 @@ def run_serving(n_requests, chips_per_launch, seeds_per_size=2):
     return out
 
 
-def run_learned(steps, n_fallback):
+def run_learned(steps, n_fallback, n_capacity, fb_batch, seeds_per_size):
     """U-Net (32-64-128-256) trained on GPU auto-labels at batch 32 of 256^2
     chips: step time and MFMA throughput, held-out accuracy against the
-    synthetic truth beside the labeller, and serving with the labeller as
-    fallback on mixed-size scenes."""
+    synthetic truth beside the labeller.  Then serving with the labeller as
+    fallback on the serving trace's mixed sizes: continuous batching of
+    chips across requests (learn.serve_mix), capacity from a burst of
+    `n_capacity` requests, Poisson arrivals at 0.5 and 0.8 of it."""
     import numpy as np
     import torch
-    from paper_2403_13135_amd import learn, serve, sil, unet
+    from paper_2403_13135_amd import learn, serve, unet
 
     widths = (32, 64, 128, 256)
     train_sc = learn.make_scenes(12, 2048, seed0=3000)
@@ -214,26 +216,44 @@ def run_learned(steps, n_fallback):
            "loss_first_last": [losses[0], float(np.mean(losses[-10:]))], "held_out": ev}
     del X, Y, train_sc
     torch.cuda.empty_cache()
-    # serving with fallback: mixed sizes as in the serving trace
-    rng = np.random.default_rng(5)
-    import synth
-    scenes = []
-    for i in range(n_fallback):
-        n = serve.SIZES[int(rng.integers(0, len(serve.SIZES)))]
-        spec = synth.SceneSpec(n, n, 6000 + i, "u16",
-                               synth.blobs_for_coverage(n, n, 6000 + i, 1, 1, 0.10),
-                               synth.blobs_for_coverage(n, n, 6000 + i, 2, 1, 0.05))
-        scenes.append(torch.from_numpy(synth.generate(spec).view(np.int16)).cuda())
-    torch.cuda.synchronize()
-    recs = learn.serve_with_fallback(model, scenes, threshold=0.02)
-    ms = np.array([r["ms"] for r in recs])
-    px = sum(r["H"] * r["W"] for r in recs)
-    out["serving_with_fallback"] = {
-        "requests": n_fallback, "gpx_s": px / (ms.sum() * 1e-3) / 1e9,
-        "p50_ms": float(np.percentile(ms, 50)), "p99_ms": float(np.percentile(ms, 99)),
-        "mean_mismatch_vs_labeller": float(np.mean([r["disagreement"] for r in recs])),
-        "fallback_rate": float(np.mean([r["fallback"] for r in recs])),
-        "threshold": 0.02, "sequential": True}
+    if n_fallback <= 0:
+        return out
+    pool = serve.make_pool(seeds_per_size=seeds_per_size)
+    infer_flops_px = learn.unet_flops_per_image(widths) / (learn.CHIP * learn.CHIP)
+
+    def play(n, rate, seed):
+        arr, picks = serve.make_trace(n, rate, pool, seed=seed)
+        scenes = [pool[sz][k][1] for sz, k in picks]
+        recs = learn.serve_mix(model, scenes, arr, threshold=0.02, batch=fb_batch)
+        return recs, picks
+
+    res = {"requests": n_fallback, "sizes": list(serve.SIZES), "scenes_per_size": seeds_per_size,
+           "threshold": 0.02, "chips_per_launch": fb_batch, "sequential": False}
+    recs, picks = play(n_capacity, 0.0, 31)
+    span = max(r.done_ms for r in recs)
+    px = sum(r.H * r.W for r in recs)
+    cap = n_capacity / span  # requests per ms
+    res["capacity"] = {"requests": n_capacity, "span_ms": span, "gpx_s": px / (span * 1e-3) / 1e9,
+                       "requests_per_s": cap * 1e3,
+                       "unet_tflops": px * infer_flops_px / (span * 1e-3) / 1e12}
+    for rho in (0.5, 0.8):
+        recs, picks = play(n_fallback, rho * cap, 33)
+        lat = np.array([r.done_ms - r.arrival_ms for r in recs])
+        span = max(r.done_ms for r in recs)
+        px = sum(r.H * r.W for r in recs)
+        by_size = {}
+        for (sz, _), l in zip(picks, lat):
+            by_size.setdefault(sz, []).append(l)
+        res[f"rho_{rho}"] = {
+            "arrival_rate_per_s": rho * cap * 1e3, "span_ms": span,
+            "throughput_gpx_s": px / (span * 1e-3) / 1e9,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "p99_ms_by_size": {str(k): float(np.percentile(v, 99)) for k, v in by_size.items()},
+            "mean_mismatch_vs_labeller": float(np.mean([r.disagreement for r in recs])),
+            "fallback_rate": float(np.mean([r.fallback for r in recs])),
+            "fallback_rate_at_5pct": float(np.mean([r.disagreement > 0.05 for r in recs])),
+            "fallback_rate_at_10pct": float(np.mean([r.disagreement > 0.10 for r in recs]))}
+    out["serving_with_fallback"] = res
     return out
 
 
@@ -253,7 +273,11 @@ def main():
     ap.add_argument("--chips-per-launch", type=int, default=1024)
     ap.add_argument("--skip-learned", action="store_true", help="omit the U-Net section")
     ap.add_argument("--unet-steps", type=int, default=120)
-    ap.add_argument("--fallback-requests", type=int, default=12)
+    ap.add_argument("--fallback-requests", type=int, default=2000,
+                    help="requests of the serving-with-fallback trace (0: skip)")
+    ap.add_argument("--fallback-capacity-requests", type=int, default=200)
+    ap.add_argument("--fallback-batch", type=int, default=128, help="chips per inference launch")
+    ap.add_argument("--pool-seeds", type=int, default=4, help="scenes per size in the serving pools")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -379,11 +403,12 @@ def main():
     if not args.skip_serving:
         del scene, labels, hist, labels0, hist0
         torch.cuda.empty_cache()
-        serving = run_serving(args.serving_requests, args.chips_per_launch)
+        serving = run_serving(args.serving_requests, args.chips_per_launch, args.pool_seeds)
     learned = None
     if not args.skip_learned:
         torch.cuda.empty_cache()
-        learned = run_learned(args.unet_steps, args.fallback_requests)
+        learned = run_learned(args.unet_steps, args.fallback_requests,
+                              args.fallback_capacity_requests, args.fallback_batch, args.pool_seeds)
 
     out = {
         "metric": "auto-labelled Gpixel/s",

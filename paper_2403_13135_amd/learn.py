@@ -216,3 +216,112 @@ def serve_with_fallback(model: unet.UNet, scenes: List[torch.Tensor], threshold:
         if outputs is not None:
             outputs.append(lab if d > threshold else pred)
     return recs
+
+
+@dataclass
+class Served:
+    """One request of serve_mix: its arrival and completion (ms from the
+    start), pixel disagreement with the labeller and whether the labeller's
+    map was served; `labels` holds the served map when kept."""
+    H: int
+    W: int
+    arrival_ms: float
+    done_ms: float = 0.0
+    disagreement: float = 0.0
+    fallback: bool = False
+    labels: torch.Tensor = None
+
+
+@torch.no_grad()
+def serve_mix(model: unet.UNet, scenes: List[torch.Tensor], arrivals_ms, threshold: float = 0.02,
+              batch: int = 128, max_inflight: int = 2, keep: bool = False) -> List[Served]:
+    """Continuous batching of the learned path: requests (scenes [3, H, W] on
+    the GPU) arrive at `arrivals_ms` (ms from the start, non-decreasing).  An
+    arrived request is labelled at once (sil.label) and its 256 x 256 chips
+    join a FIFO of chips; each inference launch takes up to `batch` chips from
+    the head of that FIFO, whatever request they belong to, so chips of
+    requests that overlap in time share launches.  When a request's last chip
+    is inferred its U-Net map is compared with the labeller's and the labeller
+    map is served if they disagree on more than `threshold` of the pixels.
+    Every kernel treats chips independently, so a request's result does not
+    depend on what it shared launches with.  At most `max_inflight` launches
+    are queued ahead of the GPU.  Returns one record per request, in order."""
+    dev = scenes[0].device
+    p = sil.Params(dtype=sil.U16)
+    recs = [Served(int(s.shape[1]), int(s.shape[2]), float(a)) for s, a in zip(scenes, arrivals_ms)]
+    xbuf = torch.empty((batch, CHIP, CHIP, unet.IN_CH), dtype=torch.bfloat16, device=dev)
+    origins_of = {}
+    stream = torch.cuda.current_stream(dev)
+    start = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    start.synchronize()
+    t0 = time.perf_counter()
+    pending = 0              # next request to admit
+    fifo = []                # [request, origins, next chip, labels, pred]
+    launches = []            # events of queued launches
+    finishing = []           # (request index, event, pinned mismatch count, labels, pred)
+    n = len(scenes)
+    done = 0
+    while done < n:
+        now = (time.perf_counter() - t0) * 1e3
+        while pending < n and recs[pending].arrival_ms <= now:
+            s = scenes[pending]
+            H, W = recs[pending].H, recs[pending].W
+            if (H, W) not in origins_of:
+                origins_of[(H, W)] = torch.from_numpy(all_origins(H, W)).to(dev)
+            lab, _ = sil.label(s, p)
+            pred = torch.empty((H, W), dtype=torch.uint8, device=dev)
+            fifo.append([pending, origins_of[(H, W)], 0, lab, pred])
+            pending += 1
+        if fifo:
+            # one launch: chips from the head of the FIFO, across requests
+            slices, used = [], 0
+            for item in fifo:
+                if used == batch:
+                    break
+                i, org, k0, _, _ = item
+                k1 = min(org.shape[0], k0 + batch - used)
+                unet.chips_input(scenes[i], org[k0:k1], out=xbuf[used:used + k1 - k0])
+                slices.append((item, k0, k1, used))
+                used += k1 - k0
+                item[2] = k1
+            logits = model.infer_logits(xbuf[:used])
+            for item, k0, k1, off in slices:
+                i, org, _, lab, pred = item
+                unet.scatter_argmax(logits[off:off + k1 - k0], org[k0:k1], pred, recs[i].H, recs[i].W)
+                if k1 == org.shape[0]:
+                    mism = (pred != lab).sum().to(torch.int64)
+                    host = torch.empty((), dtype=torch.int64, pin_memory=True)
+                    host.copy_(mism, non_blocking=True)
+                    ev = torch.cuda.Event(enable_timing=True)
+                    ev.record(stream)
+                    finishing.append((i, ev, host, lab, pred))
+            fifo = [item for item in fifo if item[2] < item[1].shape[0]]
+            ev = torch.cuda.Event()
+            ev.record(stream)
+            launches.append(ev)
+            while len(launches) > max_inflight:
+                launches.pop(0).synchronize()
+        elif not finishing:
+            # idle until the next arrival
+            if pending < n:
+                wait = recs[pending].arrival_ms - (time.perf_counter() - t0) * 1e3
+                if wait > 0.2:
+                    time.sleep((wait - 0.1) / 1e3)
+            continue
+        elif not launches or pending >= n:
+            finishing[0][1].synchronize()
+        still = []
+        for i, ev, host, lab, pred in finishing:
+            if ev.query():
+                r = recs[i]
+                r.done_ms = start.elapsed_time(ev)
+                r.disagreement = int(host.item()) / (r.H * r.W)
+                r.fallback = r.disagreement > threshold
+                if keep:
+                    r.labels = lab if r.fallback else pred
+                done += 1
+            else:
+                still.append((i, ev, host, lab, pred))
+        finishing = still
+    return recs

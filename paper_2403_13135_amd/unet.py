@@ -431,12 +431,18 @@ class Adam:
 
 
 def chips_input(scene: torch.Tensor, origins: torch.Tensor, chip: int = 256,
-                refl_max: float = 10000.0) -> torch.Tensor:
-    """bf16 [n, chip, chip, 8] network input from a [3, H, pitch] int16/uint16
-    scene for the chip origins [n, 2] (int32, device)."""
+                refl_max: float = 10000.0, out: torch.Tensor = None) -> torch.Tensor:
+    """bf16 [n, chip, chip, 8] network input from a [3, H, W] int16/uint16
+    scene for the chip origins [n, 2] (int32, device), written to `out` when
+    given (a contiguous [n, chip, chip, 8] bf16 tensor, e.g. a slice of a
+    batch shared by several scenes)."""
     _, H, pitch = scene.shape
     n = origins.shape[0]
-    out = torch.empty((n, chip, chip, IN_CH), dtype=torch.bfloat16, device=scene.device)
+    if out is None:
+        out = torch.empty((n, chip, chip, IN_CH), dtype=torch.bfloat16, device=scene.device)
+    elif out.shape != (n, chip, chip, IN_CH) or out.dtype != torch.bfloat16 \
+            or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous bf16 [{n}, {chip}, {chip}, {IN_CH}] tensor")
     _call("sil_unet_chips_input", _p(scene), H, pitch, pitch, _p(origins.contiguous()), n, chip,
           ctypes.c_float(1.0 / refl_max), _p(out), _s())
     return out

@@ -1,7 +1,9 @@
 """GPU tests of the learned part: U-Net inference is the same for a chip
 alone and in a batch; a short training on the GPU auto-labels learns the
-labeller's classes and is scored against the synthetic truth beside the
-labeller; the labeller takes over when the U-Net disagrees with it."""
+labeller's classes, and networks trained from two seeds score better than
+the labeller against the synthetic truth; the labeller takes over when the
+U-Net disagrees with it; in continuous-batched serving every request gets the
+same map as when served alone."""
 import sys
 
 import numpy as np
@@ -27,16 +29,28 @@ def mods():
 
 
 @pytest.fixture(scope="module")
-def trained(mods):
+def data(mods):
     learn, sil, unet = mods
     train_sc = learn.make_scenes(6, 1024, seed0=7100)
     test_sc = learn.make_scenes(2, 1024, seed0=7200)
     X, Y = learn.build_training_set(train_sc)
-    model = unet.UNet((16, 32, 32, 64), seed=3)
-    _say(f"case training on {X.shape[0]} auto-labelled chips")
-    losses, sec = learn.train(model, X, Y, steps=150, batch=16, lr=2e-3)
+    return X, Y, test_sc
+
+
+def _train(mods, data, seed):
+    learn, sil, unet = mods
+    X, Y, _ = data
+    model = unet.UNet((16, 32, 32, 64), seed=seed)
+    _say(f"case training seed {seed} on {X.shape[0]} auto-labelled chips")
+    losses, sec = learn.train(model, X, Y, steps=150, batch=16, lr=2e-3, seed=seed)
     _say(f"loss {losses[0]:.3f} -> {np.mean(losses[-10:]):.3f}, {sec * 1e3:.1f} ms/step")
-    return model, losses, test_sc
+    return model, losses
+
+
+@pytest.fixture(scope="module")
+def trained(mods, data):
+    model, losses = _train(mods, data, 3)
+    return model, losses, data[2]
 
 
 def test_inference_is_batch_invariant(mods, trained):
@@ -63,6 +77,22 @@ def test_training_learns_the_auto_labels(mods, trained):
     assert ev["unet_labeller_disagreement"] < 0.10
     # ...and, like the labeller, beats the unfiltered thresholds against the truth
     assert ev["unet_vs_truth"] > ev["thresholds_only_vs_truth"]
+
+
+def test_network_beats_the_labeller(mods, trained, data):
+    """Networks trained from two seeds on the auto-labels score better than
+    the labeller that produced those labels, against the synthetic truth of
+    held-out scenes (the paper's comparison of U-Net with and without its
+    auto-labelled training, on synthetic truth instead of manual labels)."""
+    learn, sil, unet = mods
+    model, _, test_sc = trained
+    gains = []
+    for seed, m in ((3, model), (4, _train(mods, data, 4)[0])):
+        ev = learn.evaluate(m, test_sc)
+        gains.append(ev["unet_vs_truth"] - ev["labeller_vs_truth"])
+        _say(f"seed {seed}: unet {ev['unet_vs_truth']:.4f} labeller {ev['labeller_vs_truth']:.4f} "
+             f"gain {gains[-1]:.4f}")
+    assert min(gains) > 0.005, gains
 
 
 def test_fallback_to_the_labeller(mods, trained):
@@ -112,3 +142,36 @@ def test_checkpoint_round_trip(mods, trained, tmp_path):
     open(bad, "wb").write(bytes(raw))
     with pytest.raises(ValueError):
         unet.load_checkpoint(bad)
+
+
+def test_continuous_batched_serving_equals_solo(mods, trained):
+    """Requests of mixed sizes arriving together and staggered share inference
+    launches; each served map (the U-Net's, threshold 1) equals the map of the
+    same request served alone and the sequential path's; with threshold 0
+    every request falls back to its labeller map."""
+    learn, sil, unet = mods
+    import synth
+    model = trained[0]
+    scenes = []
+    for i, (H, W) in enumerate([(512, 512), (700, 900), (1024, 1024), (300, 2048), (512, 512),
+                                (1500, 1100)]):
+        spec = synth.SceneSpec(H, W, 7300 + i, "u16",
+                               synth.blobs_for_coverage(H, W, 7300 + i, 1, 1, 0.10),
+                               synth.blobs_for_coverage(H, W, 7300 + i, 2, 1, 0.05))
+        scenes.append(torch.from_numpy(synth.generate(spec).view(np.int16)).cuda())
+    solo = [learn.serve_mix(model, [s], [0.0], threshold=1.0, batch=8, keep=True)[0]
+            for s in scenes]
+    seq = []
+    learn.serve_with_fallback(model, scenes, threshold=1.0, outputs=seq)
+    for arrivals in ([0.0] * len(scenes), [0.0, 1.0, 2.0, 2.0, 3.0, 30.0]):
+        _say(f"case serve_mix arrivals {arrivals}")
+        mixed = learn.serve_mix(model, scenes, arrivals, threshold=1.0, batch=8, keep=True)
+        for i, (m, a) in enumerate(zip(mixed, solo)):
+            assert not m.fallback and m.done_ms >= m.arrival_ms
+            assert torch.equal(m.labels, a.labels), f"request {i} differs in the mix"
+            assert torch.equal(m.labels, seq[i]), f"request {i} differs from the sequential path"
+            assert m.disagreement == a.disagreement
+    fb = learn.serve_mix(model, scenes, [0.0] * len(scenes), threshold=0.0, batch=8, keep=True)
+    p = sil.Params(dtype=sil.U16)
+    for s, r in zip(scenes, fb):
+        assert r.fallback and torch.equal(r.labels, sil.label(s, p)[0])
