@@ -14,7 +14,7 @@ launch from rocprofv3 FETCH_SIZE + WRITE_SIZE counters, scaled by the same
 counters' reading for a plain copy of known size; it is read from
 profiles/ and reported only while the kernel source is unchanged since the
 counters were taken.  ``cpu_baseline`` is the C oracle, single-threaded, on
-the same tile.
+the same tile: the median of 3 runs, with the host's CPU model and core count.
 """
 import argparse
 import hashlib
@@ -64,6 +64,17 @@ def read_traffic():
         return float(vals["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def calib_copy(nbytes=1 << 30, reps=3):
@@ -125,13 +136,18 @@ def run_variants(sil, scene, H, W, stream, reps=20):
     return out
 
 
-def run_serving(n_requests, chips_per_launch, seeds_per_size=2):
+def run_serving(n_requests, chips_per_launch, seeds_per_size=4):
     """Continuous-batching server on the mixed-size request trace: capacity
     (all requests arriving at once), p50/p99 latency under Poisson arrivals at
     0.5 and 0.8 of capacity, and a bit-exactness pass in which every result
-    is compared with its scene's solo sil_label output."""
+    is compared with its scene's solo sil_label output; every distinct pool
+    scene's solo output is compared with the oracle (host threads).  The same
+    trace with the scenes in page-locked host memory, copied into the
+    server's arena at admission (PCIe included), is reported separately."""
     import numpy as np
     import torch
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import sil_ref as R
     from paper_2403_13135_amd import serve, sil
 
     p = sil.Params(dtype=sil.U16)
@@ -142,12 +158,25 @@ def run_serving(n_requests, chips_per_launch, seeds_per_size=2):
             lab, hist = sil.label(t, p)
             refs[(size, i)] = (lab, hist)
     torch.cuda.synchronize()
-    out = {"requests": n_requests, "sizes": list(serve.SIZES), "dtype": "u16",
-           "scenes_per_size": seeds_per_size, "chips_per_launch": chips_per_launch}
 
-    def play(rate, release, arena):
-        arr, picks = serve.make_trace(n_requests, rate, pool, seed=11)
-        scenes = [pool[sz][k][1] for sz, k in picks]
+    def oracle_check(key):
+        size, i = key
+        s_np = pool[size][i][1].cpu().numpy().view(np.uint16)
+        ol, oh = R.label(s_np, R.make_params(dtype=R.U16))
+        lab, hist = refs[key]
+        return bool((lab.cpu().numpy() == ol).all()
+                    and (hist.cpu().numpy().astype(np.uint32) == oh).all())
+
+    keys = sorted(refs)
+    with ThreadPoolExecutor(max_workers=min(16, len(os.sched_getaffinity(0)))) as ex:
+        oks = list(ex.map(oracle_check, keys))
+    out = {"requests": n_requests, "sizes": list(serve.SIZES), "dtype": "u16",
+           "scenes_per_size": seeds_per_size, "chips_per_launch": chips_per_launch,
+           "pool_vs_oracle": f"{sum(oks)}/{len(oks)} pool scenes' solo results equal the oracle"}
+
+    def play(rate, release, arena, src, n=n_requests):
+        arr, picks = serve.make_trace(n, rate, pool, seed=11)
+        scenes = [src[sz][k][1] for sz, k in picks]
         srv = serve.Server(p, arena_bytes=arena, max_chips_per_launch=chips_per_launch,
                            max_inflight=4, nstreams=2)
         comps, start = srv.run(scenes, arr, release=release)
@@ -155,38 +184,49 @@ def run_serving(n_requests, chips_per_launch, seeds_per_size=2):
         return srv, comps, start, arr, picks, st
 
     px = lambda picks: sum(sz * sz for sz, _ in picks)
-    # capacity: every request present at t = 0
-    srv, comps, start, arr, picks, st = play(0.0, True, 8 << 30)
-    span = max(c.t_done_ms for c in comps) - start
-    cap_gpx = px(picks) / (span * 1e-3) / 1e9
-    cap_req_per_ms = n_requests / span
-    out["capacity"] = {"gpx_s": cap_gpx, "requests_per_s": cap_req_per_ms * 1e3,
-                       "span_ms": span, "launches": st["launches"]}
-    srv.close()
-    for rho in (0.5, 0.8):
-        srv, comps, start, arr, picks, st = play(rho * cap_req_per_ms, True, 8 << 30)
-        lat = np.array([c.t_done_ms - (start + a) for c, a in zip(comps, arr)])
+
+    def trace(src, out, n_exact):
+        # capacity: every request present at t = 0
+        srv, comps, start, arr, picks, st = play(0.0, True, 8 << 30, src)
         span = max(c.t_done_ms for c in comps) - start
-        by_size = {}
-        for (sz, _), l in zip(picks, lat):
-            by_size.setdefault(sz, []).append(l)
-        out[f"rho_{rho}"] = {
-            "arrival_rate_per_s": rho * cap_req_per_ms * 1e3,
-            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "throughput_gpx_s": px(picks) / (span * 1e-3) / 1e9, "launches": st["launches"],
-            "arena_peak_bytes": st["arena_peak"],
-            "p99_ms_by_size": {str(k): float(np.percentile(v, 99)) for k, v in by_size.items()}}
+        cap_req_per_ms = n_requests / span
+        out["capacity"] = {"gpx_s": px(picks) / (span * 1e-3) / 1e9,
+                           "requests_per_s": cap_req_per_ms * 1e3, "span_ms": span,
+                           "launches": st["launches"], "arena_peak_bytes": st["arena_peak"]}
         srv.close()
-    # bit-exactness: the burst again with every output kept, each compared
-    srv, comps, start, arr, picks, st = play(0.0, False, 80 << 30)
-    torch.cuda.synchronize()
-    exact = 0
-    for c, (sz, k) in zip(comps, picks):
-        lab, hist = refs[(sz, k)]
-        exact += int(torch.equal(c.labels(), lab) and torch.equal(c.hist(), hist))
-        srv.release(c.tag)
-    out["bit_exact"] = f"{exact}/{n_requests} results equal their scene's solo run"
-    srv.close()
+        for rho in (0.5, 0.8):
+            srv, comps, start, arr, picks, st = play(rho * cap_req_per_ms, True, 8 << 30, src)
+            lat = np.array([c.t_done_ms - (start + a) for c, a in zip(comps, arr)])
+            span = max(c.t_done_ms for c in comps) - start
+            by_size = {}
+            for (sz, _), l in zip(picks, lat):
+                by_size.setdefault(sz, []).append(l)
+            out[f"rho_{rho}"] = {
+                "arrival_rate_per_s": rho * cap_req_per_ms * 1e3,
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "throughput_gpx_s": px(picks) / (span * 1e-3) / 1e9, "launches": st["launches"],
+                "arena_peak_bytes": st["arena_peak"],
+                "p99_ms_by_size": {str(k): float(np.percentile(v, 99)) for k, v in by_size.items()}}
+            srv.close()
+        # bit-exactness: a burst with every output kept, each compared
+        srv, comps, start, arr, picks, st = play(0.0, False, 80 << 30, src, n_exact)
+        torch.cuda.synchronize()
+        exact = 0
+        for c, (sz, k) in zip(comps, picks):
+            lab, hist = refs[(sz, k)]
+            exact += int(torch.equal(c.labels(), lab) and torch.equal(c.hist(), hist))
+            srv.release(c.tag)
+        out["bit_exact"] = f"{exact}/{n_exact} results equal their scene's solo run"
+        srv.close()
+
+    trace(pool, out, n_requests)
+    # the scenes in page-locked host memory: copied into the arena at admission
+    host = {sz: [(seed, t.cpu().pin_memory()) for seed, t in items] for sz, items in pool.items()}
+    out["host_scenes"] = {"note": "scenes in page-locked host memory, copied into the server's "
+                                  "arena at admission (input bytes counted there)"}
+    # (kept outputs and copied bands of 200 requests fit the exactness pass's arena)
+    trace(host, out["host_scenes"], min(n_requests, 200))
+    del host
     return out
 
 
@@ -386,14 +426,20 @@ def main():
     cpu = None
     if not args.skip_cpu:
         from oracle import sil_ref as R
-        t = time.perf_counter()
-        ol, oh = R.label(scene_np, R.make_params(dtype=R.U16), W=W)
-        dt = time.perf_counter() - t
-        ok = bool((labels.cpu().numpy() == ol).all()
-                  and (hist.cpu().numpy().astype(np.uint32) == oh).all())
+        times, ok = [], True
+        for _ in range(3):
+            t = time.perf_counter()
+            ol, oh = R.label(scene_np, R.make_params(dtype=R.U16), W=W)
+            times.append(time.perf_counter() - t)
+            ok = ok and bool((labels.cpu().numpy() == ol).all()
+                             and (hist.cpu().numpy().astype(np.uint32) == oh).all())
+        dt = statistics.median(times)
         cpu = {"value": npx / dt / 1e9, "unit": "Gpixel/s", "cores": 1, "kind": "oracle",
-               "sample": f"the full {H}x{W} uint16 tile, one single-threaded run "
-                         f"({dt:.1f} s); GPU output bit-identical: {ok}"}
+               "sample": f"the full {H}x{W} uint16 tile, single-threaded C oracle, median of "
+                         f"3 runs ({', '.join(f'{t:.2f}' for t in times)} s); GPU output "
+                         f"bit-identical: {ok}",
+               "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+               "cores_available": len(os.sched_getaffinity(0))}
 
     variants = None
     if not args.skip_variants:

@@ -5,12 +5,17 @@
  * map over images; here scenes of uneven size share GPU launches).
  *
  * Model:
- *   - A request names a device-resident scene (planar [nbands][H][pitch]).
+ *   - A request names a scene (planar [nbands][H][pitch]), resident on the
+ *     device, or in host memory with SIL_REQ_HOST_SCENE (page-locked memory,
+ *     e.g. hipHostMalloc, for the copy to overlap the GPU's work).
  *   - Its outputs (label plane [H][label_pitch], rows of W labels starting on
- *     128-byte boundaries, and per-chip counts [ncy][ncx][3]) are
- *     placed in an HBM arena of fixed size allocated at creation.  Requests
- *     are admitted first-in first-out when their outputs fit in the free
- *     arena space; the head of the queue is never overtaken.
+ *     128-byte boundaries, and per-chip counts [ncy][ncx][3]) and, for a host
+ *     scene, a copy of its three selected bands ([3][H][pitch]) are placed in
+ *     an HBM arena of fixed size allocated at creation.  Requests are admitted
+ *     first-in first-out when those bytes fit in the free arena space; the
+ *     head of the queue is never overtaken.  A host scene's bands are copied
+ *     into the arena at admission, on a copy stream, and its launches wait for
+ *     that copy.
  *   - Admitted requests' chips are labelled by sil_label_batch launches of at
  *     most `max_chips_per_launch` chips over at most SIL_BATCH_MAX_JOBS
  *     requests, oldest first.  A large scene spans several launches; requests
@@ -25,7 +30,9 @@
  * and independent of the mix (each chip's result depends only on its scene).
  *
  * Resource use: sil_server_create allocates the arena (hipMalloc), the
- * streams and an event pool; nothing is allocated per request.
+ * streams (compute and copy) and two event pools (launches; host-scene
+ * copies, one per admitted request whose launches are not all enqueued yet,
+ * at most 256); nothing is allocated per request.
  */
 #ifndef SIL_SERVER_H
 #define SIL_SERVER_H
@@ -48,13 +55,18 @@ typedef struct sil_server_config {
   int32_t max_queue;             /* submitted-but-unadmitted requests, >= 1 */
 } sil_server_config;
 
+#define SIL_REQ_HOST_SCENE 1u /* sil_request.flags: the scene is in host memory */
+
 typedef struct sil_request {
-  const void* scene;  /* device, [nbands][H][pitch] of params.dtype; must stay valid until done */
+  const void* scene;  /* [nbands][H][pitch] of params.dtype, on the device (or in host memory
+                         with SIL_REQ_HOST_SCENE); must stay valid until done */
   int32_t nbands;
   int32_t sel[3];
   int32_t H, W;
   int64_t pitch;
   uint64_t tag;       /* caller's id, unique among live requests */
+  uint32_t flags;     /* 0 or SIL_REQ_HOST_SCENE */
+  uint32_t pad;
 } sil_request;
 
 typedef struct sil_completion {
@@ -86,8 +98,9 @@ void sil_server_config_default(sil_server_config* c);
  * cannot be created. */
 int sil_server_create(const sil_params* p, const sil_server_config* cfg, sil_server** out);
 
-/* Queue a request (host only, O(1)).  SIL_EINVAL on bad arguments or a
- * request whose outputs can never fit the arena; SIL_EUNSUPPORTED when the
+/* Queue a request (host only, O(1)).  SIL_EINVAL on bad arguments (unknown
+ * flags included) or a request whose arena bytes (outputs, plus the copied
+ * bands of a host scene) can never fit the arena; SIL_EUNSUPPORTED when the
  * queue is full. */
 int sil_server_submit(sil_server* s, const sil_request* r);
 
@@ -132,7 +145,9 @@ double sil_server_clock_ms(const sil_server* s);
  * release != 0 each request's outputs are released as soon as it completes
  * (their pointers in out[] are then stale); otherwise the caller releases.
  * *start_ms (nullable) receives the trace start on the server clock.
- * Returns SIL_EUNSUPPORTED if the queue overflows. */
+ * Returns SIL_EUNSUPPORTED if the queue overflows, or if with release = 0
+ * the kept outputs fill the arena so that the next request can never be
+ * admitted (nothing left running). */
 int sil_server_run(sil_server* s, const sil_request* reqs, const double* arrival_ms, int32_t n,
                    int32_t release, sil_completion* out, double* start_ms);
 

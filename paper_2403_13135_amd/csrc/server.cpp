@@ -21,6 +21,7 @@
 namespace {
 
 constexpr uint64_t kAlign = 256;
+constexpr int kCopyEvents = 256;  // host-scene copies whose launches are still to enqueue
 
 uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // Label rows start on 128-byte boundaries, so the labeller writes whole
@@ -32,6 +33,8 @@ struct Req {
   int32_t nchips = 0, next_chip = 0;
   int32_t ncy = 0, ncx = 0;
   uint64_t off = 0, bytes = 0, hist_off = 0;
+  uint64_t in_off = 0, in_bytes = 0;  // a host scene's bands in the arena
+  hipEvent_t ready = nullptr;         // its copy, while launches remain to enqueue
   int32_t outstanding = 0, launches = 0;
   double t_submit = 0, t_admit = 0, t_done = 0;
   bool admitted = false, done = false;
@@ -95,7 +98,9 @@ struct sil_server {
   char* base = nullptr;
   Arena* arena = nullptr;
   std::vector<hipStream_t> streams;
+  hipStream_t copy_stream = nullptr;
   std::vector<hipEvent_t> event_pool;
+  std::vector<hipEvent_t> copy_events;
   hipEvent_t epoch = nullptr;
   Clock::time_point epoch_host;
   std::deque<uint64_t> queue;
@@ -114,6 +119,7 @@ struct sil_server {
     return align_up((uint64_t)H * (uint64_t)label_pitch_of(W)) +
            align_up((uint64_t)ncy * ncx * 3 * 4);
   }
+  uint64_t esize() const { return p.dtype == SIL_U16 ? 2 : 1; }
 
   // Retire launches whose events have completed.
   int retire() {
@@ -141,19 +147,37 @@ struct sil_server {
     return SIL_OK;
   }
 
-  void admit() {
+  // Admit from the head of the queue while its bytes fit; a host scene's
+  // three bands are copied into the arena on the copy stream (returns
+  // SIL_EDEVICE if a copy cannot be enqueued).
+  int admit() {
     while (!queue.empty()) {
       Req& rq = reqs.at(queue.front());
+      const bool host = rq.r.flags & SIL_REQ_HOST_SCENE;
+      if (host && copy_events.empty()) break;
       uint64_t off;
       if (!arena->alloc(rq.bytes, &off)) break;
       rq.off = off;
       rq.hist_off = off + align_up((uint64_t)rq.r.H * (uint64_t)label_pitch_of(rq.r.W));
+      if (host) {
+        rq.in_off = rq.hist_off + align_up((uint64_t)rq.ncy * rq.ncx * 3 * 4);
+        const uint64_t plane = (uint64_t)rq.r.H * (uint64_t)rq.r.pitch * esize();
+        for (int b = 0; b < 3; ++b)
+          if (hipMemcpyAsync(base + rq.in_off + b * plane,
+                             (const char*)rq.r.scene + (uint64_t)rq.r.sel[b] * plane, plane,
+                             hipMemcpyHostToDevice, copy_stream) != hipSuccess)
+            return SIL_EDEVICE;
+        rq.ready = copy_events.back();
+        copy_events.pop_back();
+        if (hipEventRecord(rq.ready, copy_stream) != hipSuccess) return SIL_EDEVICE;
+      }
       rq.admitted = true;
       rq.t_admit = now_ms();
       active.push_back(queue.front());
       queue.pop_front();
       ++st.admitted;
     }
+    return SIL_OK;
   }
 
   int launch_one() {
@@ -167,9 +191,15 @@ struct sil_server {
       int32_t cnt = std::min(rq.nchips - rq.next_chip, budget);
       if (cnt <= 0) continue;
       sil_job& j = jobs[n];
-      j.scene = rq.r.scene;
-      j.nbands = rq.r.nbands;
-      for (int b = 0; b < 3; ++b) j.sel[b] = rq.r.sel[b];
+      if (rq.r.flags & SIL_REQ_HOST_SCENE) {  // the arena copy of its three bands
+        j.scene = base + rq.in_off;
+        j.nbands = 3;
+        for (int b = 0; b < 3; ++b) j.sel[b] = b;
+      } else {
+        j.scene = rq.r.scene;
+        j.nbands = rq.r.nbands;
+        for (int b = 0; b < 3; ++b) j.sel[b] = rq.r.sel[b];
+      }
       j.H = rq.r.H;
       j.W = rq.r.W;
       j.pitch = rq.r.pitch;
@@ -185,6 +215,10 @@ struct sil_server {
     if (n == 0) return SIL_OK;
     hipStream_t sm = streams[next_stream];
     next_stream = (next_stream + 1) % (int)streams.size();
+    for (int i = 0; i < n; ++i) {
+      const Req& rq = reqs.at(tags[i]);
+      if (rq.ready && hipStreamWaitEvent(sm, rq.ready, 0) != hipSuccess) return SIL_EDEVICE;
+    }
     int rc = sil_label_batch(jobs, n, &p, (void*)sm);
     if (rc != SIL_OK) return rc;
     if (event_pool.empty()) return SIL_EDEVICE;
@@ -200,6 +234,12 @@ struct sil_server {
       ++rq.outstanding;
       ++rq.launches;
       L.tags.push_back(tags[i]);
+      if (rq.ready && rq.next_chip == rq.nchips) {
+        // every launch that reads the copy waits on it already; the event
+        // may be recorded again for another request
+        copy_events.push_back(rq.ready);
+        rq.ready = nullptr;
+      }
     }
     active.erase(std::remove_if(active.begin(), active.end(),
                                 [&](uint64_t t) {
@@ -256,6 +296,12 @@ int sil_server_create(const sil_params* p, const sil_server_config* cfg, sil_ser
     ok = hipEventCreate(&e) == hipSuccess;
     if (ok) s->event_pool.push_back(e);
   }
+  ok = ok && hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking) == hipSuccess;
+  for (int i = 0; i < kCopyEvents && ok; ++i) {
+    hipEvent_t e;
+    ok = hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+    if (ok) s->copy_events.push_back(e);
+  }
   ok = ok && hipEventCreate(&s->epoch) == hipSuccess;
   ok = ok && hipStreamSynchronize(s->streams[0]) == hipSuccess;
   ok = ok && hipEventRecord(s->epoch, s->streams[0]) == hipSuccess;
@@ -270,7 +316,7 @@ int sil_server_create(const sil_params* p, const sil_server_config* cfg, sil_ser
 }
 
 int sil_server_submit(sil_server* s, const sil_request* r) {
-  if (!s || !r || !r->scene) return SIL_EINVAL;
+  if (!s || !r || !r->scene || (r->flags & ~SIL_REQ_HOST_SCENE)) return SIL_EINVAL;
   int rc = sil_validate(r->nbands, r->sel, r->H, r->W, r->pitch, r->W, &s->p);
   if (rc != SIL_OK) return rc;
   if (s->reqs.count(r->tag)) return SIL_EINVAL;
@@ -282,6 +328,10 @@ int sil_server_submit(sil_server* s, const sil_request* r) {
   rq.ncx = (r->W + C - 1) / C;
   rq.nchips = rq.ncy * rq.ncx;
   rq.bytes = s->out_bytes(r->H, r->W, rq.ncy, rq.ncx);
+  if (r->flags & SIL_REQ_HOST_SCENE) {
+    rq.in_bytes = align_up(3 * (uint64_t)r->H * (uint64_t)r->pitch * s->esize());
+    rq.bytes += rq.in_bytes;
+  }
   if (rq.bytes > s->arena->size()) return SIL_EINVAL;
   rq.t_submit = s->now_ms();
   s->reqs.emplace(r->tag, rq);
@@ -295,12 +345,14 @@ int sil_server_pump(sil_server* s, int32_t* n_launched) {
   int32_t n = 0;
   int rc = s->retire();
   if (rc != SIL_OK) return rc;
-  s->admit();
+  rc = s->admit();
+  if (rc != SIL_OK) return rc;
   while ((int32_t)s->inflight.size() < s->cfg.max_inflight && !s->active.empty()) {
     rc = s->launch_one();
     if (rc != SIL_OK) return rc;
     ++n;
-    s->admit();
+    rc = s->admit();
+    if (rc != SIL_OK) return rc;
   }
   if (n_launched) *n_launched = n;
   return SIL_OK;
@@ -416,6 +468,11 @@ int sil_server_run(sil_server* s, const sil_request* reqs, const double* arrival
     }
     int rc = sil_server_pump(s, nullptr);
     if (rc != SIL_OK) return rc;
+    // kept outputs that fill the arena: nothing runs and the queue's head
+    // can only be admitted once the caller releases
+    if (!release && s->inflight.empty() && s->active.empty() && !s->queue.empty() &&
+        s->completed.empty())
+      return SIL_EUNSUPPORTED;
     int32_t got = 0;
     rc = sil_server_poll(s, buf.data(), (int32_t)buf.size(), &got);
     if (rc != SIL_OK) return rc;
@@ -438,6 +495,11 @@ int sil_server_destroy(sil_server* s) {
     if (hipEventSynchronize(L.ev) != hipSuccess) rc = SIL_EDEVICE;
   for (auto& L : s->inflight) (void)hipEventDestroy(L.ev);
   for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
+  if (s->copy_stream && hipStreamSynchronize(s->copy_stream) != hipSuccess) rc = SIL_EDEVICE;
+  for (auto& kv : s->reqs)
+    if (kv.second.ready) s->copy_events.push_back(kv.second.ready);
+  for (hipEvent_t e : s->copy_events) (void)hipEventDestroy(e);
+  if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
   if (s->epoch) (void)hipEventDestroy(s->epoch);
   for (hipStream_t sm : s->streams) (void)hipStreamDestroy(sm);
   if (s->base) (void)hipFree(s->base);

@@ -20,10 +20,14 @@ class _Config(ctypes.Structure):
                 ("max_queue", ctypes.c_int32)]
 
 
+HOST_SCENE = 1  # SIL_REQ_HOST_SCENE
+
+
 class _Request(ctypes.Structure):
     _fields_ = [("scene", ctypes.c_void_p), ("nbands", ctypes.c_int32),
                 ("sel", ctypes.c_int32 * 3), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
-                ("pitch", ctypes.c_int64), ("tag", ctypes.c_uint64)]
+                ("pitch", ctypes.c_int64), ("tag", ctypes.c_uint64), ("flags", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32)]
 
 
 class _Completion(ctypes.Structure):
@@ -124,9 +128,14 @@ def _completion(c: _Completion, chip: int) -> Completion:
 
 
 def _request(scene: torch.Tensor, tag: int, W: Optional[int] = None, sel=(0, 1, 2)) -> _Request:
+    """A request for a device scene, or for a host scene (copied into the
+    server's arena at admission; page-locked memory lets the copy overlap)."""
     nb, H, pitch = scene.shape
+    if not scene.is_contiguous():
+        raise ValueError("scene must be contiguous")
     r = _Request()
     r.scene = scene.data_ptr()
+    r.flags = 0 if scene.is_cuda else HOST_SCENE
     r.nbands = nb
     for i in range(3):
         r.sel[i] = int(sel[i])
@@ -165,7 +174,8 @@ class Server:
             pass
 
     def submit(self, scene: torch.Tensor, tag: int, W: Optional[int] = None, sel=(0, 1, 2)):
-        """Queue a request; ``scene`` must be resident (its writes completed)."""
+        """Queue a request; a GPU ``scene`` must be resident (its writes
+        completed); a host ``scene`` is copied into the arena at admission."""
         r = _request(scene, tag, W, sel)
         _check(_lib().sil_server_submit(self._h, ctypes.byref(r)))
         self._scenes[int(tag)] = scene  # keep it alive until released
@@ -232,8 +242,9 @@ SIZES = (512, 2048, 4096, 10980)
 
 
 def make_pool(seeds_per_size: int = 2, base_seed: int = 1000, device="cuda"):
-    """Device-resident uint16 scenes {size: [tensor]} from the seeded generator
-    (one haze and one shadow blob each; seeds base_seed + i)."""
+    """uint16 scenes {size: [(seed, tensor)]} from the seeded generator (one
+    haze and one shadow blob each; seeds base_seed + i), on the GPU, or in
+    page-locked host memory with device="pinned"."""
     import synth
     pool = {}
     k = 0
@@ -245,8 +256,9 @@ def make_pool(seeds_per_size: int = 2, base_seed: int = 1000, device="cuda"):
             spec = synth.SceneSpec(n, n, seed, "u16",
                                    synth.blobs_for_coverage(n, n, seed, 1, 1, 0.10),
                                    synth.blobs_for_coverage(n, n, seed, 2, 1, 0.05))
-            s = synth.generate(spec)
-            pool[n].append((seed, torch.from_numpy(s.view(np.int16)).to(device)))
+            t = torch.from_numpy(synth.generate(spec).view(np.int16))
+            t = t.pin_memory() if device == "pinned" else t.to(device)
+            pool[n].append((seed, t))
     torch.cuda.synchronize()
     return pool
 

@@ -1,5 +1,7 @@
-"""GPU tests of the continuous-batching server: every result is the same
-alone and in the mix (bit for bit), admission respects the HBM arena, and
+"""GPU tests of the continuous-batching server: every pool scene's solo
+result equals the oracle's, every result is the same alone and in the mix
+(bit for bit), requests whose scene is in host memory are copied into the
+arena at admission and counted there, admission respects the HBM arena, and
 argument errors are rejected."""
 import sys
 
@@ -37,9 +39,9 @@ def env():
         dev = torch.from_numpy(s_np.view(np.int16)).cuda()
         lab, hist = sil.label(dev, p)
         torch.cuda.synchronize()
-        if i < 3:  # the single-scene path itself against the oracle
-            ol, oh = R.label(s_np, R.make_params(dtype=R.U16))
-            assert (lab.cpu().numpy() == ol).all() and (hist.cpu().numpy() == oh).all()
+        # every scene's solo result against the oracle
+        ol, oh = R.label(s_np, R.make_params(dtype=R.U16))
+        assert (lab.cpu().numpy() == ol).all() and (hist.cpu().numpy() == oh).all(), (H, W)
         pool.append((dev, lab, hist))
     return serve, sil, p, pool, rng
 
@@ -170,3 +172,36 @@ def test_cancel_and_queue_timeout(env):
     st = srv.stats()
     assert st["queued"] == 0 and st["active"] == 0 and st["completed"] == 2
     srv.close()
+
+
+def test_host_scenes_copied_into_the_arena(env):
+    """Requests naming page-locked host scenes, mixed with device ones: the
+    bands are copied into the arena at admission, the results equal the
+    device runs, and the arena holds the copies (an arena that fits one
+    request's outputs but not its copied bands as well refuses it)."""
+    serve, sil, p, pool, rng = env
+    host = [d.cpu().pin_memory() for d, _, _ in pool]
+    picks = [int(rng.integers(0, len(pool))) for _ in range(40)]
+    scenes = [host[k] if i % 2 == 0 else pool[k][0] for i, k in enumerate(picks)]
+    srv = serve.Server(p, arena_bytes=1 << 30, max_chips_per_launch=100, max_inflight=3,
+                       nstreams=2)
+    _say("case 40 mixed host and device requests")
+    comps, _ = srv.run(scenes, [0.0] * len(scenes), release=False)
+    torch.cuda.synchronize()
+    for c, k in zip(comps, picks):
+        assert _check(c, pool[k]), f"request {c.tag} (scene {k}) differs"
+    st = srv.stats()
+    H, W = pool[3][0].shape[1:]  # the 2048 x 2048 scene
+    in_bytes = 3 * H * W * 2
+    assert st["arena_peak"] >= in_bytes
+    for c in comps:
+        srv.release(c.tag)
+    srv.close()
+    # arena bytes of one 2048^2 request: labels (rows of 2048) and counts
+    out_bytes = H * 2048 + ((8 * 8 * 3 * 4 + 255) // 256) * 256
+    small = serve.Server(p, arena_bytes=out_bytes + in_bytes // 2)
+    small.submit(pool[3][0], 1)  # device scene: fits
+    with pytest.raises(sil.SilError) as e:
+        small.submit(host[3], 2)  # host scene: its copy does not fit beside the outputs
+    assert e.value.code == sil.EINVAL
+    small.close()
