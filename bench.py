@@ -36,6 +36,11 @@ KERNEL_SRCS = [os.path.join(ROOT, "paper_2403_13135_amd", "csrc", n)
                for n in ("sil.hip", "chip_walk.h", "rescale.h")]
 
 
+def say(msg):
+    """Progress line on stderr (long sections report as they go)."""
+    print(f"# {msg}", file=sys.stderr, flush=True)
+
+
 def algorithmic_bytes(H, W, ny, nx, in_bytes_per_px=6):
     return H * W * in_bytes_per_px + H * W + ny * nx * 3 * 4
 
@@ -168,6 +173,7 @@ def run_serving(n_requests, chips_per_launch, seeds_per_size=4):
                     and (hist.cpu().numpy().astype(np.uint32) == oh).all())
 
     keys = sorted(refs)
+    say(f"serving: {len(keys)} pool scenes against the oracle")
     with ThreadPoolExecutor(max_workers=min(16, len(os.sched_getaffinity(0)))) as ex:
         oks = list(ex.map(oracle_check, keys))
     out = {"requests": n_requests, "sizes": list(serve.SIZES), "dtype": "u16",
@@ -186,6 +192,7 @@ def run_serving(n_requests, chips_per_launch, seeds_per_size=4):
     px = lambda picks: sum(sz * sz for sz, _ in picks)
 
     def trace(src, out, n_exact):
+        say(f"serving trace of {n_requests} requests ({'host' if src is not pool else 'device'} scenes)")
         # capacity: every request present at t = 0
         srv, comps, start, arr, picks, st = play(0.0, True, 8 << 30, src)
         span = max(c.t_done_ms for c in comps) - start
@@ -246,6 +253,7 @@ def run_learned(steps, n_fallback, n_capacity, fb_batch, seeds_per_size):
     test_sc = learn.make_scenes(3, 2048, seed0=4000)
     X, Y = learn.build_training_set(train_sc)
     model = unet.UNet(widths, seed=0)
+    say(f"U-Net training, {steps} steps")
     losses, sec = learn.train(model, X, Y, steps=steps, batch=32, lr=1e-3)
     flops_step = 3 * learn.unet_flops_per_image(widths) * 32
     ev = learn.evaluate(model, test_sc)
@@ -264,9 +272,11 @@ def run_learned(steps, n_fallback, n_capacity, fb_batch, seeds_per_size):
     def play(n, rate, seed):
         arr, picks = serve.make_trace(n, rate, pool, seed=seed)
         scenes = [pool[sz][k][1] for sz, k in picks]
-        recs = learn.serve_mix(model, scenes, arr, threshold=0.02, batch=fb_batch)
+        recs = learn.serve_mix(model, scenes, arr, threshold=0.02, batch=fb_batch,
+                               progress=lambda d, m: say(f"serving with fallback: {d}/{m} served"))
         return recs, picks
 
+    say("serving with fallback: capacity burst")
     res = {"requests": n_fallback, "sizes": list(serve.SIZES), "scenes_per_size": seeds_per_size,
            "threshold": 0.02, "chips_per_launch": fb_batch, "sequential": False}
     recs, picks = play(n_capacity, 0.0, 31)
@@ -277,6 +287,7 @@ def run_learned(steps, n_fallback, n_capacity, fb_batch, seeds_per_size):
                        "requests_per_s": cap * 1e3,
                        "unet_tflops": px * infer_flops_px / (span * 1e-3) / 1e12}
     for rho in (0.5, 0.8):
+        say(f"serving with fallback: {n_fallback} requests at {rho} of capacity")
         recs, picks = play(n_fallback, rho * cap, 33)
         lat = np.array([r.done_ms - r.arrival_ms for r in recs])
         span = max(r.done_ms for r in recs)
@@ -425,6 +436,7 @@ def main():
 
     cpu = None
     if not args.skip_cpu:
+        say("CPU baseline: the oracle on the tile, 3 runs")
         from oracle import sil_ref as R
         times, ok = [], True
         for _ in range(3):

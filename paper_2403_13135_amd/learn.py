@@ -234,7 +234,8 @@ class Served:
 
 @torch.no_grad()
 def serve_mix(model: unet.UNet, scenes: List[torch.Tensor], arrivals_ms, threshold: float = 0.02,
-              batch: int = 128, max_inflight: int = 2, keep: bool = False) -> List[Served]:
+              batch: int = 128, max_inflight: int = 2, keep: bool = False,
+              progress=None) -> List[Served]:
     """Continuous batching of the learned path: requests (scenes [3, H, W] on
     the GPU) arrive at `arrivals_ms` (ms from the start, non-decreasing).  An
     arrived request is labelled at once (sil.label) and its 256 x 256 chips
@@ -245,7 +246,9 @@ def serve_mix(model: unet.UNet, scenes: List[torch.Tensor], arrivals_ms, thresho
     map is served if they disagree on more than `threshold` of the pixels.
     Every kernel treats chips independently, so a request's result does not
     depend on what it shared launches with.  At most `max_inflight` launches
-    are queued ahead of the GPU.  Returns one record per request, in order."""
+    are queued ahead of the GPU.  `progress(done, n)` (optional) is called
+    after every 100 completed requests.  Returns one record per request, in
+    order."""
     dev = scenes[0].device
     p = sil.Params(dtype=sil.U16)
     recs = [Served(int(s.shape[1]), int(s.shape[2]), float(a)) for s, a in zip(scenes, arrivals_ms)]
@@ -321,6 +324,8 @@ def serve_mix(model: unet.UNet, scenes: List[torch.Tensor], arrivals_ms, thresho
                 if keep:
                     r.labels = lab if r.fallback else pred
                 done += 1
+                if progress is not None and done % 100 == 0:
+                    progress(done, n)
             else:
                 still.append((i, ev, host, lab, pred))
         finishing = still
