@@ -105,9 +105,12 @@ int sil_unet_bn_relu(const void* z, const float* stats, const float* gamma, cons
 int sil_unet_affine_relu(const void* z, const float* scale, const float* shift, void* out,
                          int64_t P, int32_t C, void* stream);
 
-/* Backward of sil_unet_bn_relu.  dout, z: [P][C] bf16; writes dz [P][C] bf16;
- * dgamma, dbeta fp32 [C] (accumulate).  red: caller-provided fp32 [2][C]
- * scratch, zeroed by the call. */
+/* Backward of sil_unet_bn_relu.  dout, z: [P][C] bf16; writes dz [P][C] bf16.
+ * With red (caller-provided fp32 [2][C] scratch, zeroed by the call) non-NULL,
+ * dgamma and dbeta (fp32 [C]) accumulate.  With red NULL the per-channel sums
+ * are formed in dbeta and dgamma themselves, which must then hold zeros on
+ * entry (a fresh gradient), and the call makes no separate fill or add
+ * launch. */
 int sil_unet_bn_relu_bwd(const void* dout, const void* z, const float* mr, const float* gamma,
                          const float* beta, void* dz, float* dgamma, float* dbeta, float* red,
                          int64_t P, int32_t C, void* stream);
@@ -116,23 +119,29 @@ int sil_unet_bn_relu_bwd(const void* dout, const void* z, const float* mr, const
  * the winning position (first maximum in row-major window order). */
 int sil_unet_maxpool(const void* x, void* y, uint8_t* idx, int32_t N, int32_t H, int32_t W,
                      int32_t C, void* stream);
-int sil_unet_maxpool_bwd(const void* dy, const uint8_t* idx, void* dx, int32_t N, int32_t H,
-                         int32_t W, int32_t C, void* stream);
+/* Backward: dx [N][H][W][C] = dy routed to each window's winner (zero
+ * elsewhere), plus dadd [N][H][W][C] when non-NULL (the gradient the same
+ * tensor receives from its other consumer, e.g. the skip connection; summed in
+ * fp32, rounded once to bf16).  dadd may be dx itself. */
+int sil_unet_maxpool_bwd(const void* dy, const uint8_t* idx, const void* dadd, void* dx,
+                         int32_t N, int32_t H, int32_t W, int32_t C, void* stream);
 
 /* 1x1 head: logits[p][k] = b[k] + sum_c x[p][c] w[k][c], k < 3 (fp32 out). */
 int sil_unet_head(const void* x, const float* w, const float* b, float* logits, int64_t P,
                   int32_t C, void* stream);
 
-/* Softmax cross-entropy over 3 classes: loss[0] += sum_p -log softmax(l_p)[y_p]
- * (accumulate); dlogits[p] = (softmax(l_p) - onehot(y_p)) * scale.
+/* Softmax cross-entropy over 3 classes: loss[0] += scale * sum_p -log
+ * softmax(l_p)[y_p] (accumulate; scale = 1/P gives the mean);
+ * dlogits[p] = (softmax(l_p) - onehot(y_p)) * scale.
  * labels: u8 [P] in 0..2; dlogits nullable. */
 int sil_unet_softmax_xent(const float* logits, const uint8_t* labels, float* loss,
                           float* dlogits, float scale, int64_t P, void* stream);
 
-/* Head backward: dx [P][C] bf16 = dlogits w; dw fp32 [3][C] += sum_p dlogits x;
- * db fp32 [3] += sum_p dlogits. */
-int sil_unet_head_bwd(const void* x, const float* w, const float* dlogits, void* dx, float* dw,
-                      float* db, int64_t P, int32_t C, void* stream);
+/* Head backward: with d = dlogits * dscale[0] (dscale: nullable device fp32
+ * scalar, the gradient arriving at the loss; NULL means 1), dx [P][C] bf16 =
+ * d w; dw fp32 [3][C] += sum_p d x; db fp32 [3] += sum_p d. */
+int sil_unet_head_bwd(const void* x, const float* w, const float* dlogits, const float* dscale,
+                      void* dx, float* dw, float* db, int64_t P, int32_t C, void* stream);
 
 /* Class map: labels[p] = argmax_k logits[p][k] (first maximum). */
 int sil_unet_argmax(const float* logits, uint8_t* labels, int64_t P, void* stream);
@@ -157,6 +166,62 @@ int sil_unet_chips_input(const uint16_t* scene, int32_t H, int32_t W, int64_t pi
  * bf16 copy when wbf is non-NULL.  m, v: fp32 moments. */
 int sil_unet_adam(float* w, const float* g, float* m, float* v, void* wbf, int64_t n, float lr,
                   float beta1, float beta2, float eps, int32_t step, void* stream);
+
+/* One tensor of a multi-tensor Adam step: w (fp32 master weights), g
+ * (gradient), m, v (fp32 moments), n elements each. */
+typedef struct sil_unet_adam_tensor {
+  float* w;
+  const float* g;
+  float* m;
+  float* v;
+  int64_t n;
+} sil_unet_adam_tensor;
+
+/* sil_unet_adam's update (without the bf16 copy) on `count` tensors in one
+ * launch per 64 tensors. */
+int sil_unet_adam_multi(const sil_unet_adam_tensor* t, int32_t count, float lr, float beta1,
+                        float beta2, float eps, int32_t step, void* stream);
+
+#define SIL_UNET_W_CONV3 1 /* w [cout][3][3][cin]; wt [cin][3][3][cout] flipped (sil_unet_flip3x3) */
+#define SIL_UNET_W_UP2 2   /* w [2][2][cout][cin]; wt [cin][2][2][cout] (sil_unet_up_t) */
+
+/* One weight tensor to prepare for a forward and backward pass: wb = bf16(w)
+ * in w's layout, and (wt non-NULL) the bf16 transposed form the input
+ * gradient uses. */
+typedef struct sil_unet_weight_prep {
+  const float* w;
+  void* wb;
+  void* wt;
+  int32_t kind;
+  int32_t cout, cin;
+} sil_unet_weight_prep;
+
+/* bf16 weight copies and transposed forms for `count` tensors in one launch
+ * per 64 tensors (round to nearest even, as sil_unet_to_bf16). */
+int sil_unet_prep_weights(const sil_unet_weight_prep* t, int32_t count, void* stream);
+
+/* One batch-norm layer's per-channel vectors (fp32 [C]; C <= 256). */
+typedef struct sil_unet_bn_layer {
+  int32_t C;
+  const float* mr;      /* [2][C] batch (mean, rstd), from sil_unet_bn_relu */
+  float* running_mean;
+  float* running_var;
+  const float* gamma;
+  const float* beta;
+  float* scale;         /* inference: gamma / sqrt(running_var + eps) */
+  float* shift;         /* inference: beta - running_mean * scale */
+} sil_unet_bn_layer;
+
+/* Running statistics as an exponential moving average of the batch
+ * statistics: running_mean = (1 - momentum) running_mean + momentum mean,
+ * running_var likewise with the biased batch variance 1/rstd^2 - eps, for
+ * `count` layers (mr, running_mean, running_var used). */
+int sil_unet_bn_ema(const sil_unet_bn_layer* l, int32_t count, float momentum, float eps,
+                    void* stream);
+
+/* Inference scale and shift from the running statistics for `count` layers
+ * (running_mean, running_var, gamma, beta, scale, shift used). */
+int sil_unet_bn_fold(const sil_unet_bn_layer* l, int32_t count, float eps, void* stream);
 
 /* fp32 -> bf16 (round to nearest even). */
 int sil_unet_to_bf16(const float* x, void* y, int64_t n, void* stream);

@@ -41,7 +41,6 @@ constexpr int kGT = 256;      // GEMM threads (4 waves)
 constexpr int kBK = 32;       // reduction step (one MFMA K)
 constexpr int kLdsRow = 40;   // u16 per LDS row: 32 + 8 padding (80 bytes)
 
-__device__ __forceinline__ float bf2f(u16 v) { return __uint_as_float((uint32_t)v << 16); }
 // fp32 -> bf16, round to nearest even (gfx950's v_cvt_pk_bf16_f32)
 __device__ __forceinline__ u16 f2bf(float f) { return __builtin_bit_cast(u16, (__bf16)f); }
 
@@ -103,8 +102,15 @@ template <int AM, int EM, int WM, int WN, int NJ>
 __global__ __launch_bounds__(kGT) void k_gemm_nt(GemmNT g) {
   constexpr int BM = 64 * WM, BN = 16 * NJ * WN;
   static_assert(WM * WN == 4, "four waves");
-  __shared__ u16 As[2][BM][kLdsRow];
-  __shared__ u16 Bs[2][BN][kLdsRow];
+  // the operand buffers, and after a tile's last K step its bf16 output tile
+  constexpr int AS_ELEMS = 2 * BM * kLdsRow, BS_ELEMS = 2 * BN * kLdsRow;
+  constexpr int SO_ROW = BN + 8;  // u16 per staged output row (padded)
+  constexpr int SM_ELEMS =
+      AS_ELEMS + BS_ELEMS > BM * SO_ROW ? AS_ELEMS + BS_ELEMS : BM * SO_ROW;
+  __shared__ __attribute__((aligned(16))) u16 smem[SM_ELEMS];
+  u16(*As)[BM][kLdsRow] = reinterpret_cast<u16(*)[BM][kLdsRow]>(smem);
+  u16(*Bs)[BN][kLdsRow] = reinterpret_cast<u16(*)[BN][kLdsRow]>(smem + AS_ELEMS);
+  u16* const So = smem;
   __shared__ float red[WM][2][BN];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
@@ -213,73 +219,65 @@ __global__ __launch_bounds__(kGT) void k_gemm_nt(GemmNT g) {
     }
 
     // epilogue: acc[i][j][t] is C[row][col], row = wave rows + 16i + 4*(lane/16) + t,
-    // col = wave cols + 16j + lane%16
-    if constexpr (EM == E_UPSCATTER) {
-      // column -> (quadrant q, channel co) once per column; row -> (img, h, w)
-      // once per 4 consecutive rows, then advanced without divisions
-      int32_t qoff[NJ], cov[NJ];
-      float bias[NJ];
-      bool cok[NJ];
+    // col = wave cols + 16j + lane%16.  The bf16 tile goes through LDS (the
+    // operand buffers are free: the last K step ended in a barrier) so that
+    // global stores are 16 bytes of 8 consecutive columns.
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        const int32_t col = n0 + wn * 16 * NJ + 16 * j + (lane & 15);
-        cok[j] = col < g.N;
-        const int32_t q = cok[j] ? col / g.up_cout : 0;
-        cov[j] = cok[j] ? col - q * g.up_cout : 0;
-        qoff[j] = (q >> 1) * (2 * g.W) + (q & 1);
-        bias[j] = cok[j] ? g.bias[cov[j]] : 0.f;
+    for (int j = 0; j < NJ; ++j) {
+      const int cl = wn * 16 * NJ + 16 * j + (lane & 15);
+      const int32_t col = n0 + cl;
+      const bool cok = col < g.N;
+      float add = 0.f, mul = 1.f;
+      if constexpr (EM == E_UPSCATTER) add = cok ? g.bias[col % g.up_cout] : 0.f;
+      if constexpr (EM == E_AFFRELU) {
+        mul = cok ? g.scale[col] : 0.f;
+        add = cok ? g.shift[col] : 0.f;
       }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int32_t row0 = m0 + wm * 64 + 16 * i + 4 * (lane >> 4);
-        const int32_t r0 = min(row0, g.M - 1);
-        int32_t img = r0 / (g.H * g.W);
-        const int32_t rem = r0 - img * g.H * g.W;
-        int32_t h = rem / g.W, w = rem - h * g.W;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          if (row0 + t < g.M) {
-            const int64_t base = ((int64_t)img * 2 * g.H + 2 * h) * (2 * g.W) + 2 * w;
-#pragma unroll
-            for (int j = 0; j < NJ; ++j)
-              if (cok[j])
-                g.y0[(base + qoff[j]) * g.up_cout + cov[j]] = f2bf(acc[i][j][t] + bias[j]);
-          }
-          if (++w == g.W) {
-            w = 0;
-            if (++h == g.H) {
-              h = 0;
-              ++img;
-            }
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < NJ && EM != E_UPSCATTER; ++j) {
-      const int32_t col = n0 + wn * 16 * NJ + 16 * j + (lane & 15);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          const int32_t row = m0 + wm * 64 + 16 * i + 4 * (lane >> 4) + t;
+          const int rl = wm * 64 + 16 * i + 4 * (lane >> 4) + t;
           const float v = acc[i][j][t];
-          if (row >= g.M || col >= g.N) continue;
+          float o = v;
           if constexpr (EM == E_STORE) {
-            g.y0[(int64_t)row * g.N + col] = f2bf(v);
-            s1[j] += v;
-            s2[j] += v * v;
+            if (m0 + rl < g.M && cok) {
+              s1[j] += v;
+              s2[j] += v * v;
+            }
           } else if constexpr (EM == E_AFFRELU) {
-            const float t = v * g.scale[col] + g.shift[col];
-            g.y0[(int64_t)row * g.N + col] = f2bf(t > 0.f ? t : 0.f);
-          } else if constexpr (EM == E_SPLIT) {
-            if (col < g.split)
-              g.y0[(int64_t)row * g.split + col] = f2bf(v);
-            else
-              g.y1[(int64_t)row * (g.N - g.split) + (col - g.split)] = f2bf(v);
+            const float z = v * mul + add;
+            o = z > 0.f ? z : 0.f;
+          } else if constexpr (EM == E_UPSCATTER) {
+            o = v + add;
           }
+          So[rl * SO_ROW + cl] = f2bf(o);
         }
     }
+    __syncthreads();
+    for (int q = tid; q < BM * (BN / 8); q += kGT) {
+      const int rl = q / (BN / 8), ch = q - rl * (BN / 8);
+      const int32_t row = m0 + rl, col = n0 + 8 * ch;
+      if (row >= g.M || col >= g.N) continue;
+      const uint4 val = *(const uint4*)&So[rl * SO_ROW + 8 * ch];
+      if constexpr (EM == E_UPSCATTER) {
+        // column -> (quadrant qd, channel co); 8 columns stay in one quadrant
+        const int32_t qd = col / g.up_cout, co = col - qd * g.up_cout;
+        const int32_t img = row / (g.H * g.W), rem = row - img * g.H * g.W;
+        const int32_t h = rem / g.W, w = rem - h * g.W;
+        const int64_t pix =
+            ((int64_t)img * 2 * g.H + 2 * h + (qd >> 1)) * (2 * g.W) + 2 * w + (qd & 1);
+        *(uint4*)(g.y0 + pix * g.up_cout + co) = val;
+      } else if constexpr (EM == E_SPLIT) {
+        if (col < g.split)
+          *(uint4*)(g.y0 + (int64_t)row * g.split + col) = val;
+        else
+          *(uint4*)(g.y1 + (int64_t)row * (g.N - g.split) + (col - g.split)) = val;
+      } else {
+        *(uint4*)(g.y0 + (int64_t)row * g.N + col) = val;
+      }
+    }
+    __syncthreads();  // the staged tile overlaps the next tile's operand buffers
   }
 
   if constexpr (EM == E_STORE) {
@@ -538,6 +536,8 @@ struct GemmTN {
   int32_t c0, c1;
   int64_t p_per_split;
   float* c;
+  float* rowsum;        // nullable: += sum_p A[p][m] at index m % rowsum_mod
+  int32_t rowsum_mod;
 };
 
 // ---- 3x3 weight gradient with the input tile staged in LDS ------------------------
@@ -784,29 +784,36 @@ __device__ __forceinline__ uint4 tn_load(const TnSrc& s, const Pix& q, int32_t H
 }
 
 // C[m][n] += sum_p A[p][m] B[p][n] over this block's pixel range.  A^T and B^T
-// are staged in one LDS array S (rows 0..BM-1 = m, BM.. = n; 32 pixels per row,
-// double-buffered).  Staging slot c (0 .. 2*(BM+BN)) covers LDS rows
-// 8*(c/16) .. +7 at the pixel pair 2*(c%16), 2*(c%16)+1: two 16-byte loads, then
-// eight 4-byte LDS writes of (pixel 2j, pixel 2j+1) pairs, which land in
-// consecutive banks across the 16 lanes of a row group.
+// are staged in one LDS array S (rows 0..BM-1 = m, BM.. = n; kTnK pixels per
+// row, double-buffered), so one stage feeds two MFMA K steps.  Staging slot c
+// (0 .. 4*(BM+BN)) covers LDS rows 8*(c/32) .. +7 at the pixel pair 2*(c%32),
+// 2*(c%32)+1: two 16-byte loads, then eight 4-byte LDS writes of (pixel 2j,
+// pixel 2j+1) pairs, consecutive across the 32 lanes of a row group.  With
+// g.rowsum set, the blocks of the first N tile also add up A's rows over their
+// pixels (the bias gradient of the up-convolution: rowsum[m % cout] for
+// UPGATHER), one atomic per row per block.
+constexpr int kTnK = 64;                  // pixels per stage
+constexpr int kTnRow = kTnK + 8;          // u16 per staged row (padded)
+
 template <int AM, int BMD, int MI, int NJ>
 __global__ __launch_bounds__(kGT) void k_gemm_tn(GemmTN g) {
   constexpr int BM = 32 * MI, BN = 32 * NJ;
-  constexpr int SLOTS = 2 * (BM + BN);
+  constexpr int SLOTS = 4 * (BM + BN);
   constexpr int SR = (SLOTS + kGT - 1) / kGT;
-  __shared__ u16 S[2][BM + BN][kLdsRow];
+  __shared__ u16 S[2][BM + BN][kTnRow];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int32_t m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
   const int64_t p_begin = (int64_t)blockIdx.z * g.p_per_split;
   const int64_t p_end = min(g.P, p_begin + g.p_per_split);
-  const int pj = tid & 15;
+  const int pj = tid & 31;
+  const bool sum_rows = g.rowsum != nullptr && blockIdx.y == 0 && wn == 0;
 
   TnSrc src[SR];
 #pragma unroll
   for (int r = 0; r < SR; ++r) {
     const int c = tid + kGT * r;
-    const int row = 8 * (c >> 4);
+    const int row = 8 * (c >> 5);
     if (c >= SLOTS) {
       src[r] = TnSrc{};
     } else if (row < BM) {
@@ -816,24 +823,28 @@ __global__ __launch_bounds__(kGT) void k_gemm_tn(GemmTN g) {
     }
   }
 
-  Pix q = pix_of(p_begin + 2 * pj, g.H, g.W);
-  uint4 rv[SR][2];
-  auto gload = [&](int64_t p0) {
-    Pix q1 = q;
+  // Two stages of loads are in flight: while stage k is multiplied out of
+  // LDS, stage k+1 waits in registers for its LDS store and stage k+2 is
+  // being fetched.  qn is the pixel of the next stage to fetch.
+  Pix qn = pix_of(p_begin + 2 * pj, g.H, g.W);
+  uint4 ra[SR][2], rb[SR][2];
+  auto gload = [&](uint4 (&rv)[SR][2], int64_t p0) {
+    Pix q1 = qn;
     pix_adv(q1, 1, g.H, g.W);
     const int64_t pa = p0 + 2 * pj;
 #pragma unroll
     for (int r = 0; r < SR; ++r) {
-      rv[r][0] = tn_load(src[r], q, g.H, g.W, pa < p_end);
+      rv[r][0] = tn_load(src[r], qn, g.H, g.W, pa < p_end);
       rv[r][1] = tn_load(src[r], q1, g.H, g.W, pa + 1 < p_end);
     }
+    pix_adv(qn, kTnK, g.H, g.W);
   };
-  auto lstore = [&](int buf) {
+  auto lstore = [&](int buf, const uint4 (&rv)[SR][2]) {
 #pragma unroll
     for (int r = 0; r < SR; ++r) {
       const int c = tid + kGT * r;
       if (c >= SLOTS) continue;
-      const int row = 8 * (c >> 4);
+      const int row = 8 * (c >> 5);
       const uint32_t w0[4] = {rv[r][0].x, rv[r][0].y, rv[r][0].z, rv[r][0].w};
       const uint32_t w1[4] = {rv[r][1].x, rv[r][1].y, rv[r][1].z, rv[r][1].w};
 #pragma unroll
@@ -849,35 +860,57 @@ __global__ __launch_bounds__(kGT) void k_gemm_tn(GemmTN g) {
   for (int i = 0; i < MI; ++i)
 #pragma unroll
     for (int j = 0; j < NJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float rsum[MI];
+#pragma unroll
+  for (int i = 0; i < MI; ++i) rsum[i] = 0.f;
 
-  gload(p_begin);
-  lstore(0);
-  __syncthreads();
-  int buf = 0;
-  for (int64_t p0 = p_begin; p0 < p_end; p0 += kBK) {
-    const bool more = p0 + kBK < p_end;
-    if (more) {
-      pix_adv(q, kBK, g.H, g.W);
-      gload(p0 + kBK);
-    }
-    bf16x8 a[MI], b[NJ];
+  auto compute = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < MI; ++i)
-      a[i] = __builtin_bit_cast(
-          bf16x8, *(const uint4*)&S[buf][wm * (BM / 2) + 16 * i + (lane & 15)][8 * (lane >> 4)]);
+    for (int kk = 0; kk < kTnK / kBK; ++kk) {
+      bf16x8 a[MI], b[NJ];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j)
-      b[j] = __builtin_bit_cast(
-          bf16x8,
-          *(const uint4*)&S[buf][BM + wn * (BN / 2) + 16 * j + (lane & 15)][8 * (lane >> 4)]);
-#pragma unroll
-    for (int i = 0; i < MI; ++i)
+      for (int i = 0; i < MI; ++i)
+        a[i] = __builtin_bit_cast(
+            bf16x8, *(const uint4*)&S[buf][wm * (BM / 2) + 16 * i + (lane & 15)]
+                                     [kBK * kk + 8 * (lane >> 4)]);
 #pragma unroll
       for (int j = 0; j < NJ; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-    if (more) lstore(buf ^ 1);
+        b[j] = __builtin_bit_cast(
+            bf16x8, *(const uint4*)&S[buf][BM + wn * (BN / 2) + 16 * j + (lane & 15)]
+                                     [kBK * kk + 8 * (lane >> 4)]);
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+      if (sum_rows) {
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) rsum[i] += (float)a[i][e];
+      }
+    }
+  };
+
+  gload(ra, p_begin);
+  if (p_begin + kTnK < p_end) gload(rb, p_begin + kTnK);
+  lstore(0, ra);
+  __syncthreads();
+  // stages alternate between the register sets ra and rb: the loop body is
+  // written out for two stages
+  for (int64_t p0 = p_begin; p0 < p_end; p0 += 2 * kTnK) {
+    // stage p0 is in LDS buffer 0, stage p0 + K in rb
+    if (p0 + 2 * kTnK < p_end) gload(ra, p0 + 2 * kTnK);
+    compute(0);
+    if (p0 + kTnK >= p_end) break;
+    lstore(1, rb);
     __syncthreads();
-    buf ^= 1;
+    // stage p0 + K is in LDS buffer 1, stage p0 + 2K in ra
+    if (p0 + 3 * kTnK < p_end) gload(rb, p0 + 3 * kTnK);
+    compute(1);
+    if (p0 + 2 * kTnK >= p_end) break;
+    lstore(0, ra);
+    __syncthreads();
   }
 #pragma unroll
   for (int i = 0; i < MI; ++i)
@@ -889,6 +922,17 @@ __global__ __launch_bounds__(kGT) void k_gemm_tn(GemmTN g) {
         const int32_t col = n0 + wn * (BN / 2) + 16 * j + (lane & 15);
         if (row < g.M && col < g.N) atomicAdd(&g.c[(int64_t)row * g.N + col], acc[i][j][t]);
       }
+  if (sum_rows) {
+    // lanes l, l ^ 16, l ^ 32, l ^ 48 summed the same row over different pixels
+#pragma unroll
+    for (int i = 0; i < MI; ++i) {
+      float v = rsum[i];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      const int32_t row = m0 + wm * (BM / 2) + 16 * i + lane;
+      if (lane < 16 && row < g.M) atomicAdd(&g.rowsum[row % g.rowsum_mod], v);
+    }
+  }
 }
 
 // ---- elementwise and reduction kernels ----------------------------------------
@@ -946,33 +990,39 @@ __device__ __forceinline__ uint4 pack8(const float f[8]) {
   return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-// per-channel (mean, rstd) from sums, in double
-__global__ void k_bn_stats(const float* stats, int32_t C, int64_t count, float eps, float* mr) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= C) return;
-  const double mean = (double)stats[c] / (double)count;
-  double var = (double)stats[C + c] / (double)count - mean * mean;
-  if (var < 0) var = 0;
-  mr[c] = (float)mean;
-  mr[C + c] = (float)(1.0 / sqrt(var + (double)eps));
-}
-
-// BN + ReLU, 8 channels per thread (C % 8 == 0)
+// BN + ReLU, 8 channels per thread (C % 8 == 0).  Each block first turns the
+// per-channel sums into (mean, rstd) for all C channels in LDS, in double;
+// block 0 also writes them to mr for the backward pass.
 // The element-wise BN kernels walk [P][C] in 16-byte groups of 8 channels
 // with a grid stride of gridDim.x * 256 groups.  C divides 256, so the stride
 // (a multiple of 2048 elements) is a multiple of C and each thread keeps the
 // same 8 channels: their parameters are loaded once, and two groups are in
 // flight per iteration.
-__global__ void k_bn_relu(const u16* z, const float* mr, const float* gamma, const float* beta,
-                          u16* out, int64_t n, int32_t C) {
-  const int64_t n8 = n / 8, i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_bn_relu(const u16* z, const float* stats, int64_t count, float eps,
+                          const float* gamma, const float* beta, u16* out, float* mr, int64_t n,
+                          int32_t C) {
+  __shared__ float smean[256], srstd[256];
+  const int t = threadIdx.x;
+  if (t < C) {
+    const double mean = (double)stats[t] / (double)count;
+    double var = (double)stats[C + t] / (double)count - mean * mean;
+    if (var < 0) var = 0;
+    smean[t] = (float)mean;
+    srstd[t] = (float)(1.0 / sqrt(var + (double)eps));
+    if (blockIdx.x == 0) {
+      mr[t] = smean[t];
+      mr[C + t] = srstd[t];
+    }
+  }
+  __syncthreads();
+  const int64_t n8 = n / 8, i0 = (int64_t)blockIdx.x * blockDim.x + t;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int32_t c0 = (int32_t)((i0 * 8) % C);
   float mean[8], rstd[8], gm[8], bt[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    mean[j] = mr[c0 + j];
-    rstd[j] = mr[C + c0 + j];
+    mean[j] = smean[c0 + j];
+    rstd[j] = srstd[c0 + j];
     gm[j] = gamma[c0 + j];
     bt[j] = beta[c0 + j];
   }
@@ -997,11 +1047,13 @@ __global__ void k_bn_relu(const u16* z, const float* mr, const float* gamma, con
 
 // Per-channel sums over [P][C] for the BN backward: thread t owns channel
 // group g = t % (C/8) (8 channels, 16-byte loads) and rows t / (C/8) + k *
-// (256 / (C/8)) of its block's row range; C <= 256, 256 % (C/8) == 0.
-// Partial sums meet in LDS, then one atomic per channel per block.
+// (256 / (C/8)) of its block's row range, four rows (eight loads) in flight;
+// C <= 256, 256 % (C/8) == 0.  Partial sums meet in LDS, then one atomic per
+// channel per block into r1 (sum of the masked gradient) and r2 (its sum
+// against the normalised input).
 __global__ void k_bn_bwd_reduce(const u16* dout, const u16* z, const float* mr,
-                                const float* gamma, const float* beta, float* red, int64_t P,
-                                int32_t C) {
+                                const float* gamma, const float* beta, float* r1, float* r2,
+                                int64_t P, int32_t C) {
   __shared__ float s1[256 * 8], s2[256 * 8];
   const int t = threadIdx.x, G = C / 8;
   const int g = t % G, r0 = t / G, rstep = 256 / G;
@@ -1016,14 +1068,10 @@ __global__ void k_bn_bwd_reduce(const u16* dout, const u16* z, const float* mr,
     gm[j] = gamma[c0 + j];
     bt[j] = beta[c0 + j];
   }
-  const int64_t rows_per_block = (P + gridDim.x - 1) / gridDim.x;
-  const int64_t rb = (int64_t)blockIdx.x * rows_per_block;
-  const int64_t re = min(P, rb + rows_per_block);
-  for (int64_t p = rb + r0; p < re; p += rstep) {
-    const int64_t i = (p * C + c0) / 8;
+  auto add = [&](const uint4 zin, const uint4 din) {
     float fz[8], fd[8];
-    unpack8(((const uint4*)z)[i], fz);
-    unpack8(((const uint4*)dout)[i], fd);
+    unpack8(zin, fz);
+    unpack8(din, fd);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const float zh = (fz[j] - mean[j]) * rstd[j];
@@ -1031,7 +1079,24 @@ __global__ void k_bn_bwd_reduce(const u16* dout, const u16* z, const float* mr,
       a1[j] += d;
       a2[j] += d * zh;
     }
+  };
+  const int64_t rows_per_block = (P + gridDim.x - 1) / gridDim.x;
+  const int64_t rb = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t re = min(P, rb + rows_per_block);
+  const uint4* zv = (const uint4*)z;
+  const uint4* dv = (const uint4*)dout;
+  int64_t p = rb + r0;
+  for (; p + 3 * rstep < re; p += 4 * rstep) {
+    uint4 zz[4], dd[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      zz[u] = zv[(p + u * rstep) * G + g];
+      dd[u] = dv[(p + u * rstep) * G + g];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) add(zz[u], dd[u]);
   }
+  for (; p < re; p += rstep) add(zv[p * G + g], dv[p * G + g]);
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     s1[j * 256 + t] = a1[j];
@@ -1045,14 +1110,14 @@ __global__ void k_bn_bwd_reduce(const u16* dout, const u16* z, const float* mr,
       b1 += s1[j * 256 + k];
       b2 += s2[j * 256 + k];
     }
-    atomicAdd(&red[t], b1);
-    atomicAdd(&red[C + t], b2);
+    atomicAdd(&r1[t], b1);
+    atomicAdd(&r2[t], b2);
   }
 }
 
 __global__ void k_bn_bwd_apply(const u16* dout, const u16* z, const float* mr, const float* gamma,
-                               const float* beta, const float* red, u16* dz, int64_t n, int32_t C,
-                               float inv_count) {
+                               const float* beta, const float* red1, const float* red2, u16* dz,
+                               int64_t n, int32_t C, float inv_count) {
   const int64_t n8 = n / 8, i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int32_t c0 = (int32_t)((i0 * 8) % C);  // fixed per thread (see k_bn_relu)
@@ -1063,8 +1128,8 @@ __global__ void k_bn_bwd_apply(const u16* dout, const u16* z, const float* mr, c
     rstd[j] = mr[C + c0 + j];
     gm[j] = gamma[c0 + j];
     bt[j] = beta[c0 + j];
-    r1[j] = red[c0 + j];
-    r2[j] = red[C + c0 + j];
+    r1[j] = red1[c0 + j];
+    r2[j] = red2[c0 + j];
   }
   auto one = [&](const uint4 zin, const uint4 din) {
     float fz[8], fd[8], o[8];
@@ -1134,9 +1199,13 @@ __global__ void k_scatter_argmax(const float* logits, const int32_t* origins, in
   }
 }
 
-__global__ void k_add_vec(float* dst, const float* src, int32_t n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] += src[i];
+// dst0[i] += src[i], dst1[i] += src[n + i] for i < n (n <= 256)
+__global__ void k_add_pair(float* dst0, float* dst1, const float* src, int32_t n) {
+  const int i = threadIdx.x;
+  if (i < n) {
+    dst0[i] += src[i];
+    dst1[i] += src[n + i];
+  }
 }
 
 // 2x2 max pool, 8 channels per thread
@@ -1174,8 +1243,10 @@ __global__ void k_maxpool(const u16* x, u16* y, uint8_t* idx, int32_t N, int32_t
   }
 }
 
-__global__ void k_maxpool_bwd(const u16* dy, const uint8_t* idx, u16* dx, int32_t N, int32_t H,
-                              int32_t W, int32_t C) {
+// dx = the pooled gradient routed to each window's winner, plus dadd (the
+// gradient of the same tensor from its other consumer, nullable; may be dx)
+__global__ void k_maxpool_bwd(const u16* dy, const uint8_t* idx, const u16* dadd, u16* dx,
+                              int32_t N, int32_t H, int32_t W, int32_t C) {
   const int32_t G = C / 8;
   const int64_t n = (int64_t)N * H * W * G;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -1198,7 +1269,16 @@ __global__ void k_maxpool_bwd(const u16* dy, const uint8_t* idx, u16* dx, int32_
       const uint32_t lo = (word >> (16 * (q & 1))) & 0xffu, hi = (word >> (16 * (q & 1) + 8)) & 0xffu;
       out[q] = (lo == k ? (dw[q] & 0xffffu) : 0u) | (hi == k ? (dw[q] & 0xffff0000u) : 0u);
     }
-    ((uint4*)dx)[i] = make_uint4(out[0], out[1], out[2], out[3]);
+    uint4 res = make_uint4(out[0], out[1], out[2], out[3]);
+    if (dadd) {
+      float f[8], e[8];
+      unpack8(res, f);
+      unpack8(((const uint4*)dadd)[i], e);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) f[j] += e[j];
+      res = pack8(f);
+    }
+    ((uint4*)dx)[i] = res;
   }
 }
 
@@ -1235,7 +1315,7 @@ __global__ void k_softmax_xent(const float* logits, const uint8_t* labels, float
     const float s = ea + eb + ec;
     const int y = labels[p];
     const float ly = y == 0 ? a : (y == 1 ? b : c);
-    acc += logf(s) + mx - ly;
+    acc += (logf(s) + mx - ly) * scale;
     if (dlogits) {
       const float inv = 1.f / s;
       dlogits[3 * p] = (ea * inv - (y == 0)) * scale;
@@ -1252,67 +1332,72 @@ __global__ void k_softmax_xent(const float* logits, const uint8_t* labels, float
   if (threadIdx.x == 0) atomicAdd(loss, part[0]);
 }
 
-// head backward, input gradient: one thread per (pixel, channel)
-__global__ void k_head_dx(const float* w, const float* dl, u16* dx, int64_t P, int32_t C) {
-  const int32_t G = C / 8;
-  const int64_t n = P * G;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t p = i / G;
-    const int32_t c0 = 8 * (int32_t)(i - p * G);
-    const float d0 = dl[3 * p], d1 = dl[3 * p + 1], d2 = dl[3 * p + 2];
-    float o[8];
+// Head backward in one pass over x: thread t owns channel group g = t % (C/8)
+// (8 channels) and rows t / (C/8) + k * (256 / (C/8)) of its block's row range
+// (256 % (C/8) == 0).  Per row it writes dx = dlogits w for its 8 channels and
+// adds dlogits (x) x into 24 partial sums (and dlogits into 3 for the bias);
+// partial sums meet in LDS, then one atomic per output per block.
+__global__ void k_head_bwd(const u16* x, const float* w, const float* dl, const float* dscale,
+                           u16* dx, float* dw, float* db, int64_t P, int32_t C) {
+  __shared__ float s[27][256];
+  const int t = threadIdx.x, G = C / 8;
+  const int g = t % G, r0 = t / G, rstep = 256 / G;
+  const int c0 = 8 * g;
+  float wk[3][8], a[3][8], bsum[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-    for (int j = 0; j < 8; ++j) o[j] = d0 * w[c0 + j] + d1 * w[C + c0 + j] + d2 * w[2 * C + c0 + j];
-    ((uint4*)dx)[i] = pack8(o);
-  }
-}
-
-// head backward, weight and bias gradients: thread t sums channel t % C over
-// rows t / C + k * (256 / C) of its block's row range (256 % C == 0)
-__global__ void k_head_dw(const u16* x, const float* dl, float* dw, float* db, int64_t P,
-                          int32_t C) {
-  __shared__ float s[3][256];
-  __shared__ float sb[3][256];
-  const int t = threadIdx.x, c = t % C, r0 = t / C, rstep = 256 / C;
-  float a0 = 0.f, a1 = 0.f, a2 = 0.f, b0 = 0.f, b1 = 0.f, b2 = 0.f;
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      wk[k][j] = w[k * C + c0 + j];
+      a[k][j] = 0.f;
+    }
+  const float sc = dscale ? *dscale : 1.f;
+  auto one = [&](int64_t p, const uint4 xin) {
+    const float d0 = dl[3 * p] * sc, d1 = dl[3 * p + 1] * sc, d2 = dl[3 * p + 2] * sc;
+    float f[8], o[8];
+    unpack8(xin, f);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      o[j] = d0 * wk[0][j] + d1 * wk[1][j] + d2 * wk[2][j];
+      a[0][j] += d0 * f[j];
+      a[1][j] += d1 * f[j];
+      a[2][j] += d2 * f[j];
+    }
+    bsum[0] += d0;
+    bsum[1] += d1;
+    bsum[2] += d2;
+    ((uint4*)dx)[p * G + g] = pack8(o);
+  };
   const int64_t rows_per_block = (P + gridDim.x - 1) / gridDim.x;
   const int64_t rb = (int64_t)blockIdx.x * rows_per_block;
   const int64_t re = min(P, rb + rows_per_block);
-  for (int64_t p = rb + r0; p < re; p += rstep) {
-    const float v = bf2f(x[p * C + c]);
-    const float d0 = dl[3 * p], d1 = dl[3 * p + 1], d2 = dl[3 * p + 2];
-    a0 += d0 * v;
-    a1 += d1 * v;
-    a2 += d2 * v;
-    if (c == 0) {
-      b0 += d0;
-      b1 += d1;
-      b2 += d2;
-    }
+  const uint4* xv = (const uint4*)x;
+  int64_t p = rb + r0;
+  for (; p + rstep < re; p += 2 * rstep) {
+    const uint4 xa = xv[p * G + g], xb = xv[(p + rstep) * G + g];
+    one(p, xa);
+    one(p + rstep, xb);
   }
-  s[0][t] = a0;
-  s[1][t] = a1;
-  s[2][t] = a2;
-  sb[0][t] = b0;
-  sb[1][t] = b1;
-  sb[2][t] = b2;
+  if (p < re) one(p, xv[p * G + g]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s[k * 8 + j][t] = a[k][j];
+    s[24 + k][t] = g == 0 ? bsum[k] : 0.f;
+  }
   __syncthreads();
-  if (t < C) {
-    float e0 = 0.f, e1 = 0.f, e2 = 0.f;
-    for (int k = t; k < 256; k += C) {
-      e0 += s[0][k];
-      e1 += s[1][k];
-      e2 += s[2][k];
+  for (int u = t; u < 3 * C + 3; u += 256) {
+    if (u < 3 * C) {
+      const int k = u / C, c = u - k * C, gg = c / 8, j = c % 8;
+      float e = 0.f;
+      for (int q = gg; q < 256; q += G) e += s[k * 8 + j][q];
+      atomicAdd(&dw[k * C + c], e);
+    } else {
+      const int k = u - 3 * C;
+      float e = 0.f;
+      for (int q = 0; q < 256; q += G) e += s[24 + k][q];
+      atomicAdd(&db[k], e);
     }
-    atomicAdd(&dw[c], e0);
-    atomicAdd(&dw[C + c], e1);
-    atomicAdd(&dw[2 * C + c], e2);
-  }
-  if (t < 3) {
-    float e = 0.f;
-    for (int k = 0; k < 256; k += C) e += sb[t][k];
-    atomicAdd(&db[t], e);
   }
 }
 
@@ -1328,33 +1413,6 @@ __global__ void k_argmax(const float* logits, uint8_t* labels, int64_t P) {
     }
     if (c > m) k = 2;
     labels[p] = k;
-  }
-}
-
-// column sums of dy [P][C] into db (accumulate); 8 channels per thread,
-// blocks of 256, 256 % (C/8) == 0
-__global__ void k_colsum(const u16* dy, float* db, int64_t P, int32_t C) {
-  __shared__ float s[256 * 8];
-  const int t = threadIdx.x, G = C / 8;
-  const int g = t % G, r0 = t / G, rstep = 256 / G;
-  float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  const int64_t rows_per_block = (P + gridDim.x - 1) / gridDim.x;
-  const int64_t rb = (int64_t)blockIdx.x * rows_per_block;
-  const int64_t re = min(P, rb + rows_per_block);
-  for (int64_t p = rb + r0; p < re; p += rstep) {
-    float f[8];
-    unpack8(*(const uint4*)(dy + p * C + 8 * g), f);
-#pragma unroll
-    for (int j = 0; j < 8; ++j) a[j] += f[j];
-  }
-#pragma unroll
-  for (int j = 0; j < 8; ++j) s[j * 256 + t] = a[j];
-  __syncthreads();
-  if (t < C) {
-    const int gg = t / 8, j = t % 8;
-    float b = 0.f;
-    for (int k = gg; k < 256; k += G) b += s[j * 256 + k];
-    atomicAdd(&db[t], b);
   }
 }
 
@@ -1391,6 +1449,111 @@ __global__ void k_adam(float* w, const float* g, float* m, float* v, u16* wbf, i
     const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
     w[i] = wi;
     if (wbf) wbf[i] = f2bf(wi);
+  }
+}
+
+// ---- multi-tensor kernels --------------------------------------------------------
+//
+// One launch covers a list of tensors passed by value in the kernel
+// arguments (at most kMulti per launch).  Tensor i owns blocks blk0[i] ..
+// blk0[i+1]-1, each block kPerBlock consecutive elements.
+constexpr int kMulti = 64;
+constexpr int kPerBlock = 4 * 256;
+
+struct AdamList {
+  sil_unet_adam_tensor t[kMulti];
+  int32_t blk0[kMulti + 1];
+  int32_t count;
+};
+struct PrepList {
+  sil_unet_weight_prep t[kMulti];
+  int32_t blk0[kMulti + 1];
+  int32_t count;
+};
+constexpr int kMultiBn = 32;
+struct BnList {
+  sil_unet_bn_layer t[kMultiBn];
+};
+
+__device__ __forceinline__ int list_find(const int32_t* blk0, int count, int b) {
+  int i = 0;
+  while (i + 1 < count && blk0[i + 1] <= b) ++i;
+  return i;
+}
+
+// Adam with the arithmetic of k_adam, on every tensor of the list
+__global__ void k_adam_multi(AdamList L, float lr, float b1, float b2, float eps, float c1,
+                             float c2) {
+  const int i = list_find(L.blk0, L.count, blockIdx.x);
+  float* w = L.t[i].w;
+  const float* g = L.t[i].g;
+  float* m = L.t[i].m;
+  float* v = L.t[i].v;
+  const int64_t n = L.t[i].n;
+  const int64_t base = (int64_t)(blockIdx.x - L.blk0[i]) * kPerBlock + threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < kPerBlock / 256; ++u) {
+    const int64_t e = base + 256 * u;
+    if (e >= n) break;
+    const float gi = g[e];
+    const float mi = b1 * m[e] + (1.f - b1) * gi;
+    const float vi = b2 * v[e] + (1.f - b2) * gi * gi;
+    m[e] = mi;
+    v[e] = vi;
+    w[e] = w[e] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+}
+
+// bf16 copies of the weights, and their transposed forms for the input
+// gradients.  Element e is the e-th element of both outputs: wb[e] =
+// bf16(w[e]), and wt[e] gathers its source from w, so that every store is
+// coalesced and the scattered reads hit the cache.
+__global__ void k_prep_weights(PrepList L) {
+  const int i = list_find(L.blk0, L.count, blockIdx.x);
+  const float* w = L.t[i].w;
+  u16* wb = (u16*)L.t[i].wb;
+  u16* wt = (u16*)L.t[i].wt;
+  const int32_t kind = L.t[i].kind, cout = L.t[i].cout, cin = L.t[i].cin;
+  const int64_t n = (int64_t)(kind == SIL_UNET_W_CONV3 ? 9 : 4) * cout * cin;
+  const int64_t base = (int64_t)(blockIdx.x - L.blk0[i]) * kPerBlock + threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < kPerBlock / 256; ++u) {
+    const int64_t e = base + 256 * u;
+    if (e >= n) break;
+    wb[e] = f2bf(w[e]);
+    if (!wt) continue;
+    // 32-bit index arithmetic: tensors hold at most 2^30 elements
+    const int32_t e32 = (int32_t)e, rest = e32 / cout, co = e32 - rest * cout;
+    if (kind == SIL_UNET_W_CONV3) {
+      // wt[ci][r][s][co] = w[co][2-r][2-s][ci]
+      const int32_t ci = rest / 9, rs = rest - ci * 9;
+      wt[e] = f2bf(w[(co * 9 + (8 - rs)) * cin + ci]);
+    } else {
+      // wt[ci][q][co] = w[q][co][ci]
+      const int32_t ci = rest >> 2, q = rest & 3;
+      wt[e] = f2bf(w[(q * cout + co) * cin + ci]);
+    }
+  }
+}
+
+// exponential moving average of the batch statistics, one block per layer
+__global__ void k_bn_ema(BnList L, float mom, float eps) {
+  const sil_unet_bn_layer& T = L.t[blockIdx.x];
+  for (int c = threadIdx.x; c < T.C; c += blockDim.x) {
+    const float mean = T.mr[c], rstd = T.mr[T.C + c];
+    const float var = 1.f / (rstd * rstd) - eps;
+    T.running_mean[c] = T.running_mean[c] * (1.f - mom) + mom * mean;
+    T.running_var[c] = T.running_var[c] * (1.f - mom) + mom * var;
+  }
+}
+
+// inference scale and shift from the running statistics, one block per layer
+__global__ void k_bn_fold(BnList L, float eps) {
+  const sil_unet_bn_layer& T = L.t[blockIdx.x];
+  for (int c = threadIdx.x; c < T.C; c += blockDim.x) {
+    const float sc = T.gamma[c] / sqrtf(T.running_var[c] + eps);
+    T.scale[c] = sc;
+    T.shift[c] = T.beta[c] - T.running_mean[c] * sc;
   }
 }
 
@@ -1471,6 +1634,14 @@ int launch_conv_lds(const GemmNT& g, hipStream_t st) {
   return done();
 }
 
+#ifndef SIL_TN_BLOCKS
+#define SIL_TN_BLOCKS 1024
+#endif
+#ifndef SIL_TN_ATOMICS
+#define SIL_TN_ATOMICS (1 << 22)
+#endif
+constexpr int64_t kTnBlocks = SIL_TN_BLOCKS, kTnAtomics = SIL_TN_ATOMICS;
+
 // Weight-gradient tile (32*MI x 32*NJ): the widest N tile that divides N
 // (192, 128, 96, 64), else 96 for N <= 96, else 32.
 template <int AM, int BMD>
@@ -1487,12 +1658,15 @@ int launch_tn(GemmTN g, hipStream_t st) {
   else nj = 1;
   const int bm = 32 * mi, bn = 32 * nj;
   const int64_t tiles = (int64_t)((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn);
-  // split the pixel reduction so that roughly 2048 workgroups run
-  int64_t splits = (2048 + tiles - 1) / tiles;
+  // Split the pixel reduction across workgroups: about kTnBlocks of them, but
+  // every split adds one fp32 atomic per output element, and atomics on the
+  // same addresses serialise, so the splits times M*N stay near kTnAtomics.
+  int64_t splits = (kTnBlocks + tiles - 1) / tiles;
+  splits = std::min(splits, std::max<int64_t>(1, kTnAtomics / ((int64_t)g.M * g.N)));
   const int64_t max_splits = (g.P + 255) / 256;
   if (splits > max_splits) splits = max_splits;
   if (splits < 1) splits = 1;
-  g.p_per_split = ((g.P + splits - 1) / splits + kBK - 1) / kBK * kBK;
+  g.p_per_split = ((g.P + splits - 1) / splits + kTnK - 1) / kTnK * kTnK;
   splits = (g.P + g.p_per_split - 1) / g.p_per_split;
   dim3 grid((g.M + bm - 1) / bm, (g.N + bn - 1) / bn, (unsigned)splits);
 #define SIL_TN(MIv, NJv)                                                            \
@@ -1673,13 +1847,9 @@ int sil_unet_upconv_wgrad(const void* x, const void* dy, float* dw, float* db, i
   g.a = (const u16*)dy;
   g.b0 = (const u16*)x;
   g.c = dw;
-  int rc = launch_tn<T_UPGATHER, T_PLAIN>(g, (hipStream_t)stream);
-  if (rc != SIL_OK) return rc;
-  if (cout > 256 || 256 % cout) return SIL_EINVAL;
-  const int64_t Pout = (int64_t)N * 4 * H * W;
-  hipLaunchKernelGGL(k_colsum, dim3(std::min(grid_for(Pout * (cout / 8) / 2048 + 1, 1), kRedBlocks)), dim3(256), 0,
-                     (hipStream_t)stream, (const u16*)dy, db, Pout, cout);
-  return done();
+  g.rowsum = db;  // the bias gradient: the column sums of dy, formed in the same pass
+  g.rowsum_mod = cout;
+  return launch_tn<T_UPGATHER, T_PLAIN>(g, (hipStream_t)stream);
 }
 
 int sil_unet_up_t(const void* w, void* wt, int32_t cin, int32_t cout, void* stream) {
@@ -1698,12 +1868,11 @@ int sil_unet_bn_relu(const void* z, const float* stats, const float* gamma, cons
       C > 256 || 256 % C)
     return SIL_EINVAL;
   (void)hipGetLastError();
-  hipStream_t st = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_bn_stats, dim3((C + 255) / 256), dim3(256), 0, st, stats, C, count, eps,
-                     mr);
   const int64_t n = P * C;
-  hipLaunchKernelGGL(k_bn_relu, dim3(grid_for(n / 8)), dim3(256), 0, st, (const u16*)z, mr, gamma,
-                     beta, (u16*)out, n, C);
+  // every block derives (mean, rstd) itself: a capped grid keeps that cheap
+  hipLaunchKernelGGL(k_bn_relu, dim3(std::min(grid_for(n / 8), 2048)), dim3(256), 0,
+                     (hipStream_t)stream, (const u16*)z, stats, count, eps, gamma, beta,
+                     (u16*)out, mr, n, C);
   return done();
 }
 
@@ -1733,19 +1902,23 @@ int sil_unet_scatter_argmax(const float* logits, const int32_t* origins, int32_t
 int sil_unet_bn_relu_bwd(const void* dout, const void* z, const float* mr, const float* gamma,
                          const float* beta, void* dz, float* dgamma, float* dbeta, float* red,
                          int64_t P, int32_t C, void* stream) {
-  if (!dout || !z || !mr || !gamma || !beta || !dz || !dgamma || !dbeta || !red || P <= 0 ||
-      C < 8 || C > 256 || 256 % C)
+  if (!dout || !z || !mr || !gamma || !beta || !dz || !dgamma || !dbeta || P <= 0 || C < 8 ||
+      C > 256 || 256 % C)
     return SIL_EINVAL;
   (void)hipGetLastError();
   hipStream_t st = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_fill, dim3(1), dim3(256), 0, st, red, (int64_t)2 * C, 0.f);
+  // with scratch the sums are formed there and added to dbeta/dgamma at the
+  // end; without it they are formed in dbeta/dgamma themselves (zero on entry)
+  float* r1 = red ? red : dbeta;
+  float* r2 = red ? red + C : dgamma;
+  if (red) hipLaunchKernelGGL(k_fill, dim3(1), dim3(256), 0, st, red, (int64_t)2 * C, 0.f);
   hipLaunchKernelGGL(k_bn_bwd_reduce, dim3(std::min(grid_for(P * (C / 8) / 2048 + 1, 1), kRedBlocks)), dim3(256), 0, st,
-                     (const u16*)dout, (const u16*)z, mr, gamma, beta, red, P, C);
+                     (const u16*)dout, (const u16*)z, mr, gamma, beta, r1, r2, P, C);
   const int64_t n = P * C;
   hipLaunchKernelGGL(k_bn_bwd_apply, dim3(grid_for(n / 8)), dim3(256), 0, st, (const u16*)dout,
-                     (const u16*)z, mr, gamma, beta, red, (u16*)dz, n, C, 1.f / (float)P);
-  hipLaunchKernelGGL(k_add_vec, dim3((C + 255) / 256), dim3(256), 0, st, dbeta, red, C);
-  hipLaunchKernelGGL(k_add_vec, dim3((C + 255) / 256), dim3(256), 0, st, dgamma, red + C, C);
+                     (const u16*)z, mr, gamma, beta, r1, r2, (u16*)dz, n, C, 1.f / (float)P);
+  if (red)
+    hipLaunchKernelGGL(k_add_pair, dim3(1), dim3(256), 0, st, dbeta, dgamma, red, C);
   return done();
 }
 
@@ -1760,14 +1933,14 @@ int sil_unet_maxpool(const void* x, void* y, uint8_t* idx, int32_t N, int32_t H,
   return done();
 }
 
-int sil_unet_maxpool_bwd(const void* dy, const uint8_t* idx, void* dx, int32_t N, int32_t H,
-                         int32_t W, int32_t C, void* stream) {
+int sil_unet_maxpool_bwd(const void* dy, const uint8_t* idx, const void* dadd, void* dx,
+                         int32_t N, int32_t H, int32_t W, int32_t C, void* stream) {
   if (!dy || !idx || !dx || !ok_dims(N, H, W) || H % 2 || W % 2 || C <= 0 || C % 8)
     return SIL_EINVAL;
   (void)hipGetLastError();
   const int64_t n = (int64_t)N * H * W * (C / 8);
   hipLaunchKernelGGL(k_maxpool_bwd, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream,
-                     (const u16*)dy, idx, (u16*)dx, N, H, W, C);
+                     (const u16*)dy, idx, (const u16*)dadd, (u16*)dx, N, H, W, C);
   return done();
 }
 
@@ -1789,16 +1962,14 @@ int sil_unet_softmax_xent(const float* logits, const uint8_t* labels, float* los
   return done();
 }
 
-int sil_unet_head_bwd(const void* x, const float* w, const float* dlogits, void* dx, float* dw,
-                      float* db, int64_t P, int32_t C, void* stream) {
+int sil_unet_head_bwd(const void* x, const float* w, const float* dlogits, const float* dscale,
+                      void* dx, float* dw, float* db, int64_t P, int32_t C, void* stream) {
   if (!x || !w || !dlogits || !dx || !dw || !db || P <= 0 || C < 8 || C > 256 || 256 % C)
     return SIL_EINVAL;
   (void)hipGetLastError();
-  hipStream_t st = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_head_dx, dim3(grid_for(P * C / 8)), dim3(256), 0, st, w, dlogits, (u16*)dx,
-                     P, C);
-  hipLaunchKernelGGL(k_head_dw, dim3(std::min(grid_for(P / 64 + 1, 1), kRedBlocks)), dim3(256), 0, st, (const u16*)x,
-                     dlogits, dw, db, P, C);
+  hipLaunchKernelGGL(k_head_bwd, dim3(std::min(grid_for(P * (C / 8) / 2048 + 1, 1), kRedBlocks)),
+                     dim3(256), 0, (hipStream_t)stream, (const u16*)x, w, dlogits, dscale,
+                     (u16*)dx, dw, db, P, C);
   return done();
 }
 
@@ -1830,6 +2001,89 @@ int sil_unet_adam(float* w, const float* g, float* m, float* v, void* wbf, int64
   const float c1 = 1.f - powf(beta1, (float)step), c2 = 1.f - powf(beta2, (float)step);
   hipLaunchKernelGGL(k_adam, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, w, g, m, v,
                      (u16*)wbf, n, lr, beta1, beta2, eps, c1, c2);
+  return done();
+}
+
+int sil_unet_adam_multi(const sil_unet_adam_tensor* t, int32_t count, float lr, float beta1,
+                        float beta2, float eps, int32_t step, void* stream) {
+  if (!t || count <= 0 || step < 1) return SIL_EINVAL;
+  int64_t blocks = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    if (!t[i].w || !t[i].g || !t[i].m || !t[i].v || t[i].n <= 0) return SIL_EINVAL;
+    blocks += (t[i].n + kPerBlock - 1) / kPerBlock;
+  }
+  if (blocks > INT32_MAX) return SIL_EINVAL;
+  (void)hipGetLastError();
+  const float c1 = 1.f - powf(beta1, (float)step), c2 = 1.f - powf(beta2, (float)step);
+  for (int32_t s0 = 0; s0 < count; s0 += kMulti) {
+    AdamList L{};
+    L.count = std::min(kMulti, count - s0);
+    int32_t b = 0;
+    for (int32_t i = 0; i < L.count; ++i) {
+      L.t[i] = t[s0 + i];
+      L.blk0[i] = b;
+      b += (int32_t)((t[s0 + i].n + kPerBlock - 1) / kPerBlock);
+    }
+    L.blk0[L.count] = b;
+    hipLaunchKernelGGL(k_adam_multi, dim3(b), dim3(256), 0, (hipStream_t)stream, L, lr, beta1,
+                       beta2, eps, c1, c2);
+  }
+  return done();
+}
+
+int sil_unet_prep_weights(const sil_unet_weight_prep* t, int32_t count, void* stream) {
+  if (!t || count <= 0) return SIL_EINVAL;
+  for (int32_t i = 0; i < count; ++i) {
+    if (!t[i].w || !t[i].wb || t[i].cout <= 0 || t[i].cin <= 0) return SIL_EINVAL;
+    if (t[i].kind != SIL_UNET_W_CONV3 && t[i].kind != SIL_UNET_W_UP2) return SIL_EINVAL;
+    if ((int64_t)9 * t[i].cout * t[i].cin > ((int64_t)1 << 30)) return SIL_EINVAL;
+  }
+  (void)hipGetLastError();
+  for (int32_t s0 = 0; s0 < count; s0 += kMulti) {
+    PrepList L{};
+    L.count = std::min(kMulti, count - s0);
+    int32_t b = 0;
+    for (int32_t i = 0; i < L.count; ++i) {
+      const sil_unet_weight_prep& T = t[s0 + i];
+      L.t[i] = T;
+      L.blk0[i] = b;
+      const int64_t n = (int64_t)(T.kind == SIL_UNET_W_CONV3 ? 9 : 4) * T.cout * T.cin;
+      b += (int32_t)((n + kPerBlock - 1) / kPerBlock);
+    }
+    L.blk0[L.count] = b;
+    hipLaunchKernelGGL(k_prep_weights, dim3(b), dim3(256), 0, (hipStream_t)stream, L);
+  }
+  return done();
+}
+
+int sil_unet_bn_ema(const sil_unet_bn_layer* l, int32_t count, float momentum, float eps,
+                    void* stream) {
+  if (!l || count <= 0) return SIL_EINVAL;
+  for (int32_t i = 0; i < count; ++i)
+    if (!l[i].mr || !l[i].running_mean || !l[i].running_var || l[i].C <= 0) return SIL_EINVAL;
+  (void)hipGetLastError();
+  for (int32_t s0 = 0; s0 < count; s0 += kMultiBn) {
+    BnList L{};
+    const int32_t k = std::min(kMultiBn, count - s0);
+    for (int32_t i = 0; i < k; ++i) L.t[i] = l[s0 + i];
+    hipLaunchKernelGGL(k_bn_ema, dim3(k), dim3(256), 0, (hipStream_t)stream, L, momentum, eps);
+  }
+  return done();
+}
+
+int sil_unet_bn_fold(const sil_unet_bn_layer* l, int32_t count, float eps, void* stream) {
+  if (!l || count <= 0) return SIL_EINVAL;
+  for (int32_t i = 0; i < count; ++i)
+    if (!l[i].running_mean || !l[i].running_var || !l[i].gamma || !l[i].beta || !l[i].scale ||
+        !l[i].shift || l[i].C <= 0)
+      return SIL_EINVAL;
+  (void)hipGetLastError();
+  for (int32_t s0 = 0; s0 < count; s0 += kMultiBn) {
+    BnList L{};
+    const int32_t k = std::min(kMultiBn, count - s0);
+    for (int32_t i = 0; i < k; ++i) L.t[i] = l[s0 + i];
+    hipLaunchKernelGGL(k_bn_fold, dim3(k), dim3(256), 0, (hipStream_t)stream, L, eps);
+  }
   return done();
 }
 

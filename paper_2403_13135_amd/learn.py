@@ -106,7 +106,7 @@ def train(model: unet.UNet, X: torch.Tensor, Y: torch.Tensor, steps: int, batch:
         t0 = time.perf_counter()
         opt.zero_grad()
         loss, _ = model.forward(xb, yb)
-        loss.backward()
+        model.backward(loss)
         opt.step()
         model.update_running_stats()
         torch.cuda.synchronize()

@@ -48,13 +48,17 @@ def _lib():
             "sil_unet_affine_relu": [vp, vp, vp, vp, i64, i32, vp],
             "sil_unet_scatter_argmax": [vp, vp, i32, i32, vp, i32, i32, i64, vp],
             "sil_unet_maxpool": [vp, vp, vp, i32, i32, i32, i32, vp],
-            "sil_unet_maxpool_bwd": [vp, vp, vp, i32, i32, i32, i32, vp],
+            "sil_unet_maxpool_bwd": [vp, vp, vp, vp, i32, i32, i32, i32, vp],
             "sil_unet_head": [vp, vp, vp, vp, i64, i32, vp],
             "sil_unet_softmax_xent": [vp, vp, vp, vp, f32, i64, vp],
-            "sil_unet_head_bwd": [vp, vp, vp, vp, vp, vp, i64, i32, vp],
+            "sil_unet_head_bwd": [vp, vp, vp, vp, vp, vp, vp, i64, i32, vp],
             "sil_unet_argmax": [vp, vp, i64, vp],
             "sil_unet_chips_input": [vp, i32, i32, i64, vp, i32, i32, f32, vp, vp],
             "sil_unet_adam": [vp, vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp],
+            "sil_unet_adam_multi": [vp, i32, f32, f32, f32, f32, i32, vp],
+            "sil_unet_prep_weights": [vp, i32, vp],
+            "sil_unet_bn_ema": [vp, i32, f32, f32, vp],
+            "sil_unet_bn_fold": [vp, i32, f32, vp],
             "sil_unet_to_bf16": [vp, vp, i64, vp],
             "sil_unet_fill_f32": [vp, i64, f32, vp],
         }
@@ -84,6 +88,32 @@ def _bf16(w: torch.Tensor) -> torch.Tensor:
     out = torch.empty(w.shape, dtype=torch.bfloat16, device=w.device)
     _call("sil_unet_to_bf16", _p(w.contiguous()), _p(out), w.numel(), _s())
     return out
+
+
+class _AdamTensor(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_void_p), ("g", ctypes.c_void_p), ("m", ctypes.c_void_p),
+                ("v", ctypes.c_void_p), ("n", ctypes.c_int64)]
+
+
+W_CONV3, W_UP2 = 1, 2
+
+
+class _WeightPrep(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_void_p), ("wb", ctypes.c_void_p), ("wt", ctypes.c_void_p),
+                ("kind", ctypes.c_int32), ("cout", ctypes.c_int32), ("cin", ctypes.c_int32)]
+
+
+class _BnLayer(ctypes.Structure):
+    _fields_ = [("C", ctypes.c_int32), ("mr", ctypes.c_void_p), ("running_mean", ctypes.c_void_p),
+                ("running_var", ctypes.c_void_p), ("gamma", ctypes.c_void_p),
+                ("beta", ctypes.c_void_p), ("scale", ctypes.c_void_p), ("shift", ctypes.c_void_p)]
+
+
+def _array(ctype, items):
+    arr = (ctype * len(items))()
+    for i, it in enumerate(items):
+        arr[i] = it
+    return arr
 
 
 class _ZeroPool:
@@ -130,15 +160,18 @@ def _zeros(shape, device, pool: "_ZeroPool" = None):
 
 
 class Conv3x3BNReLU(torch.autograd.Function):
-    """relu(batchnorm(conv3x3(concat(x0, x1)))) with batch statistics."""
+    """relu(batchnorm(conv3x3(concat(x0, x1)))) with batch statistics.  wb and
+    wt are the weights' bf16 copy and flipped, transposed bf16 form, prepared
+    from w for this pass (UNet.prepare_weights)."""
 
     @staticmethod
-    def forward(ctx, x0, x1, w, gamma, beta, mr=None, pool=None):
+    def forward(ctx, x0, x1, w, gamma, beta, mr=None, pool=None, wb=None, wt=None):
         """mr (optional [2, cout] fp32) receives the batch (mean, rstd)."""
         N, H, W, c0 = x0.shape
         c1 = 0 if x1 is None else x1.shape[3]
         cout = w.shape[0]
-        wb = _bf16(w)
+        if wb is None:
+            wb = _bf16(w)
         z = torch.empty((N, H, W, cout), dtype=torch.bfloat16, device=x0.device)
         ctx.pool = pool
         stats = _zeros((2, cout), x0.device, pool)
@@ -151,6 +184,7 @@ class Conv3x3BNReLU(torch.autograd.Function):
         _call("sil_unet_bn_relu", _p(z), _p(stats), _p(gamma), _p(beta), ctypes.c_float(BN_EPS),
               P, _p(out), _p(mr), P, cout, _s())
         ctx.save_for_backward(x0, x1 if x1 is not None else torch.empty(0), wb, z, mr, gamma, beta)
+        ctx.wt = wt
         ctx.has_x1 = x1 is not None
         return out
 
@@ -164,26 +198,33 @@ class Conv3x3BNReLU(torch.autograd.Function):
         cout = wb.shape[0]
         P = N * H * W
         dz = torch.empty_like(z)
+        # fresh zeroed gradients: the batch-norm sums are formed in them directly
         dgamma = _zeros((cout,), z.device, ctx.pool)
         dbeta = _zeros((cout,), z.device, ctx.pool)
-        red = torch.empty((2, cout), dtype=torch.float32, device=z.device)
         _call("sil_unet_bn_relu_bwd", _p(dout), _p(z), _p(mr), _p(gamma), _p(beta), _p(dz),
-              _p(dgamma), _p(dbeta), _p(red), P, cout, _s())
+              _p(dgamma), _p(dbeta), None, P, cout, _s())
         dw = _zeros(wb.shape, z.device, ctx.pool)
         _call("sil_unet_conv3x3_wgrad", _p(dz), cout, _p(x0), c0, _p(x1), c1, _p(dw), N, H, W,
               _s())
         dx0 = dx1 = None
         if ctx.needs_input_grad[0] or (x1 is not None and ctx.needs_input_grad[1]):
-            wt = torch.empty((c0 + c1, 3, 3, cout), dtype=torch.bfloat16, device=z.device)
-            _call("sil_unet_flip3x3", _p(wb), _p(wt), cout, c0 + c1, _s())
+            wt = ctx.wt
+            if wt is None:
+                wt = torch.empty((c0 + c1, 3, 3, cout), dtype=torch.bfloat16, device=z.device)
+                _call("sil_unet_flip3x3", _p(wb), _p(wt), cout, c0 + c1, _s())
             dx0 = torch.empty_like(x0)
             dx1 = torch.empty_like(x1) if x1 is not None else None
             _call("sil_unet_conv3x3_dgrad", _p(dz), cout, _p(wt), _p(dx0), c0, _p(dx1), c1, N, H,
                   W, _s())
-        return dx0, dx1, dw, dgamma, dbeta, None, None
+        return dx0, dx1, dw, dgamma, dbeta, None, None, None, None
 
 
 class MaxPool2(torch.autograd.Function):
+    """2x2 max pooling that also hands its input on unchanged as the skip map:
+    returns (pooled, skip).  The gradients of both outputs reach one backward
+    call, where the routed pooled gradient and the skip gradient are summed in
+    one kernel."""
+
     @staticmethod
     def forward(ctx, x):
         N, H, W, C = x.shape
@@ -192,29 +233,38 @@ class MaxPool2(torch.autograd.Function):
         _call("sil_unet_maxpool", _p(x), _p(y), _p(idx), N, H, W, C, _s())
         ctx.save_for_backward(idx)
         ctx.shape = x.shape
-        return y
+        ctx.set_materialize_grads(False)
+        return y, x
 
     @staticmethod
-    def backward(ctx, dy):
+    def backward(ctx, dy, dskip):
         (idx,) = ctx.saved_tensors
         N, H, W, C = ctx.shape
+        if dy is None:
+            return dskip
         dx = torch.empty(ctx.shape, dtype=dy.dtype, device=dy.device)
-        _call("sil_unet_maxpool_bwd", _p(dy.contiguous()), _p(idx), _p(dx), N, H, W, C, _s())
+        dadd = None if dskip is None else dskip.contiguous()
+        _call("sil_unet_maxpool_bwd", _p(dy.contiguous()), _p(idx), _p(dadd), _p(dx), N, H, W, C,
+              _s())
         return dx
 
 
 class UpConv2(torch.autograd.Function):
-    """2x2 transposed convolution, stride 2, with bias; w: [2, 2, cout, cin]."""
+    """2x2 transposed convolution, stride 2, with bias; w: [2, 2, cout, cin].
+    wb and wt: the weights' bf16 copy and [cin, 2, 2, cout] bf16 form, prepared
+    for this pass (UNet.prepare_weights)."""
 
     @staticmethod
-    def forward(ctx, x, w, b, pool=None):
+    def forward(ctx, x, w, b, pool=None, wb=None, wt=None):
         ctx.pool = pool
         N, H, W, cin = x.shape
         cout = w.shape[2]
-        wb = _bf16(w)
+        if wb is None:
+            wb = _bf16(w)
         y = torch.empty((N, 2 * H, 2 * W, cout), dtype=torch.bfloat16, device=x.device)
         _call("sil_unet_upconv", _p(x), _p(wb), _p(b), _p(y), N, H, W, cin, cout, _s())
         ctx.save_for_backward(x, wb)
+        ctx.wt = wt
         return y
 
     @staticmethod
@@ -226,11 +276,13 @@ class UpConv2(torch.autograd.Function):
         dw = _zeros(wb.shape, x.device, ctx.pool)
         db = _zeros((cout,), x.device, ctx.pool)
         _call("sil_unet_upconv_wgrad", _p(x), _p(dy), _p(dw), _p(db), N, H, W, cin, cout, _s())
-        wt = torch.empty((cin, 2, 2, cout), dtype=torch.bfloat16, device=x.device)
-        _call("sil_unet_up_t", _p(wb), _p(wt), cin, cout, _s())
+        wt = ctx.wt
+        if wt is None:
+            wt = torch.empty((cin, 2, 2, cout), dtype=torch.bfloat16, device=x.device)
+            _call("sil_unet_up_t", _p(wb), _p(wt), cin, cout, _s())
         dx = torch.empty_like(x)
         _call("sil_unet_upconv_dgrad", _p(dy), _p(wt), _p(dx), N, H, W, cin, cout, _s())
-        return dx, dw, db, None
+        return dx, dw, db, None, None, None
 
 
 class HeadXent(torch.autograd.Function):
@@ -243,25 +295,31 @@ class HeadXent(torch.autograd.Function):
         logits = torch.empty((P, 3), dtype=torch.float32, device=x.device)
         _call("sil_unet_head", _p(x), _p(w), _p(b), _p(logits), P, C, _s())
         ctx.pool = pool
-        loss = _zeros((1,), x.device, pool)
+        loss = _zeros((1,), x.device)  # its own tensor: callers may keep it past the step
         dlogits = torch.empty_like(logits)
         _call("sil_unet_softmax_xent", _p(logits), _p(labels), _p(loss), _p(dlogits),
               ctypes.c_float(1.0 / P), P, _s())
         ctx.save_for_backward(x, w, dlogits)
         ctx.mark_non_differentiable(logits)
-        return loss[0] / P, logits.view(N, H, W, 3)
+        ctx.set_materialize_grads(False)
+        return loss.view(()), logits.view(N, H, W, 3)
 
     @staticmethod
     def backward(ctx, dloss, _dlogits):
         x, w, dlogits = ctx.saved_tensors
         N, H, W, C = x.shape
         P = N * H * W
-        # dlogits already carries the 1/P of the mean; scale by the incoming grad
-        dl = dlogits * dloss if float(dloss) != 1.0 else dlogits
         dx = torch.empty_like(x)
         dw = _zeros((3, C), x.device, ctx.pool)
         db = _zeros((3,), x.device, ctx.pool)
-        _call("sil_unet_head_bwd", _p(x), _p(w), _p(dl), _p(dx), _p(dw), _p(db), P, C, _s())
+        if dloss is None:
+            dx.zero_()
+            return dx, dw, db, None, None
+        # dlogits carries the 1/P of the mean; the kernel scales it by the
+        # incoming gradient on the device (no host synchronisation)
+        dl = dloss.contiguous()
+        _call("sil_unet_head_bwd", _p(x), _p(w), _p(dlogits), _p(dl), _p(dx), _p(dw), _p(db), P, C,
+              _s())
         return dx, dw, db, None, None
 
 
@@ -315,6 +373,38 @@ class UNet:
         self.batch_mr = {n: torch.empty((2, P[n + ".gamma"].numel()), device=device)
                          for n in self.bn_names}
         self.momentum = 0.1
+        # bf16 weights for the convolutions and their transposed forms for the
+        # input gradients, rewritten from the fp32 masters before every pass
+        self.wb, self.wt, preps = {}, {}, []
+        for name, kind, cin, cout in layer_specs(widths):
+            if kind == "conv1":
+                continue
+            w = self.params[name + ".w"]
+            self.wb[name] = torch.empty(w.shape, dtype=torch.bfloat16, device=device)
+            tshape = (cin, 3, 3, cout) if kind == "conv3" else (cin, 2, 2, cout)
+            self.wt[name] = torch.empty(tshape, dtype=torch.bfloat16, device=device)
+            preps.append((w, name, W_CONV3 if kind == "conv3" else W_UP2, cout, cin))
+        self._prep_train = _array(_WeightPrep, [
+            _WeightPrep(w.data_ptr(), self.wb[n].data_ptr(), self.wt[n].data_ptr(), k, co, ci)
+            for w, n, k, co, ci in preps])
+        self._prep_infer = _array(_WeightPrep, [
+            _WeightPrep(w.data_ptr(), self.wb[n].data_ptr(), None, k, co, ci)
+            for w, n, k, co, ci in preps])
+        # inference scale/shift from the running statistics
+        self.scale = {n: torch.empty(P[n + ".gamma"].numel(), device=device) for n in self.bn_names}
+        self.shift = {n: torch.empty(P[n + ".gamma"].numel(), device=device) for n in self.bn_names}
+        self._bn = _array(_BnLayer, [
+            _BnLayer(self.params[n + ".gamma"].numel(), self.batch_mr[n].data_ptr(),
+                     self.running[n][0].data_ptr(), self.running[n][1].data_ptr(),
+                     self.params[n + ".gamma"].data_ptr(), self.params[n + ".beta"].data_ptr(),
+                     self.scale[n].data_ptr(), self.shift[n].data_ptr())
+            for n in self.bn_names])
+
+    def prepare_weights(self, with_transposed: bool = True):
+        """Write the bf16 weights (and, for training, their transposed forms)
+        from the current fp32 masters: one launch for all layers."""
+        arr = self._prep_train if with_transposed else self._prep_infer
+        _call("sil_unet_prep_weights", ctypes.cast(arr, ctypes.c_void_p), len(arr), _s())
 
     def forward(self, x: torch.Tensor, labels: torch.Tensor):
         """x: bf16 [N, H, W, 8]; labels: uint8 [N, H, W].  Returns (loss, logits).
@@ -324,6 +414,7 @@ class UNet:
         gradients of the previous step must have been consumed (optimizer step
         taken, zero_grad called) before the next forward."""
         self.pool.begin_step(x.device)
+        self.prepare_weights(with_transposed=True)
         P = self.params
         skips = []
         h = x
@@ -331,29 +422,33 @@ class UNet:
 
         def cbr(h, skip, n):
             return Conv3x3BNReLU.apply(h, skip, P[n + ".w"], P[n + ".gamma"], P[n + ".beta"],
-                                       self.batch_mr[n], self.pool)
+                                       self.batch_mr[n], self.pool, self.wb[n], self.wt[n])
 
         for i in range(L):
             name = f"enc{i}" if i < L - 1 else "mid"
             h = cbr(cbr(h, None, name + ".conv0"), None, name + ".conv1")
             if i < L - 1:
-                skips.append(h)
-                h = MaxPool2.apply(h)
+                h, skip = MaxPool2.apply(h)
+                skips.append(skip)
         for i in reversed(range(L - 1)):
-            up = UpConv2.apply(h, P[f"dec{i}.up.w"], P[f"dec{i}.up.b"], self.pool)
+            n = f"dec{i}.up"
+            up = UpConv2.apply(h, P[n + ".w"], P[n + ".b"], self.pool, self.wb[n], self.wt[n])
             h = cbr(cbr(up, skips[i], f"dec{i}.conv0"), None, f"dec{i}.conv1")
         return HeadXent.apply(h, P["head.w"], P["head.b"], labels, self.pool)
 
+    def backward(self, loss: torch.Tensor):
+        """loss.backward() with a seed gradient of 1 kept on the device, so that
+        starting the backward pass launches no fill."""
+        if getattr(self, "_one", None) is None or self._one.device != loss.device:
+            self._one = torch.ones((), dtype=loss.dtype, device=loss.device)
+        loss.backward(self._one)
+
     @torch.no_grad()
     def update_running_stats(self):
-        """Exponential moving average of the last batch's statistics."""
-        m = self.momentum
-        for n in self.bn_names:
-            mean, rstd = self.batch_mr[n][0], self.batch_mr[n][1]
-            var = 1.0 / (rstd * rstd) - BN_EPS
-            rm, rv = self.running[n]
-            rm.mul_(1 - m).add_(mean, alpha=m)
-            rv.mul_(1 - m).add_(var, alpha=m)
+        """Exponential moving average of the last batch's statistics (biased
+        batch variance recovered from rstd), all layers in one launch."""
+        _call("sil_unet_bn_ema", ctypes.cast(self._bn, ctypes.c_void_p), len(self._bn),
+              ctypes.c_float(self.momentum), ctypes.c_float(BN_EPS), _s())
 
     @torch.no_grad()
     def infer_logits(self, x: torch.Tensor) -> torch.Tensor:
@@ -363,18 +458,18 @@ class UNet:
         P = self.params
         N, H, W, _ = x.shape
         dev = x.device
+        self.prepare_weights(with_transposed=False)
+        _call("sil_unet_bn_fold", ctypes.cast(self._bn, ctypes.c_void_p), len(self._bn),
+              ctypes.c_float(BN_EPS), _s())
 
         def cbr(h, skip, n):
             Nn, Hh, Ww, c0 = h.shape
             c1 = 0 if skip is None else skip.shape[3]
-            wb = _bf16(P[n + ".w"])
+            wb = self.wb[n]
             cout = wb.shape[0]
-            rm, rv = self.running[n]
-            scale = (P[n + ".gamma"] / torch.sqrt(rv + BN_EPS)).contiguous()
-            shift = (P[n + ".beta"] - rm * scale).contiguous()
             out = torch.empty((Nn, Hh, Ww, cout), dtype=torch.bfloat16, device=dev)
-            _call("sil_unet_conv3x3_affine_relu", _p(h), c0, _p(skip), c1, _p(wb), _p(scale),
-                  _p(shift), _p(out), Nn, Hh, Ww, cout, _s())
+            _call("sil_unet_conv3x3_affine_relu", _p(h), c0, _p(skip), c1, _p(wb),
+                  _p(self.scale[n]), _p(self.shift[n]), _p(out), Nn, Hh, Ww, cout, _s())
             return out
 
         skips, h, L = [], x, len(self.widths)
@@ -382,10 +477,11 @@ class UNet:
             name = f"enc{i}" if i < L - 1 else "mid"
             h = cbr(cbr(h, None, name + ".conv0"), None, name + ".conv1")
             if i < L - 1:
-                skips.append(h)
-                h = MaxPool2.apply(h)
+                h, skip = MaxPool2.apply(h)
+                skips.append(skip)
         for i in reversed(range(L - 1)):
-            up = UpConv2.apply(h, P[f"dec{i}.up.w"], P[f"dec{i}.up.b"])
+            n = f"dec{i}.up"
+            up = UpConv2.apply(h, P[n + ".w"], P[n + ".b"], None, self.wb[n])
             h = cbr(cbr(up, skips[i], f"dec{i}.conv0"), None, f"dec{i}.conv1")
         C = h.shape[3]
         logits = torch.empty((N, H, W, 3), dtype=torch.float32, device=dev)
@@ -406,7 +502,8 @@ class UNet:
 
 
 class Adam:
-    """Adam on the model's fp32 master weights (one fused kernel per tensor)."""
+    """Adam on the model's fp32 master weights: every tensor with a gradient in
+    one multi-tensor launch."""
 
     def __init__(self, params: Dict[str, torch.Tensor], lr=1e-3, betas=(0.9, 0.999), eps=1e-8):
         self.params = params
@@ -414,16 +511,28 @@ class Adam:
         self.m = {k: torch.zeros_like(v) for k, v in params.items()}
         self.v = {k: torch.zeros_like(v) for k, v in params.items()}
         self.t = 0
+        self._key = None
+        self._arr = None
 
     @torch.no_grad()
     def step(self):
         self.t += 1
+        items = []
         for k, p in self.params.items():
             if p.grad is None:
                 continue
-            _call("sil_unet_adam", _p(p), _p(p.grad.contiguous()), _p(self.m[k]), _p(self.v[k]),
-                  None, p.numel(), ctypes.c_float(self.lr), ctypes.c_float(self.b1),
-                  ctypes.c_float(self.b2), ctypes.c_float(self.eps), self.t, _s())
+            g = p.grad if p.grad.is_contiguous() else p.grad.contiguous()
+            items.append((p.data_ptr(), g.data_ptr(), self.m[k].data_ptr(),
+                          self.v[k].data_ptr(), p.numel(), g))
+        if not items:
+            return
+        key = tuple(it[:5] for it in items)
+        if key != self._key:  # gradients usually sit at the same addresses every step
+            self._arr = _array(_AdamTensor, [_AdamTensor(*it[:5]) for it in items])
+            self._key = key
+        _call("sil_unet_adam_multi", ctypes.cast(self._arr, ctypes.c_void_p), len(self._arr),
+              ctypes.c_float(self.lr), ctypes.c_float(self.b1), ctypes.c_float(self.b2),
+              ctypes.c_float(self.eps), self.t, _s())
 
     def zero_grad(self):
         for p in self.params.values():

@@ -78,9 +78,12 @@ def test_bn_relu(un, P, C):
     _check(out, ref, BF * ref + 8 * U32 * (t.abs() + beta.double().abs()), "bn_relu out")
 
 
-@pytest.mark.parametrize("P,C", [(512, 8), (2048, 64), (1000, 256)])
-def test_bn_relu_backward(un, P, C):
-    _say(f"case bn_relu_bwd P={P} C={C}")
+@pytest.mark.parametrize("P,C,scratch", [(512, 8, True), (2048, 64, True), (1000, 256, True),
+                                         (3000, 32, False), (1000, 256, False)])
+def test_bn_relu_backward(un, P, C, scratch):
+    """With scratch the sums are added to dgamma/dbeta; without it they are
+    formed in dgamma/dbeta directly (zero on entry)."""
+    _say(f"case bn_relu_bwd P={P} C={C} scratch={scratch}")
     g = torch.Generator().manual_seed(7 * P + C)
     z = _bf((P, C), g, 2.0)
     dout = _bf((P, C), g)
@@ -92,7 +95,7 @@ def test_bn_relu_backward(un, P, C):
     dz = torch.empty((P, C), dtype=torch.bfloat16, device="cuda")
     dgamma = torch.zeros(C, device="cuda")
     dbeta = torch.zeros(C, device="cuda")
-    red = torch.empty((2, C), device="cuda")
+    red = torch.empty((2, C), device="cuda") if scratch else None
     zc, dc, mrc, gc, bc = z.cuda(), dout.cuda(), mr.cuda(), gamma.cuda(), beta.cuda()
     un._call("sil_unet_bn_relu_bwd", un._p(dc), un._p(zc), un._p(mrc), un._p(gc), un._p(bc),
              un._p(dz), un._p(dgamma), un._p(dbeta), un._p(red), P, C, un._s())
@@ -147,7 +150,12 @@ def test_maxpool_forward_and_backward_with_ties(un):
     dy = _bf((N, H // 2, W // 2, C), g)
     dyc = dy.cuda()
     dx = torch.empty((N, H, W, C), dtype=torch.bfloat16, device="cuda")
-    un._call("sil_unet_maxpool_bwd", un._p(dyc), un._p(idx), un._p(dx), N, H, W, C, un._s())
+    un._call("sil_unet_maxpool_bwd", un._p(dyc), un._p(idx), None, un._p(dx), N, H, W, C, un._s())
+    # with the skip connection's gradient added in the same kernel, in place
+    dskip = _bf((N, H, W, C), g)
+    dsum = dskip.cuda()
+    un._call("sil_unet_maxpool_bwd", un._p(dyc), un._p(idx), un._p(dsum), un._p(dsum), N, H, W, C,
+             un._s())
     torch.cuda.synchronize()
     # window positions in row-major order; the first maximum wins
     win = torch.stack([x[:, 0::2, 0::2], x[:, 0::2, 1::2], x[:, 1::2, 0::2], x[:, 1::2, 1::2]])
@@ -159,6 +167,8 @@ def test_maxpool_forward_and_backward_with_ties(un):
     for k, (a, b) in enumerate([(0, 0), (0, 1), (1, 0), (1, 1)]):
         ref[:, a::2, b::2] = torch.where(first == k, dy, torch.zeros((), dtype=torch.bfloat16))
     assert torch.equal(dx.cpu(), ref)
+    # the fp32 sum of two bf16 values, rounded once to bf16
+    assert torch.equal(dsum.cpu(), (ref.float() + dskip.float()).to(torch.bfloat16))
 
 
 @pytest.mark.parametrize("P,C", [(777, 8), (2048, 32), (300, 256)])
@@ -175,14 +185,16 @@ def test_head_forward_and_backward(un, P, C):
     dx = torch.empty((P, C), dtype=torch.bfloat16, device="cuda")
     dw = torch.zeros((3, C), device="cuda")
     db = torch.zeros(3, device="cuda")
-    un._call("sil_unet_head_bwd", un._p(xc), un._p(wc), un._p(dlc), un._p(dx), un._p(dw), un._p(db),
-             P, C, un._s())
+    # the gradient arriving at the loss scales dlogits on the device
+    dscale = torch.tensor([1.5], device="cuda")
+    un._call("sil_unet_head_bwd", un._p(xc), un._p(wc), un._p(dlc), un._p(dscale), un._p(dx),
+             un._p(dw), un._p(db), P, C, un._s())
     torch.cuda.synchronize()
-    xd, wd, dld = x.double(), w.double(), dl.double()
+    xd, wd, dld = x.double(), w.double(), 1.5 * dl.double()
     ref = xd @ wd.T + b.double()
     _check(logits, ref, (C + 1) * U32 * (xd.abs() @ wd.abs().T + b.double().abs()), "head logits")
     rdx = dld @ wd
-    _check(dx, rdx, BF * rdx.abs() + 4 * U32 * (dld.abs() @ wd.abs()), "head dx")
+    _check(dx, rdx, BF * rdx.abs() + 6 * U32 * (dld.abs() @ wd.abs()), "head dx")
     rdw = dld.T @ xd
     _check(dw, rdw, P * U32 * (dld.abs().T @ xd.abs()) + 1e-30, "head dw")
     _check(db, dld.sum(0), P * U32 * dld.abs().sum(0) + 1e-30, "head db")
@@ -207,8 +219,9 @@ def test_softmax_xent(un):
     # expf/logf and the three-term sums: a few units of float32 roundoff per pixel
     # per pixel: expf, logf and the three-term sum (a few float32 roundoffs);
     # across pixels: a tree inside each block and one atomic per block
-    _check(loss[0], per.sum(), 16 * U32 * (lse.abs() + ld.abs().max(1).values).sum()
-           + (np.log2(P) + 64) * U32 * per.sum(), "loss")
+    # loss is the scaled sum (scale = 1/P: the mean)
+    _check(loss[0], scale * per.sum(), scale * (16 * U32 * (lse.abs() + ld.abs().max(1).values).sum()
+           + (np.log2(P) + 64) * U32 * per.sum()), "loss")
     sm = torch.softmax(ld, 1)
     ref = (sm - torch.nn.functional.one_hot(labels.long(), 3).double()) * scale
     _check(dl, ref, 16 * U32 * scale * (sm + 1.0), "dlogits")
@@ -296,3 +309,114 @@ def test_to_bf16_and_fill(un):
     torch.cuda.synchronize()
     assert torch.equal(y.cpu().view(torch.int16), x.to(torch.bfloat16).view(torch.int16))
     assert (f.cpu() == -2.5).all()
+
+
+def test_adam_multi_tensor(un):
+    """One launch over 50 tensors (two launches of at most 48), sizes around
+    the per-block chunk, against the float64 update of each tensor."""
+    _say("case adam_multi")
+    g = torch.Generator().manual_seed(18)
+    sizes = [1, 7, 1023, 1024, 1025, 4096 + 3] + [int(v) for v in
+                                                  torch.randint(1, 3000, (44,), generator=g)]
+    lr, b1, b2, eps, step = 1e-3, 0.9, 0.999, 1e-8, 5
+    host, dev, items = [], [], []
+    for n in sizes:
+        t = [torch.randn(n, generator=g), torch.randn(n, generator=g) * 1e-2,
+             torch.randn(n, generator=g) * 1e-3, torch.rand(n, generator=g) * 1e-4]
+        d = [x.cuda() for x in t]
+        host.append(t)
+        dev.append(d)
+        items.append(un._AdamTensor(d[0].data_ptr(), d[1].data_ptr(), d[2].data_ptr(),
+                                    d[3].data_ptr(), n))
+    arr = un._array(un._AdamTensor, items)
+    un._call("sil_unet_adam_multi", ctypes.cast(arr, ctypes.c_void_p), len(arr),
+             ctypes.c_float(lr), ctypes.c_float(b1), ctypes.c_float(b2), ctypes.c_float(eps),
+             step, un._s())
+    torch.cuda.synchronize()
+    f = lambda a: float(np.float32(a))
+    b1f, b2f = f(b1), f(b2)
+    c1, c2 = f(1 - f(b1f ** step)), f(1 - f(b2f ** step))
+    for k, ((w, grad, m, v), (wc, _, mc, vc)) in enumerate(zip(host, dev)):
+        gd, md, vd = grad.double(), m.double(), v.double()
+        mr = b1f * md + (1 - b1f) * gd
+        vr = b2f * vd + (1 - b2f) * gd * gd
+        upd = f(lr) * (mr / c1) / (torch.sqrt(vr / c2) + f(eps))
+        wr = w.double() - upd
+        _check(mc, mr, 4 * U32 * (b1f * md.abs() + gd.abs()), f"adam_multi m[{k}]")
+        _check(vc, vr, 4 * U32 * (b2f * vd + gd * gd), f"adam_multi v[{k}]")
+        _check(wc, wr, 2 * U32 * wr.abs() + 32 * U32 * upd.abs(), f"adam_multi w[{k}]")
+
+
+def test_prep_weights_layouts(un):
+    """bf16 copies (round to nearest even) and the transposed forms, bit for
+    bit: wt[ci][r][s][co] = w[co][2-r][2-s][ci] for 3x3 weights and
+    wt[ci][q][co] = w[q][co][ci] for 2x2 up-convolution weights."""
+    _say("case prep_weights")
+    g = torch.Generator().manual_seed(19)
+    specs = [("conv3", 16, 8), ("conv3", 32, 64), ("up2", 24, 48), ("conv3", 8, 40),
+             ("up2", 8, 8)]
+    keep, items, refs = [], [], []
+    for kind, cout, cin in specs:
+        shape = (cout, 3, 3, cin) if kind == "conv3" else (2, 2, cout, cin)
+        w = torch.randn(shape, generator=g) * 3
+        wc = w.cuda()
+        wb = torch.empty(shape, dtype=torch.bfloat16, device="cuda")
+        tshape = (cin, 3, 3, cout) if kind == "conv3" else (cin, 2, 2, cout)
+        wt = torch.empty(tshape, dtype=torch.bfloat16, device="cuda")
+        keep += [wc, wb, wt]
+        items.append(un._WeightPrep(wc.data_ptr(), wb.data_ptr(), wt.data_ptr(),
+                                    un.W_CONV3 if kind == "conv3" else un.W_UP2, cout, cin))
+        b = w.to(torch.bfloat16)
+        if kind == "conv3":
+            t = b.flip(1, 2).permute(3, 1, 2, 0).contiguous()
+        else:
+            t = b.permute(3, 0, 1, 2).contiguous()
+        refs.append((wb, b, wt, t))
+    arr = un._array(un._WeightPrep, items)
+    un._call("sil_unet_prep_weights", ctypes.cast(arr, ctypes.c_void_p), len(arr), un._s())
+    torch.cuda.synchronize()
+    for k, (wb, b, wt, t) in enumerate(refs):
+        assert torch.equal(wb.cpu().view(torch.int16), b.view(torch.int16)), f"wb[{k}]"
+        assert torch.equal(wt.cpu().view(torch.int16), t.view(torch.int16)), f"wt[{k}]"
+
+
+def test_bn_running_statistics_and_fold(un):
+    """EMA of the batch statistics (variance recovered from rstd) and the
+    inference scale/shift, against float64 on the same float32 inputs."""
+    _say("case bn_ema and bn_fold")
+    g = torch.Generator().manual_seed(20)
+    mom, eps = 0.1, 1e-5
+    layers, host, keep = [], [], []
+    for C in (8, 32, 256, 64):
+        mean = torch.randn(C, generator=g)
+        rstd = torch.rand(C, generator=g) * 3 + 0.2
+        rm = torch.randn(C, generator=g)
+        rv = torch.rand(C, generator=g) + 0.1
+        gamma = torch.rand(C, generator=g) + 0.5
+        beta = torch.randn(C, generator=g)
+        mr = torch.stack([mean, rstd]).cuda()
+        rmc, rvc, gc, bc = rm.cuda(), rv.cuda(), gamma.cuda(), beta.cuda()
+        sc, sh = torch.empty(C, device="cuda"), torch.empty(C, device="cuda")
+        keep += [mr, rmc, rvc, gc, bc, sc, sh]
+        layers.append(un._BnLayer(C, mr.data_ptr(), rmc.data_ptr(), rvc.data_ptr(), gc.data_ptr(),
+                                  bc.data_ptr(), sc.data_ptr(), sh.data_ptr()))
+        host.append((mean, rstd, rm, rv, gamma, beta, rmc, rvc, sc, sh))
+    arr = un._array(un._BnLayer, layers)
+    un._call("sil_unet_bn_ema", ctypes.cast(arr, ctypes.c_void_p), len(arr), ctypes.c_float(mom),
+             ctypes.c_float(eps), un._s())
+    un._call("sil_unet_bn_fold", ctypes.cast(arr, ctypes.c_void_p), len(arr), ctypes.c_float(eps),
+             un._s())
+    torch.cuda.synchronize()
+    m32, e32 = float(np.float32(mom)), float(np.float32(eps))
+    for k, (mean, rstd, rm, rv, gamma, beta, rmc, rvc, sc, sh) in enumerate(host):
+        var = 1.0 / rstd.double() ** 2 - e32
+        rm1 = (1 - m32) * rm.double() + m32 * mean.double()
+        rv1 = (1 - m32) * rv.double() + m32 * var
+        _check(rmc, rm1, 4 * U32 * (rm.double().abs() + mean.double().abs()), f"running_mean[{k}]")
+        _check(rvc, rv1, 8 * U32 * (rv.double().abs() + var.abs() + e32), f"running_var[{k}]")
+        # the fold reads the updated float32 running statistics
+        rmg, rvg = rmc.cpu().double(), rvc.cpu().double()
+        scale = gamma.double() / torch.sqrt(rvg + e32)
+        shift = beta.double() - rmg * scale
+        _check(sc, scale, 8 * U32 * scale.abs(), f"scale[{k}]")
+        _check(sh, shift, 8 * U32 * (beta.double().abs() + (rmg * scale).abs()), f"shift[{k}]")
