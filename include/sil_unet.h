@@ -55,12 +55,33 @@ int sil_unet_conv3x3_affine_relu(const void* x0, int32_t c0, const void* x1, int
                                  const void* w, const float* scale, const float* shift, void* y,
                                  int32_t N, int32_t H, int32_t W, int32_t cout, void* stream);
 
+/* Batch-norm backward sums of a conv + batch-norm + ReLU layer, formed by the
+ * call that produces the gradient dout of that layer's output (passed to the
+ * input-gradient, pooling and head backward calls below; NULL: none).  With d
+ * = dout where the layer's ReLU passed (xhat * gamma + beta > 0, xhat = (z -
+ * mean) * rstd) and 0 elsewhere: sum_d[c] += sum_p d (the beta gradient),
+ * sum_dxhat[c] += sum_p d * xhat (the gamma gradient), both fp32 [C]
+ * accumulate; sil_unet_bn_relu_bwd_apply then forms dz from them.  z: the
+ * layer's batch-norm input [P][C] bf16, same pixels as dout; mr: its (mean,
+ * rstd) [2][C].  C must equal dout's channel count and 256 % (C/8) == 0. */
+typedef struct sil_unet_bn_grad {
+  const void* z;
+  const float* mr;
+  const float* gamma;
+  const float* beta;
+  float* sum_d;
+  float* sum_dxhat;
+  int32_t C;
+} sil_unet_bn_grad;
+
 /* Input gradient of sil_unet_conv3x3: dx = conv3x3(dy, wt) with wt the
  * flipped, transposed weights [c0+c1][3][3][cout] (sil_unet_flip3x3).  The
  * result is split by channel into dx0 [N][H][W][c0] and dx1 [..][c1]
- * (dx1 NULL when c1 = 0). */
+ * (dx1 NULL when c1 = 0).  bn (nullable, only with c1 = 0): the sums of the
+ * layer whose output gradient dx0 is. */
 int sil_unet_conv3x3_dgrad(const void* dy, int32_t cout, const void* wt, void* dx0, int32_t c0,
-                           void* dx1, int32_t c1, int32_t N, int32_t H, int32_t W, void* stream);
+                           void* dx1, int32_t c1, int32_t N, int32_t H, int32_t W,
+                           const sil_unet_bn_grad* bn, void* stream);
 
 /* Weight gradient of sil_unet_conv3x3 (accumulate): dw [cout][3][3][c0+c1] fp32
  * += sum over pixels of dy (x) im2col(concat(x0, x1)). */
@@ -78,9 +99,11 @@ int sil_unet_upconv(const void* x, const void* w, const float* b, void* y, int32
                     int32_t W, int32_t cin, int32_t cout, void* stream);
 
 /* Input gradient: dx[n][h][w][ci] = sum_{i,j,co} dy[n][2h+i][2w+j][co] *
- * w[i][j][co][ci], with wt = the weights as [ci][2][2][co] (sil_unet_up_t). */
+ * w[i][j][co][ci], with wt = the weights as [ci][2][2][co] (sil_unet_up_t).
+ * bn (nullable): the sums of the layer whose output gradient dx is. */
 int sil_unet_upconv_dgrad(const void* dy, const void* wt, void* dx, int32_t N, int32_t H,
-                          int32_t W, int32_t cin, int32_t cout, void* stream);
+                          int32_t W, int32_t cin, int32_t cout, const sil_unet_bn_grad* bn,
+                          void* stream);
 
 /* Weight and bias gradients (accumulate): dw fp32 [2][2][cout][cin],
  * db fp32 [cout]. */
@@ -115,6 +138,15 @@ int sil_unet_bn_relu_bwd(const void* dout, const void* z, const float* mr, const
                          const float* beta, void* dz, float* dgamma, float* dbeta, float* red,
                          int64_t P, int32_t C, void* stream);
 
+/* The second half of sil_unet_bn_relu_bwd, with the per-channel sums given
+ * (sum_d = the beta gradient, sum_dxhat = the gamma gradient, e.g. formed
+ * through a sil_unet_bn_grad request): dz = gamma * rstd * (d - (sum_d + xhat
+ * sum_dxhat) / P). */
+int sil_unet_bn_relu_bwd_apply(const void* dout, const void* z, const float* mr,
+                               const float* gamma, const float* beta, const float* sum_d,
+                               const float* sum_dxhat, void* dz, int64_t P, int32_t C,
+                               void* stream);
+
 /* 2x2 max pooling, stride 2 (H, W even).  idx [N][H/2][W/2][C] u8 records
  * the winning position (first maximum in row-major window order). */
 int sil_unet_maxpool(const void* x, void* y, uint8_t* idx, int32_t N, int32_t H, int32_t W,
@@ -122,9 +154,11 @@ int sil_unet_maxpool(const void* x, void* y, uint8_t* idx, int32_t N, int32_t H,
 /* Backward: dx [N][H][W][C] = dy routed to each window's winner (zero
  * elsewhere), plus dadd [N][H][W][C] when non-NULL (the gradient the same
  * tensor receives from its other consumer, e.g. the skip connection; summed in
- * fp32, rounded once to bf16).  dadd may be dx itself. */
+ * fp32, rounded once to bf16).  dadd may be dx itself.  bn (nullable): the
+ * sums of the layer whose output gradient dx is. */
 int sil_unet_maxpool_bwd(const void* dy, const uint8_t* idx, const void* dadd, void* dx,
-                         int32_t N, int32_t H, int32_t W, int32_t C, void* stream);
+                         int32_t N, int32_t H, int32_t W, int32_t C, const sil_unet_bn_grad* bn,
+                         void* stream);
 
 /* 1x1 head: logits[p][k] = b[k] + sum_c x[p][c] w[k][c], k < 3 (fp32 out). */
 int sil_unet_head(const void* x, const float* w, const float* b, float* logits, int64_t P,
@@ -139,9 +173,11 @@ int sil_unet_softmax_xent(const float* logits, const uint8_t* labels, float* los
 
 /* Head backward: with d = dlogits * dscale[0] (dscale: nullable device fp32
  * scalar, the gradient arriving at the loss; NULL means 1), dx [P][C] bf16 =
- * d w; dw fp32 [3][C] += sum_p d x; db fp32 [3] += sum_p d. */
+ * d w; dw fp32 [3][C] += sum_p d x; db fp32 [3] += sum_p d.  bn (nullable):
+ * the sums of the layer whose output gradient dx is. */
 int sil_unet_head_bwd(const void* x, const float* w, const float* dlogits, const float* dscale,
-                      void* dx, float* dw, float* db, int64_t P, int32_t C, void* stream);
+                      void* dx, float* dw, float* db, int64_t P, int32_t C,
+                      const sil_unet_bn_grad* bn, void* stream);
 
 /* Class map: labels[p] = argmax_k logits[p][k] (first maximum). */
 int sil_unet_argmax(const float* logits, uint8_t* labels, int64_t P, void* stream);

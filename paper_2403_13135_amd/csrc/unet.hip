@@ -44,13 +44,99 @@ constexpr int kLdsRow = 40;   // u16 per LDS row: 32 + 8 padding (80 bytes)
 // fp32 -> bf16, round to nearest even (gfx950's v_cvt_pk_bf16_f32)
 __device__ __forceinline__ u16 f2bf(float f) { return __builtin_bit_cast(u16, (__bf16)f); }
 
+// 8 bf16 <-> 8 floats
+__device__ __forceinline__ void unpack8(uint4 v, float f[8]) {
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    f[2 * i] = __uint_as_float(w[i] << 16);
+    f[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+  }
+}
+__device__ __forceinline__ uint4 pack8(const float f[8]) {
+  uint32_t w[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) w[i] = (uint32_t)f2bf(f[2 * i]) | ((uint32_t)f2bf(f[2 * i + 1]) << 16);
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// Batch-norm backward sums of one layer, formed by the kernel that produces
+// that layer's output gradient dout: d = dout where the layer's ReLU passed
+// (xhat * gamma + beta > 0, xhat = (z - mean) * rstd), s1[c] += sum d (the
+// beta gradient), s2[c] += sum d * xhat (the gamma gradient).
+struct BnGrad {
+  const u16* z;  // [P][C] bf16 batch-norm input; nullptr: no sums
+  const float* mr;
+  const float* gamma;
+  const float* beta;
+  float* s1;
+  float* s2;
+  int32_t C;
+};
+
+// One thread's share of the sums: 8 consecutive channels
+struct BnAcc8 {
+  float mean[8], rstd[8], gm[8], bt[8], a1[8], a2[8];
+  __device__ __forceinline__ void init(const BnGrad& b, int32_t c0) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const bool ok = c0 + j < b.C;  // channels past C (a partial tile) never pass
+      mean[j] = ok ? b.mr[c0 + j] : 0.f;
+      rstd[j] = ok ? b.mr[b.C + c0 + j] : 0.f;
+      gm[j] = ok ? b.gamma[c0 + j] : 0.f;
+      bt[j] = ok ? b.beta[c0 + j] : 0.f;
+      a1[j] = 0.f;
+      a2[j] = 0.f;
+    }
+  }
+  __device__ __forceinline__ void add(const uint4 zin, const uint4 din) {
+    float fz[8], fd[8];
+    unpack8(zin, fz);
+    unpack8(din, fd);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const float zh = (fz[j] - mean[j]) * rstd[j];
+      const float d = zh * gm[j] + bt[j] > 0.f ? fd[j] : 0.f;
+      a1[j] += d;
+      a2[j] += d * zh;
+    }
+  }
+  // Block-wide: threads t and t' hold the same channels iff t % G == t' % G;
+  // thread t's channels are c_first + 8 * (t % G) + 0..7.  lds: 16 * 256
+  // floats, free on entry.  One atomic per channel per block.  Every thread
+  // of the block calls this.
+  __device__ __forceinline__ void flush(const BnGrad& b, float* lds, int G, int32_t c_first) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      lds[j * 256 + t] = a1[j];
+      lds[(8 + j) * 256 + t] = a2[j];
+    }
+    __syncthreads();
+    for (int u = t; u < 8 * G; u += 256) {
+      const int grp = u >> 3, j = u & 7;
+      const int32_t c = c_first + 8 * grp + j;
+      if (c >= b.C) continue;
+      float e1 = 0.f, e2 = 0.f;
+      for (int q = grp; q < 256; q += G) {
+        e1 += lds[j * 256 + q];
+        e2 += lds[(8 + j) * 256 + q];
+      }
+      atomicAdd(&b.s1[c], e1);
+      atomicAdd(&b.s2[c], e2);
+    }
+  }
+};
+
 // A_IM2COL32: the im2col of A_IM2COL when c0 + c1 is a multiple of 32, so a
 // 32-wide reduction step lies inside one tap: the tap and channel offset are
 // block-uniform counters and each row's shifted address is one add.
 enum AMode : int { A_ROWS = 0, A_IM2COL = 1, A_UPGATHER = 2, A_IM2COL32 = 3 };
 // E_AFFRELU: inference epilogue, y = max(0, acc * scale[n] + shift[n]) (batch
 // norm with running statistics folded into scale/shift, then ReLU)
-enum EMode : int { E_STORE = 0, E_SPLIT = 1, E_UPSCATTER = 2, E_AFFRELU = 3 };
+// E_BNGRAD: bf16 store of an output gradient, with the batch-norm backward
+// sums of the layer it belongs to (g.bn) formed on the way
+enum EMode : int { E_STORE = 0, E_SPLIT = 1, E_UPSCATTER = 2, E_AFFRELU = 3, E_BNGRAD = 4 };
 
 struct GemmNT {
   int32_t M, N, K;
@@ -66,6 +152,7 @@ struct GemmNT {
   float* stats;       // STORE: [2][N] (nullable)
   const float* scale;  // AFFRELU: [N]
   const float* shift;  // AFFRELU: [N]
+  BnGrad bn;           // STORE: batch-norm backward sums of y0 (bn.z nullable)
 };
 
 // 16 bytes (8 bf16) of A at row m, reduction index k (k % 8 == 0).
@@ -124,6 +211,10 @@ __global__ __launch_bounds__(kGT) void k_gemm_nt(GemmNT g) {
   float s1[NJ], s2[NJ];
 #pragma unroll
   for (int j = 0; j < NJ; ++j) s1[j] = s2[j] = 0.f;
+  constexpr int NQ = BM * (BN / 8) / kGT;  // 16-byte output chunks per thread per tile
+  static_assert(NQ * kGT == BM * (BN / 8), "whole chunks per thread");
+  BnAcc8 bacc;  // E_BNGRAD: this thread's 8 channels are n0 + 8 * (tid % (BN / 8))
+  if constexpr (EM == E_BNGRAD) bacc.init(g.bn, n0 + 8 * (tid % (BN / 8)));
 
   for (int32_t mt = blockIdx.x; mt < mtiles; mt += gridDim.x) {
     const int32_t m0 = mt * BM;
@@ -222,6 +313,17 @@ __global__ __launch_bounds__(kGT) void k_gemm_nt(GemmNT g) {
     // col = wave cols + 16j + lane%16.  The bf16 tile goes through LDS (the
     // operand buffers are free: the last K step ended in a barrier) so that
     // global stores are 16 bytes of 8 consecutive columns.
+    uint4 zpre[EM == E_BNGRAD ? NQ : 1];  // E_BNGRAD: batch-norm input at the stored chunks
+    if constexpr (EM == E_BNGRAD) {
+#pragma unroll
+      for (int r = 0; r < NQ; ++r) {
+        const int q = tid + kGT * r;
+        const int rl = q / (BN / 8), ch = q - rl * (BN / 8);
+        const int32_t row = m0 + rl, col = n0 + 8 * ch;
+        zpre[r] = make_uint4(0, 0, 0, 0);
+        if (row < g.M && col < g.N) zpre[r] = *(const uint4*)(g.bn.z + (int64_t)row * g.N + col);
+      }
+    }
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
       const int cl = wn * 16 * NJ + 16 * j + (lane & 15);
@@ -255,7 +357,9 @@ __global__ __launch_bounds__(kGT) void k_gemm_nt(GemmNT g) {
         }
     }
     __syncthreads();
-    for (int q = tid; q < BM * (BN / 8); q += kGT) {
+#pragma unroll
+    for (int r = 0; r < NQ; ++r) {
+      const int q = tid + kGT * r;
       const int rl = q / (BN / 8), ch = q - rl * (BN / 8);
       const int32_t row = m0 + rl, col = n0 + 8 * ch;
       if (row >= g.M || col >= g.N) continue;
@@ -276,9 +380,11 @@ __global__ __launch_bounds__(kGT) void k_gemm_nt(GemmNT g) {
       } else {
         *(uint4*)(g.y0 + (int64_t)row * g.N + col) = val;
       }
+      if constexpr (EM == E_BNGRAD) bacc.add(zpre[r], val);
     }
     __syncthreads();  // the staged tile overlaps the next tile's operand buffers
   }
+  if constexpr (EM == E_BNGRAD) bacc.flush(g.bn, (float*)smem, BN / 8, n0);
 
   if constexpr (EM == E_STORE) {
     if (g.stats) {
@@ -346,6 +452,8 @@ __global__ __launch_bounds__(kGT) void k_conv3_lds(GemmNT g) {
   float s1[NJ], s2[NJ];
 #pragma unroll
   for (int j = 0; j < NJ; ++j) s1[j] = s2[j] = 0.f;
+  BnAcc8 bacc;  // E_BNGRAD: this thread's 8 channels are n0 + 8 * (tid % (BN / 8))
+  if constexpr (EM == E_BNGRAD) bacc.init(g.bn, n0 + 8 * (tid % (BN / 8)));
 
   // The block's work is a sequence of (tile, chunk) items: tiles blockIdx.x,
   // blockIdx.x + gridDim.x, ..., each with nchunk input chunks.  The loads of
@@ -423,24 +531,37 @@ __global__ __launch_bounds__(kGT) void k_conv3_lds(GemmNT g) {
         gload(t, (c + 1) * kBK, true);
       else if (t + gridDim.x < ntiles)
         gload(t + gridDim.x, 0, !w_once);
+      // Tap (dy, dx) multiplies output row block i (row 2*wave + i/2, column
+      // half i%2) with staged row 2*wave + i/2 + dy shifted by dx.  Per column
+      // shift dx, the four staged rows u = i/2 + dy = 0..3 of each column half
+      // are read once and serve the taps dy = u - i/2: 8 A and 3*NJ weight
+      // reads per 12*NJ MFMAs.
 #pragma unroll
-      for (int tap = 0; tap < 9; ++tap) {
-        const int dy = tap / 3, dx = tap % 3;
-        bf16x8 a[4], b[NJ];
+      for (int dx = 0; dx < 3; ++dx) {
+        bf16x8 b[3][NJ];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          a[i] = __builtin_bit_cast(
-              bf16x8, *(const uint4*)&Si[2 * wave + (i >> 1) + dy][16 * (i & 1) + (lane & 15) + dx]
-                                        [8 * (lane >> 4)]);
-#pragma unroll
-        for (int j = 0; j < NJ; ++j)
-          b[j] = __builtin_bit_cast(bf16x8,
-                                    *(const uint4*)&Sw[tap][16 * j + (lane & 15)][8 * (lane >> 4)]);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
           for (int j = 0; j < NJ; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+            b[dy][j] = __builtin_bit_cast(
+                bf16x8, *(const uint4*)&Sw[dy * 3 + dx][16 * j + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const bf16x8 a = __builtin_bit_cast(
+                bf16x8,
+                *(const uint4*)&Si[2 * wave + u][16 * h + (lane & 15) + dx][8 * (lane >> 4)]);
+#pragma unroll
+            for (int ih = 0; ih < 2; ++ih) {  // output row 2*wave + ih uses tap dy = u - ih
+              const int dy = u - ih;
+              if (dy < 0 || dy > 2) continue;
+#pragma unroll
+              for (int j = 0; j < NJ; ++j)
+                acc[2 * ih + h][j] =
+                    __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[dy][j], acc[2 * ih + h][j], 0, 0, 0);
+            }
+          }
       }
     }
 
@@ -448,6 +569,19 @@ __global__ __launch_bounds__(kGT) void k_conv3_lds(GemmNT g) {
     // 4*(lane/16) + t), channel n0 + 16j + lane%16.  The bf16 tile goes through LDS
     // (the staged input is no longer needed) so that global stores are 16 bytes.
     u16* const So = &Si[0][0][0];  // [256 pixels][kLdsRow]
+    uint4 zpre[BN / 8];            // E_BNGRAD: the batch-norm input at the stored chunks
+    if constexpr (EM == E_BNGRAD) {
+#pragma unroll
+      for (int r = 0; r < BN / 8; ++r) {
+        const int q = tid + kGT * r;
+        const int pl = q / (BN / 8), sub = q % (BN / 8);
+        const int32_t oy = oy0 + pl / kCTW, ox = ox0 + pl % kCTW;
+        zpre[r] = make_uint4(0, 0, 0, 0);
+        if (oy < g.H && ox < g.W)
+          zpre[r] = *(const uint4*)(g.bn.z + (((int64_t)img * g.H + oy) * g.W + ox) * g.N +
+                                    n0 + 8 * sub);
+      }
+    }
     __syncthreads();                // every wave's MFMA reads of Si are done
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
@@ -493,7 +627,12 @@ __global__ __launch_bounds__(kGT) void k_conv3_lds(GemmNT g) {
       } else {
         *(uint4*)(g.y0 + row * g.N + col) = val;
       }
+      if constexpr (EM == E_BNGRAD) bacc.add(zpre[r], val);
     }
+  }
+  if constexpr (EM == E_BNGRAD) {
+    __syncthreads();  // the last tile's reads of So are done
+    bacc.flush(g.bn, (float*)&Si[0][0][0], BN / 8, n0);
   }
 
   if constexpr (EM == E_STORE) {
@@ -671,18 +810,34 @@ __global__ __launch_bounds__(kGT) void k_wgrad3_lds(GemmTN g) {
     lstore();
     __syncthreads();
     if (t + gridDim.x < ntiles) gload(t + gridDim.x);
+    // The wave's block (mi, nj) for all 9 taps: tap (dy, dx) pairs output row
+    // r of dy^T with halo row r + dy of the dx-shifted x^T.  Walking the halo
+    // rows s, each x^T fragment (s, dx) serves the three taps dy = 0..2 with
+    // output rows s - dy, and each dy^T row fragment stays in registers for
+    // the three halo rows that use it: 18 LDS reads per 72 MFMAs.
+    {
+      const int mi = (wave >> 1) & 1, nj = wave & 1;
+      const int ar = 16 * mi + (lane & 15), xr = 16 * nj + (lane & 15);
+      bf16x8 arow[kCTH];
 #pragma unroll
-    for (int r = 0; r < kCTH; ++r) {
+      for (int s = 0; s < kCIH; ++s) {
+        if (s < kCTH)
+          arow[s] = __builtin_bit_cast(
+              bf16x8, *(const uint4*)&Sa[ar][swz(ar, kCTW * s + 8 * (lane >> 4))]);
+        bf16x8 bx[3];
 #pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        const int b = wave + 4 * k, tap = b >> 2, mi = (b >> 1) & 1, nj = b & 1;
-        const int dy = tap / 3, dx = tap % 3;
-        const int ar = 16 * mi + (lane & 15), xr = 16 * nj + (lane & 15);
-        const bf16x8 av = __builtin_bit_cast(
-            bf16x8, *(const uint4*)&Sa[ar][swz(ar, kCTW * r + 8 * (lane >> 4))]);
-        const bf16x8 bv = __builtin_bit_cast(
-            bf16x8, *(const uint4*)&Sx[dx][xr][swz(xr, kCTW * (r + dy) + 8 * (lane >> 4))]);
-        acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[k], 0, 0, 0);
+        for (int dx = 0; dx < 3; ++dx)
+          bx[dx] = __builtin_bit_cast(
+              bf16x8, *(const uint4*)&Sx[dx][xr][swz(xr, kCTW * s + 8 * (lane >> 4))]);
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+          const int r = s - dy;
+          if (r < 0 || r >= kCTH) continue;
+#pragma unroll
+          for (int dx = 0; dx < 3; ++dx)
+            acc[dy * 3 + dx] =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(arow[r], bx[dx], acc[dy * 3 + dx], 0, 0, 0);
+        }
       }
     }
   }
@@ -974,21 +1129,6 @@ __global__ void k_up_t(const u16* w, u16* wt, int32_t cin, int32_t cout) {
   }
 }
 
-// 8 bf16 <-> 8 floats
-__device__ __forceinline__ void unpack8(uint4 v, float f[8]) {
-  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    f[2 * i] = __uint_as_float(w[i] << 16);
-    f[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
-  }
-}
-__device__ __forceinline__ uint4 pack8(const float f[8]) {
-  uint32_t w[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) w[i] = (uint32_t)f2bf(f[2 * i]) | ((uint32_t)f2bf(f[2 * i + 1]) << 16);
-  return make_uint4(w[0], w[1], w[2], w[3]);
-}
 
 // BN + ReLU, 8 channels per thread (C % 8 == 0).  Each block first turns the
 // per-channel sums into (mean, rstd) for all C channels in LDS, in double;
@@ -1245,41 +1385,76 @@ __global__ void k_maxpool(const u16* x, u16* y, uint8_t* idx, int32_t N, int32_t
 
 // dx = the pooled gradient routed to each window's winner, plus dadd (the
 // gradient of the same tensor from its other consumer, nullable; may be dx)
+// (with bn.z set, 256 % (C/8) == 0: each thread keeps one channel group)
 __global__ void k_maxpool_bwd(const u16* dy, const uint8_t* idx, const u16* dadd, u16* dx,
-                              int32_t N, int32_t H, int32_t W, int32_t C) {
+                              int32_t N, int32_t H, int32_t W, int32_t C, BnGrad bn) {
+  __shared__ float lds[16 * 256];
   const int32_t G = C / 8;
   const int64_t n = (int64_t)N * H * W * G;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t g = (int32_t)(i % G);
-    int64_t r = i / G;
-    const int32_t w = (int32_t)(r % W);
-    r /= W;
-    const int32_t h = (int32_t)(r % H);
-    const int32_t img = (int32_t)(r / H);
+  const bool with_bn = bn.z != nullptr;
+  BnAcc8 bacc;
+  if (with_bn) bacc.init(bn, 8 * (int32_t)(threadIdx.x % G));
+  // two chunks per iteration, every load issued before any use
+  struct In {
+    uint4 d, e, z;
+    uint2 ix;
+    uint32_t k;
+  };
+  const bool small = n <= INT32_MAX;  // 32-bit index arithmetic
+  auto fetch = [&](int64_t i, In& v) {
+    int32_t g, w, h, img;
+    if (small) {
+      const uint32_t i32 = (uint32_t)i, r0 = i32 / (uint32_t)G, r1 = r0 / (uint32_t)W;
+      g = (int32_t)(i32 - r0 * (uint32_t)G);
+      w = (int32_t)(r0 - r1 * (uint32_t)W);
+      img = (int32_t)(r1 / (uint32_t)H);
+      h = (int32_t)(r1 - (uint32_t)img * (uint32_t)H);
+    } else {
+      g = (int32_t)(i % G);
+      int64_t r = i / G;
+      w = (int32_t)(r % W);
+      r /= W;
+      h = (int32_t)(r % H);
+      img = (int32_t)(r / H);
+    }
     const int64_t o = (((int64_t)img * (H / 2) + h / 2) * (W / 2) + w / 2) * G + g;
-    const uint32_t k = (uint32_t)((h & 1) * 2 + (w & 1));
-    const uint4 d = ((const uint4*)dy)[o];
-    const uint2 ix = ((const uint2*)idx)[o];
-    const uint32_t dw[4] = {d.x, d.y, d.z, d.w};
+    v.k = (uint32_t)((h & 1) * 2 + (w & 1));
+    v.d = ((const uint4*)dy)[o];
+    v.ix = ((const uint2*)idx)[o];
+    if (dadd) v.e = ((const uint4*)dadd)[i];
+    if (with_bn) v.z = ((const uint4*)bn.z)[i];
+  };
+  auto finish = [&](int64_t i, const In& v) {
+    const uint32_t dw[4] = {v.d.x, v.d.y, v.d.z, v.d.w};
     uint32_t out[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const uint32_t word = q < 2 ? ix.x : ix.y;
+      const uint32_t word = q < 2 ? v.ix.x : v.ix.y;
       const uint32_t lo = (word >> (16 * (q & 1))) & 0xffu, hi = (word >> (16 * (q & 1) + 8)) & 0xffu;
-      out[q] = (lo == k ? (dw[q] & 0xffffu) : 0u) | (hi == k ? (dw[q] & 0xffff0000u) : 0u);
+      out[q] = (lo == v.k ? (dw[q] & 0xffffu) : 0u) | (hi == v.k ? (dw[q] & 0xffff0000u) : 0u);
     }
     uint4 res = make_uint4(out[0], out[1], out[2], out[3]);
     if (dadd) {
       float f[8], e[8];
       unpack8(res, f);
-      unpack8(((const uint4*)dadd)[i], e);
+      unpack8(v.e, e);
 #pragma unroll
       for (int j = 0; j < 8; ++j) f[j] += e[j];
       res = pack8(f);
     }
     ((uint4*)dx)[i] = res;
+    if (with_bn) bacc.add(v.z, res);
+  };
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += 2 * stride) {
+    In va, vb;
+    fetch(i, va);
+    const bool two = i + stride < n;
+    if (two) fetch(i + stride, vb);
+    finish(i, va);
+    if (two) finish(i + stride, vb);
   }
+  if (with_bn) bacc.flush(bn, lds, G, 0);
 }
 
 __global__ void k_head(const u16* x, const float* w, const float* b, float* logits, int64_t P,
@@ -1337,8 +1512,8 @@ __global__ void k_softmax_xent(const float* logits, const uint8_t* labels, float
 // (256 % (C/8) == 0).  Per row it writes dx = dlogits w for its 8 channels and
 // adds dlogits (x) x into 24 partial sums (and dlogits into 3 for the bias);
 // partial sums meet in LDS, then one atomic per output per block.
-__global__ void k_head_bwd(const u16* x, const float* w, const float* dl, const float* dscale,
-                           u16* dx, float* dw, float* db, int64_t P, int32_t C) {
+__global__ __launch_bounds__(256) void k_head_bwd(const u16* x, const float* w, const float* dl, const float* dscale,
+                           u16* dx, float* dw, float* db, int64_t P, int32_t C, BnGrad bn) {
   __shared__ float s[27][256];
   const int t = threadIdx.x, G = C / 8;
   const int g = t % G, r0 = t / G, rstep = 256 / G;
@@ -1352,10 +1527,24 @@ __global__ void k_head_bwd(const u16* x, const float* w, const float* dl, const 
       a[k][j] = 0.f;
     }
   const float sc = dscale ? *dscale : 1.f;
-  auto one = [&](int64_t p, const uint4 xin) {
-    const float d0 = dl[3 * p] * sc, d1 = dl[3 * p + 1] * sc, d2 = dl[3 * p + 2] * sc;
+  const bool with_bn = bn.z != nullptr;
+  BnAcc8 bacc;
+  if (with_bn) bacc.init(bn, c0);
+  struct Row {
+    uint4 x, z;
+    float d0, d1, d2;
+  };
+  auto fetch = [&](int64_t p, Row& v) {
+    v.x = ((const uint4*)x)[p * G + g];
+    v.d0 = dl[3 * p];
+    v.d1 = dl[3 * p + 1];
+    v.d2 = dl[3 * p + 2];
+    if (with_bn) v.z = ((const uint4*)bn.z)[p * G + g];
+  };
+  auto one = [&](int64_t p, const Row& v) {
+    const float d0 = v.d0 * sc, d1 = v.d1 * sc, d2 = v.d2 * sc;
     float f[8], o[8];
-    unpack8(xin, f);
+    unpack8(v.x, f);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       o[j] = d0 * wk[0][j] + d1 * wk[1][j] + d2 * wk[2][j];
@@ -1366,19 +1555,26 @@ __global__ void k_head_bwd(const u16* x, const float* w, const float* dl, const 
     bsum[0] += d0;
     bsum[1] += d1;
     bsum[2] += d2;
-    ((uint4*)dx)[p * G + g] = pack8(o);
+    const uint4 res = pack8(o);
+    ((uint4*)dx)[p * G + g] = res;
+    if (with_bn) bacc.add(v.z, res);
   };
   const int64_t rows_per_block = (P + gridDim.x - 1) / gridDim.x;
   const int64_t rb = (int64_t)blockIdx.x * rows_per_block;
   const int64_t re = min(P, rb + rows_per_block);
-  const uint4* xv = (const uint4*)x;
   int64_t p = rb + r0;
   for (; p + rstep < re; p += 2 * rstep) {
-    const uint4 xa = xv[p * G + g], xb = xv[(p + rstep) * G + g];
-    one(p, xa);
-    one(p + rstep, xb);
+    Row a, b;
+    fetch(p, a);
+    fetch(p + rstep, b);
+    one(p, a);
+    one(p + rstep, b);
   }
-  if (p < re) one(p, xv[p * G + g]);
+  if (p < re) {
+    Row a;
+    fetch(p, a);
+    one(p, a);
+  }
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
 #pragma unroll
@@ -1398,6 +1594,10 @@ __global__ void k_head_bwd(const u16* x, const float* w, const float* dl, const 
       for (int q = 0; q < 256; q += G) e += s[24 + k][q];
       atomicAdd(&db[k], e);
     }
+  }
+  if (with_bn) {
+    __syncthreads();  // the head sums' reads of s are done
+    bacc.flush(bn, &s[0][0], G, 0);
   }
 }
 
@@ -1562,6 +1762,15 @@ __global__ void k_bn_fold(BnList L, float eps) {
 // Reductions that end in global atomics run at most this many blocks: atomics
 // on one address serialise, so their count, not the bytes read, would bound them.
 constexpr int kRedBlocks = 1024;
+// The batch-norm backward sums add 2*C atomics per block onto only 2*C
+// addresses: fewer, longer blocks measured faster there.
+#ifndef SIL_BNRED_BLOCKS
+#define SIL_BNRED_BLOCKS 256
+#endif
+constexpr int kBnRedBlocks = SIL_BNRED_BLOCKS;
+#ifndef SIL_BNRELU_BLOCKS
+#define SIL_BNRELU_BLOCKS 2048
+#endif
 
 int grid_for(int64_t n, int block = 256) {
   int64_t g = (n + block - 1) / block;
@@ -1608,7 +1817,8 @@ void launch_nt_tile(const GemmNT& g, hipStream_t st) {
 template <int AM, int EM>
 int launch_nt(const GemmNT& g, hipStream_t st) {
   (void)hipGetLastError();
-  if (g.N % 128 == 0)
+  // (the 128-wide tile would hold the batch-norm sums' operands in too many registers)
+  if (g.N % 128 == 0 && EM != E_BNGRAD)
     launch_nt_tile<AM, EM, 2, 2, 4>(g, st);
   else if (g.N % 64 == 0)
     launch_nt_tile<AM, EM, 2, 2, 2>(g, st);
@@ -1683,6 +1893,18 @@ int launch_tn(GemmTN g, hipStream_t st) {
 
 bool ok_dims(int32_t N, int32_t H, int32_t W) { return N > 0 && H > 0 && W > 0; }
 
+// The device form of a caller's batch-norm backward request (nullptr: none).
+// False when the request is malformed or its channel count is not C.
+bool bn_grad_of(const sil_unet_bn_grad* p, int32_t C, BnGrad* out) {
+  *out = BnGrad{};
+  if (!p) return true;
+  if (!p->z || !p->mr || !p->gamma || !p->beta || !p->sum_d || !p->sum_dxhat || p->C != C ||
+      C < 8 || C % 8 || 256 % (C / 8))
+    return false;
+  *out = BnGrad{(const u16*)p->z, p->mr, p->gamma, p->beta, p->sum_d, p->sum_dxhat, p->C};
+  return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1736,10 +1958,13 @@ int sil_unet_conv3x3_affine_relu(const void* x0, int32_t c0, const void* x1, int
 }
 
 int sil_unet_conv3x3_dgrad(const void* dy, int32_t cout, const void* wt, void* dx0, int32_t c0,
-                           void* dx1, int32_t c1, int32_t N, int32_t H, int32_t W, void* stream) {
+                           void* dx1, int32_t c1, int32_t N, int32_t H, int32_t W,
+                           const sil_unet_bn_grad* bn, void* stream) {
   if (!dy || !wt || !dx0 || (c1 > 0 && !dx1) || !ok_dims(N, H, W)) return SIL_EINVAL;
   if (cout <= 0 || cout % 8 || c0 <= 0 || c0 % 8 || c1 < 0 || c1 % 8) return SIL_EINVAL;
+  if (bn && c1 > 0) return SIL_EINVAL;
   GemmNT g{};
+  if (!bn_grad_of(bn, c0, &g.bn)) return SIL_EINVAL;
   g.M = N * H * W;
   g.N = c0 + c1;
   g.K = 9 * cout;
@@ -1753,6 +1978,11 @@ int sil_unet_conv3x3_dgrad(const void* dy, int32_t cout, const void* wt, void* d
   g.y1 = (u16*)dx1;
   g.split = c1 > 0 ? c0 : c0 + c1;
   hipStream_t st = (hipStream_t)stream;
+  if (bn) {
+    if (conv_lds_ok(g)) return launch_conv_lds<E_BNGRAD>(g, st);
+    if (cout % kBK == 0) return launch_nt<A_IM2COL32, E_BNGRAD>(g, st);
+    return launch_nt<A_IM2COL, E_BNGRAD>(g, st);
+  }
   if (conv_lds_ok(g))
     return c1 > 0 ? launch_conv_lds<E_SPLIT>(g, st) : launch_conv_lds<E_STORE>(g, st);
   if (cout % kBK == 0)
@@ -1817,10 +2047,12 @@ int sil_unet_upconv(const void* x, const void* w, const float* b, void* y, int32
 }
 
 int sil_unet_upconv_dgrad(const void* dy, const void* wt, void* dx, int32_t N, int32_t H,
-                          int32_t W, int32_t cin, int32_t cout, void* stream) {
+                          int32_t W, int32_t cin, int32_t cout, const sil_unet_bn_grad* bn,
+                          void* stream) {
   if (!dy || !wt || !dx || !ok_dims(N, H, W) || cin <= 0 || cin % 8 || cout <= 0 || cout % 8)
     return SIL_EINVAL;
   GemmNT g{};
+  if (!bn_grad_of(bn, cin, &g.bn)) return SIL_EINVAL;
   g.M = N * H * W;
   g.N = cin;
   g.K = 4 * cout;
@@ -1830,6 +2062,7 @@ int sil_unet_upconv_dgrad(const void* dy, const void* wt, void* dx, int32_t N, i
   g.W = W;
   g.b = (const u16*)wt;
   g.y0 = (u16*)dx;
+  if (bn) return launch_nt<A_UPGATHER, E_BNGRAD>(g, (hipStream_t)stream);
   return launch_nt<A_UPGATHER, E_STORE>(g, (hipStream_t)stream);
 }
 
@@ -1870,7 +2103,7 @@ int sil_unet_bn_relu(const void* z, const float* stats, const float* gamma, cons
   (void)hipGetLastError();
   const int64_t n = P * C;
   // every block derives (mean, rstd) itself: a capped grid keeps that cheap
-  hipLaunchKernelGGL(k_bn_relu, dim3(std::min(grid_for(n / 8), 2048)), dim3(256), 0,
+  hipLaunchKernelGGL(k_bn_relu, dim3(std::min(grid_for(n / 8), SIL_BNRELU_BLOCKS)), dim3(256), 0,
                      (hipStream_t)stream, (const u16*)z, stats, count, eps, gamma, beta,
                      (u16*)out, mr, n, C);
   return done();
@@ -1912,13 +2145,28 @@ int sil_unet_bn_relu_bwd(const void* dout, const void* z, const float* mr, const
   float* r1 = red ? red : dbeta;
   float* r2 = red ? red + C : dgamma;
   if (red) hipLaunchKernelGGL(k_fill, dim3(1), dim3(256), 0, st, red, (int64_t)2 * C, 0.f);
-  hipLaunchKernelGGL(k_bn_bwd_reduce, dim3(std::min(grid_for(P * (C / 8) / 2048 + 1, 1), kRedBlocks)), dim3(256), 0, st,
+  hipLaunchKernelGGL(k_bn_bwd_reduce, dim3(std::min(grid_for(P * (C / 8) / 2048 + 1, 1), kBnRedBlocks)), dim3(256), 0, st,
                      (const u16*)dout, (const u16*)z, mr, gamma, beta, r1, r2, P, C);
   const int64_t n = P * C;
   hipLaunchKernelGGL(k_bn_bwd_apply, dim3(grid_for(n / 8)), dim3(256), 0, st, (const u16*)dout,
                      (const u16*)z, mr, gamma, beta, r1, r2, (u16*)dz, n, C, 1.f / (float)P);
   if (red)
     hipLaunchKernelGGL(k_add_pair, dim3(1), dim3(256), 0, st, dbeta, dgamma, red, C);
+  return done();
+}
+
+int sil_unet_bn_relu_bwd_apply(const void* dout, const void* z, const float* mr,
+                               const float* gamma, const float* beta, const float* sum_d,
+                               const float* sum_dxhat, void* dz, int64_t P, int32_t C,
+                               void* stream) {
+  if (!dout || !z || !mr || !gamma || !beta || !sum_d || !sum_dxhat || !dz || P <= 0 || C < 8 ||
+      C > 256 || 256 % C)
+    return SIL_EINVAL;
+  (void)hipGetLastError();
+  const int64_t n = P * C;
+  hipLaunchKernelGGL(k_bn_bwd_apply, dim3(grid_for(n / 8)), dim3(256), 0, (hipStream_t)stream,
+                     (const u16*)dout, (const u16*)z, mr, gamma, beta, sum_d, sum_dxhat, (u16*)dz,
+                     n, C, 1.f / (float)P);
   return done();
 }
 
@@ -1934,13 +2182,18 @@ int sil_unet_maxpool(const void* x, void* y, uint8_t* idx, int32_t N, int32_t H,
 }
 
 int sil_unet_maxpool_bwd(const void* dy, const uint8_t* idx, const void* dadd, void* dx,
-                         int32_t N, int32_t H, int32_t W, int32_t C, void* stream) {
+                         int32_t N, int32_t H, int32_t W, int32_t C, const sil_unet_bn_grad* bn,
+                         void* stream) {
   if (!dy || !idx || !dx || !ok_dims(N, H, W) || H % 2 || W % 2 || C <= 0 || C % 8)
     return SIL_EINVAL;
+  BnGrad b;
+  if (!bn_grad_of(bn, C, &b)) return SIL_EINVAL;
   (void)hipGetLastError();
   const int64_t n = (int64_t)N * H * W * (C / 8);
-  hipLaunchKernelGGL(k_maxpool_bwd, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream,
-                     (const u16*)dy, idx, (const u16*)dadd, (u16*)dx, N, H, W, C);
+  // with the batch-norm sums: a bounded grid, so that each block's atomics cover more pixels
+  const int grid = bn ? std::min(grid_for(n), kRedBlocks) : grid_for(n);
+  hipLaunchKernelGGL(k_maxpool_bwd, dim3(grid), dim3(256), 0, (hipStream_t)stream,
+                     (const u16*)dy, idx, (const u16*)dadd, (u16*)dx, N, H, W, C, b);
   return done();
 }
 
@@ -1963,13 +2216,16 @@ int sil_unet_softmax_xent(const float* logits, const uint8_t* labels, float* los
 }
 
 int sil_unet_head_bwd(const void* x, const float* w, const float* dlogits, const float* dscale,
-                      void* dx, float* dw, float* db, int64_t P, int32_t C, void* stream) {
+                      void* dx, float* dw, float* db, int64_t P, int32_t C,
+                      const sil_unet_bn_grad* bn, void* stream) {
   if (!x || !w || !dlogits || !dx || !dw || !db || P <= 0 || C < 8 || C > 256 || 256 % C)
     return SIL_EINVAL;
+  BnGrad b;
+  if (!bn_grad_of(bn, C, &b)) return SIL_EINVAL;
   (void)hipGetLastError();
   hipLaunchKernelGGL(k_head_bwd, dim3(std::min(grid_for(P * (C / 8) / 2048 + 1, 1), kRedBlocks)),
                      dim3(256), 0, (hipStream_t)stream, (const u16*)x, w, dlogits, dscale,
-                     (u16*)dx, dw, db, P, C);
+                     (u16*)dx, dw, db, P, C, b);
   return done();
 }
 

@@ -36,22 +36,23 @@ def _lib():
             "sil_unet_conv3x3": [vp, i32, vp, i32, vp, vp, vp, i32, i32, i32, i32, vp],
             "sil_unet_conv3x3_affine_relu": [vp, i32, vp, i32, vp, vp, vp, vp, i32, i32, i32,
                                              i32, vp],
-            "sil_unet_conv3x3_dgrad": [vp, i32, vp, vp, i32, vp, i32, i32, i32, i32, vp],
+            "sil_unet_conv3x3_dgrad": [vp, i32, vp, vp, i32, vp, i32, i32, i32, i32, vp, vp],
             "sil_unet_conv3x3_wgrad": [vp, i32, vp, i32, vp, i32, vp, i32, i32, i32, vp],
             "sil_unet_flip3x3": [vp, vp, i32, i32, vp],
             "sil_unet_upconv": [vp, vp, vp, vp, i32, i32, i32, i32, i32, vp],
-            "sil_unet_upconv_dgrad": [vp, vp, vp, i32, i32, i32, i32, i32, vp],
+            "sil_unet_upconv_dgrad": [vp, vp, vp, i32, i32, i32, i32, i32, vp, vp],
             "sil_unet_upconv_wgrad": [vp, vp, vp, vp, i32, i32, i32, i32, i32, vp],
             "sil_unet_up_t": [vp, vp, i32, i32, vp],
             "sil_unet_bn_relu": [vp, vp, vp, vp, f32, i64, vp, vp, i64, i32, vp],
             "sil_unet_bn_relu_bwd": [vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, i32, vp],
+            "sil_unet_bn_relu_bwd_apply": [vp, vp, vp, vp, vp, vp, vp, vp, i64, i32, vp],
             "sil_unet_affine_relu": [vp, vp, vp, vp, i64, i32, vp],
             "sil_unet_scatter_argmax": [vp, vp, i32, i32, vp, i32, i32, i64, vp],
             "sil_unet_maxpool": [vp, vp, vp, i32, i32, i32, i32, vp],
-            "sil_unet_maxpool_bwd": [vp, vp, vp, vp, i32, i32, i32, i32, vp],
+            "sil_unet_maxpool_bwd": [vp, vp, vp, vp, i32, i32, i32, i32, vp, vp],
             "sil_unet_head": [vp, vp, vp, vp, i64, i32, vp],
             "sil_unet_softmax_xent": [vp, vp, vp, vp, f32, i64, vp],
-            "sil_unet_head_bwd": [vp, vp, vp, vp, vp, vp, vp, i64, i32, vp],
+            "sil_unet_head_bwd": [vp, vp, vp, vp, vp, vp, vp, i64, i32, vp, vp],
             "sil_unet_argmax": [vp, vp, i64, vp],
             "sil_unet_chips_input": [vp, i32, i32, i64, vp, i32, i32, f32, vp, vp],
             "sil_unet_adam": [vp, vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp],
@@ -107,6 +108,39 @@ class _BnLayer(ctypes.Structure):
     _fields_ = [("C", ctypes.c_int32), ("mr", ctypes.c_void_p), ("running_mean", ctypes.c_void_p),
                 ("running_var", ctypes.c_void_p), ("gamma", ctypes.c_void_p),
                 ("beta", ctypes.c_void_p), ("scale", ctypes.c_void_p), ("shift", ctypes.c_void_p)]
+
+
+class _BnGrad(ctypes.Structure):
+    _fields_ = [("z", ctypes.c_void_p), ("mr", ctypes.c_void_p), ("gamma", ctypes.c_void_p),
+                ("beta", ctypes.c_void_p), ("sum_d", ctypes.c_void_p),
+                ("sum_dxhat", ctypes.c_void_p), ("C", ctypes.c_int32)]
+
+
+class _BnSlot:
+    """Links a conv + batch-norm + ReLU layer to the one consumer of its
+    output.  The layer's forward records its batch-norm input and statistics
+    here; the consumer's backward, while it writes the layer's output
+    gradient, also forms the layer's batch-norm sums (the beta and gamma
+    gradients) in `sums`; the layer's backward then only applies them."""
+    __slots__ = ("bn", "sums")
+
+    def __init__(self):
+        self.bn = None
+        self.sums = None
+
+    def request(self, pool):
+        """(address of a sil_unet_bn_grad, the struct to keep alive), or
+        (None, None) when the layer recorded nothing."""
+        if self.bn is None:
+            return None, None
+        z, mr, gamma, beta = self.bn
+        C = z.shape[-1]
+        s_d = _zeros((C,), z.device, pool)
+        s_x = _zeros((C,), z.device, pool)
+        self.sums = (s_d, s_x)
+        req = _BnGrad(z.data_ptr(), mr.data_ptr(), gamma.data_ptr(), beta.data_ptr(),
+                      s_d.data_ptr(), s_x.data_ptr(), C)
+        return ctypes.addressof(req), req
 
 
 def _array(ctype, items):
@@ -165,8 +199,12 @@ class Conv3x3BNReLU(torch.autograd.Function):
     from w for this pass (UNet.prepare_weights)."""
 
     @staticmethod
-    def forward(ctx, x0, x1, w, gamma, beta, mr=None, pool=None, wb=None, wt=None):
-        """mr (optional [2, cout] fp32) receives the batch (mean, rstd)."""
+    def forward(ctx, x0, x1, w, gamma, beta, mr=None, pool=None, wb=None, wt=None, slot=None,
+                in_slot=None):
+        """mr (optional [2, cout] fp32) receives the batch (mean, rstd).  slot
+        (optional _BnSlot): this layer's link to the one consumer of its
+        output; in_slot: the link of the layer that produced x0, when this
+        layer is its only consumer."""
         N, H, W, c0 = x0.shape
         c1 = 0 if x1 is None else x1.shape[3]
         cout = w.shape[0]
@@ -186,6 +224,9 @@ class Conv3x3BNReLU(torch.autograd.Function):
         ctx.save_for_backward(x0, x1 if x1 is not None else torch.empty(0), wb, z, mr, gamma, beta)
         ctx.wt = wt
         ctx.has_x1 = x1 is not None
+        ctx.slot, ctx.in_slot = slot, in_slot
+        if slot is not None:
+            slot.bn = (z, mr, gamma, beta)
         return out
 
     @staticmethod
@@ -198,11 +239,17 @@ class Conv3x3BNReLU(torch.autograd.Function):
         cout = wb.shape[0]
         P = N * H * W
         dz = torch.empty_like(z)
-        # fresh zeroed gradients: the batch-norm sums are formed in them directly
-        dgamma = _zeros((cout,), z.device, ctx.pool)
-        dbeta = _zeros((cout,), z.device, ctx.pool)
-        _call("sil_unet_bn_relu_bwd", _p(dout), _p(z), _p(mr), _p(gamma), _p(beta), _p(dz),
-              _p(dgamma), _p(dbeta), None, P, cout, _s())
+        if ctx.slot is not None and ctx.slot.sums is not None:
+            # the consumer formed the batch-norm sums while writing dout
+            dbeta, dgamma = ctx.slot.sums
+            _call("sil_unet_bn_relu_bwd_apply", _p(dout), _p(z), _p(mr), _p(gamma), _p(beta),
+                  _p(dbeta), _p(dgamma), _p(dz), P, cout, _s())
+        else:
+            # fresh zeroed gradients: the batch-norm sums are formed in them directly
+            dgamma = _zeros((cout,), z.device, ctx.pool)
+            dbeta = _zeros((cout,), z.device, ctx.pool)
+            _call("sil_unet_bn_relu_bwd", _p(dout), _p(z), _p(mr), _p(gamma), _p(beta), _p(dz),
+                  _p(dgamma), _p(dbeta), None, P, cout, _s())
         dw = _zeros(wb.shape, z.device, ctx.pool)
         _call("sil_unet_conv3x3_wgrad", _p(dz), cout, _p(x0), c0, _p(x1), c1, _p(dw), N, H, W,
               _s())
@@ -214,9 +261,12 @@ class Conv3x3BNReLU(torch.autograd.Function):
                 _call("sil_unet_flip3x3", _p(wb), _p(wt), cout, c0 + c1, _s())
             dx0 = torch.empty_like(x0)
             dx1 = torch.empty_like(x1) if x1 is not None else None
+            req, keep = (None, None)
+            if ctx.in_slot is not None and x1 is None:
+                req, keep = ctx.in_slot.request(ctx.pool)
             _call("sil_unet_conv3x3_dgrad", _p(dz), cout, _p(wt), _p(dx0), c0, _p(dx1), c1, N, H,
-                  W, _s())
-        return dx0, dx1, dw, dgamma, dbeta, None, None, None, None
+                  W, req, _s())
+        return dx0, dx1, dw, dgamma, dbeta, None, None, None, None, None, None
 
 
 class MaxPool2(torch.autograd.Function):
@@ -226,13 +276,16 @@ class MaxPool2(torch.autograd.Function):
     one kernel."""
 
     @staticmethod
-    def forward(ctx, x):
+    def forward(ctx, x, in_slot=None, pool=None):
+        """in_slot (optional _BnSlot): the link of the layer that produced x;
+        its batch-norm sums are formed here in the backward pass."""
         N, H, W, C = x.shape
         y = torch.empty((N, H // 2, W // 2, C), dtype=x.dtype, device=x.device)
         idx = torch.empty((N, H // 2, W // 2, C), dtype=torch.uint8, device=x.device)
         _call("sil_unet_maxpool", _p(x), _p(y), _p(idx), N, H, W, C, _s())
         ctx.save_for_backward(idx)
         ctx.shape = x.shape
+        ctx.in_slot, ctx.pool = in_slot, pool
         ctx.set_materialize_grads(False)
         return y, x
 
@@ -241,12 +294,13 @@ class MaxPool2(torch.autograd.Function):
         (idx,) = ctx.saved_tensors
         N, H, W, C = ctx.shape
         if dy is None:
-            return dskip
+            return dskip, None, None
         dx = torch.empty(ctx.shape, dtype=dy.dtype, device=dy.device)
         dadd = None if dskip is None else dskip.contiguous()
+        req, keep = (None, None) if ctx.in_slot is None else ctx.in_slot.request(ctx.pool)
         _call("sil_unet_maxpool_bwd", _p(dy.contiguous()), _p(idx), _p(dadd), _p(dx), N, H, W, C,
-              _s())
-        return dx
+              req, _s())
+        return dx, None, None
 
 
 class UpConv2(torch.autograd.Function):
@@ -255,8 +309,9 @@ class UpConv2(torch.autograd.Function):
     for this pass (UNet.prepare_weights)."""
 
     @staticmethod
-    def forward(ctx, x, w, b, pool=None, wb=None, wt=None):
+    def forward(ctx, x, w, b, pool=None, wb=None, wt=None, in_slot=None):
         ctx.pool = pool
+        ctx.in_slot = in_slot
         N, H, W, cin = x.shape
         cout = w.shape[2]
         if wb is None:
@@ -281,16 +336,18 @@ class UpConv2(torch.autograd.Function):
             wt = torch.empty((cin, 2, 2, cout), dtype=torch.bfloat16, device=x.device)
             _call("sil_unet_up_t", _p(wb), _p(wt), cin, cout, _s())
         dx = torch.empty_like(x)
-        _call("sil_unet_upconv_dgrad", _p(dy), _p(wt), _p(dx), N, H, W, cin, cout, _s())
-        return dx, dw, db, None, None, None
+        req, keep = (None, None) if ctx.in_slot is None else ctx.in_slot.request(ctx.pool)
+        _call("sil_unet_upconv_dgrad", _p(dy), _p(wt), _p(dx), N, H, W, cin, cout, req, _s())
+        return dx, dw, db, None, None, None, None
 
 
 class HeadXent(torch.autograd.Function):
     """Mean softmax cross-entropy of the 1x1 head; returns (loss, logits)."""
 
     @staticmethod
-    def forward(ctx, x, w, b, labels, pool=None):
+    def forward(ctx, x, w, b, labels, pool=None, in_slot=None):
         N, H, W, C = x.shape
+        ctx.in_slot = in_slot
         P = N * H * W
         logits = torch.empty((P, 3), dtype=torch.float32, device=x.device)
         _call("sil_unet_head", _p(x), _p(w), _p(b), _p(logits), P, C, _s())
@@ -314,13 +371,14 @@ class HeadXent(torch.autograd.Function):
         db = _zeros((3,), x.device, ctx.pool)
         if dloss is None:
             dx.zero_()
-            return dx, dw, db, None, None
+            return dx, dw, db, None, None, None
         # dlogits carries the 1/P of the mean; the kernel scales it by the
         # incoming gradient on the device (no host synchronisation)
         dl = dloss.contiguous()
+        req, keep = (None, None) if ctx.in_slot is None else ctx.in_slot.request(ctx.pool)
         _call("sil_unet_head_bwd", _p(x), _p(w), _p(dlogits), _p(dl), _p(dx), _p(dw), _p(db), P, C,
-              _s())
-        return dx, dw, db, None, None
+              req, _s())
+        return dx, dw, db, None, None, None
 
 
 def layer_specs(widths: Sequence[int], in_ch: int = IN_CH):
@@ -419,22 +477,33 @@ class UNet:
         skips = []
         h = x
         L = len(self.widths)
+        # Every conv + BN + ReLU output has one consumer (the next conv, the
+        # pooling layer, an up-convolution or the head): the consumer's
+        # backward forms the layer's batch-norm sums (slot links).
+        link = None  # the link of the layer that produced h
 
-        def cbr(h, skip, n):
-            return Conv3x3BNReLU.apply(h, skip, P[n + ".w"], P[n + ".gamma"], P[n + ".beta"],
-                                       self.batch_mr[n], self.pool, self.wb[n], self.wt[n])
+        def cbr(h, skip, n, in_slot):
+            slot = _BnSlot()
+            out = Conv3x3BNReLU.apply(h, skip, P[n + ".w"], P[n + ".gamma"], P[n + ".beta"],
+                                      self.batch_mr[n], self.pool, self.wb[n], self.wt[n], slot,
+                                      in_slot)
+            return out, slot
 
         for i in range(L):
             name = f"enc{i}" if i < L - 1 else "mid"
-            h = cbr(cbr(h, None, name + ".conv0"), None, name + ".conv1")
+            h, link = cbr(h, None, name + ".conv0", link)
+            h, link = cbr(h, None, name + ".conv1", link)
             if i < L - 1:
-                h, skip = MaxPool2.apply(h)
+                h, skip = MaxPool2.apply(h, link, self.pool)
                 skips.append(skip)
+                link = None
         for i in reversed(range(L - 1)):
             n = f"dec{i}.up"
-            up = UpConv2.apply(h, P[n + ".w"], P[n + ".b"], self.pool, self.wb[n], self.wt[n])
-            h = cbr(cbr(up, skips[i], f"dec{i}.conv0"), None, f"dec{i}.conv1")
-        return HeadXent.apply(h, P["head.w"], P["head.b"], labels, self.pool)
+            up = UpConv2.apply(h, P[n + ".w"], P[n + ".b"], self.pool, self.wb[n], self.wt[n],
+                               link)
+            h, link = cbr(up, skips[i], f"dec{i}.conv0", None)
+            h, link = cbr(h, None, f"dec{i}.conv1", link)
+        return HeadXent.apply(h, P["head.w"], P["head.b"], labels, self.pool, link)
 
     def backward(self, loss: torch.Tensor):
         """loss.backward() with a seed gradient of 1 kept on the device, so that

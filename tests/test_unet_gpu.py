@@ -106,7 +106,7 @@ def test_conv3x3_forward_and_gradients(un, N, H, W, c0, c1, cout):
     dx0 = torch.empty((N, H, W, c0), dtype=torch.bfloat16, device="cuda")
     dx1 = torch.empty((N, H, W, c1), dtype=torch.bfloat16, device="cuda") if c1 else None
     un._call("sil_unet_conv3x3_dgrad", un._p(dyc), cout, un._p(wt), un._p(dx0), c0, un._p(dx1),
-             c1, N, H, W, un._s())
+             c1, N, H, W, None, un._s())
     dw = torch.zeros((cout, 3, 3, c0 + c1), device="cuda")
     un._call("sil_unet_conv3x3_wgrad", un._p(dyc), cout, un._p(x0c), c0, un._p(x1c), c1,
              un._p(dw), N, H, W, un._s())
@@ -182,7 +182,7 @@ def test_upconv_forward_and_gradients(un, N, H, W, cin, cout):
     un._call("sil_unet_up_t", un._p(wc), un._p(wt), cin, cout, un._s())
     dx = torch.empty_like(xc)
     un._call("sil_unet_upconv_dgrad", un._p(dyc), un._p(wt), un._p(dx), N, H, W, cin, cout,
-             un._s())
+             None, un._s())
     dw = torch.zeros((2, 2, cout, cin), device="cuda")
     db = torch.zeros((cout,), device="cuda")
     un._call("sil_unet_upconv_wgrad", un._p(xc), un._p(dyc), un._p(dw), un._p(db), N, H, W, cin,

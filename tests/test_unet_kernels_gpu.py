@@ -150,12 +150,13 @@ def test_maxpool_forward_and_backward_with_ties(un):
     dy = _bf((N, H // 2, W // 2, C), g)
     dyc = dy.cuda()
     dx = torch.empty((N, H, W, C), dtype=torch.bfloat16, device="cuda")
-    un._call("sil_unet_maxpool_bwd", un._p(dyc), un._p(idx), None, un._p(dx), N, H, W, C, un._s())
+    un._call("sil_unet_maxpool_bwd", un._p(dyc), un._p(idx), None, un._p(dx), N, H, W, C, None,
+             un._s())
     # with the skip connection's gradient added in the same kernel, in place
     dskip = _bf((N, H, W, C), g)
     dsum = dskip.cuda()
     un._call("sil_unet_maxpool_bwd", un._p(dyc), un._p(idx), un._p(dsum), un._p(dsum), N, H, W, C,
-             un._s())
+             None, un._s())
     torch.cuda.synchronize()
     # window positions in row-major order; the first maximum wins
     win = torch.stack([x[:, 0::2, 0::2], x[:, 0::2, 1::2], x[:, 1::2, 0::2], x[:, 1::2, 1::2]])
@@ -188,7 +189,7 @@ def test_head_forward_and_backward(un, P, C):
     # the gradient arriving at the loss scales dlogits on the device
     dscale = torch.tensor([1.5], device="cuda")
     un._call("sil_unet_head_bwd", un._p(xc), un._p(wc), un._p(dlc), un._p(dscale), un._p(dx),
-             un._p(dw), un._p(db), P, C, un._s())
+             un._p(dw), un._p(db), P, C, None, un._s())
     torch.cuda.synchronize()
     xd, wd, dld = x.double(), w.double(), 1.5 * dl.double()
     ref = xd @ wd.T + b.double()
@@ -420,3 +421,156 @@ def test_bn_running_statistics_and_fold(un):
         shift = beta.double() - rmg * scale
         _check(sc, scale, 8 * U32 * scale.abs(), f"scale[{k}]")
         _check(sh, shift, 8 * U32 * (beta.double().abs() + (rmg * scale).abs()), f"shift[{k}]")
+
+
+def _bn_layer(g, P, C):
+    """A batch-norm layer's saved state: z [P, C] bf16, mr, gamma, beta."""
+    z = _bf((P, C), g, 2.0)
+    mean = (torch.randn(C, generator=g) * 0.3).float()
+    rstd = (torch.rand(C, generator=g) + 0.5).float()
+    gamma = torch.rand(C, generator=g) + 0.5
+    beta = torch.randn(C, generator=g) * 0.5
+    return z, torch.stack([mean, rstd]), gamma, beta
+
+
+def _bn_sums_ref(dout, z, mr, gamma, beta):
+    """float64 sums of the batch-norm backward and their bounds (as in
+    test_bn_relu_backward): d = dout where the ReLU passed."""
+    zh = (z.double() - mr[0].double()) * mr[1].double()
+    y = zh * gamma.double() + beta.double()
+    amb = y.abs() <= 8 * U32 * ((zh * gamma.double()).abs() + beta.double().abs())
+    zero = torch.zeros(()).double()
+    d = torch.where(y > 0, dout.double(), zero)
+    da = torch.where(amb, dout.double().abs(), zero)
+    P = d.shape[0]
+    s1, s2 = d.sum(0), (d * zh).sum(0)
+    e1 = P * U32 * d.abs().sum(0) + da.sum(0)
+    e2 = P * U32 * (d * zh).abs().sum(0) + (da * zh.abs()).sum(0)
+    return s1, s2, e1, e2, zh, d, amb
+
+
+class _Req:
+    """A sil_unet_bn_grad request on device copies of a layer's state."""
+
+    def __init__(self, un, z, mr, gamma, beta):
+        C = z.shape[-1]
+        self.t = [z.cuda(), mr.cuda(), gamma.cuda(), beta.cuda()]
+        self.s_d = torch.zeros(C, device="cuda")
+        self.s_x = torch.zeros(C, device="cuda")
+        self.req = un._BnGrad(*(t.data_ptr() for t in self.t), self.s_d.data_ptr(),
+                              self.s_x.data_ptr(), C)
+        self.addr = ctypes.addressof(self.req)
+
+
+def _check_bn_sums(un, what, dout_gpu, layer, req):
+    z, mr, gamma, beta = layer
+    C = z.shape[-1]
+    s1, s2, e1, e2, *_ = _bn_sums_ref(dout_gpu.cpu().reshape(-1, C), z.reshape(-1, C), mr, gamma,
+                                      beta)
+    _check(req.s_d, s1, e1 + 1e-30, what + " sum_d")
+    _check(req.s_x, s2, e2 + 1e-30, what + " sum_dxhat")
+
+
+@pytest.mark.parametrize("N,H,W,cout,c0", [(2, 16, 40, 32, 32), (1, 9, 13, 32, 64),
+                                           (2, 8, 8, 16, 8)])
+def test_bn_sums_in_conv_input_gradient(un, N, H, W, cout, c0):
+    """The input gradient with the batch-norm sums of the layer it belongs to:
+    the same dx bit for bit, and sums of it against float64."""
+    _say(f"case conv dgrad + bn sums N={N} H={H} W={W} cout={cout} c0={c0}")
+    g = torch.Generator().manual_seed(N * 100 + H + c0)
+    dy = _bf((N, H, W, cout), g)
+    wt = _bf((c0, 3, 3, cout), g, 0.1)
+    layer = _bn_layer(g, N * H * W, c0)
+    dyc, wtc = dy.cuda(), wt.cuda()
+    plain = torch.empty((N, H, W, c0), dtype=torch.bfloat16, device="cuda")
+    fused = torch.empty_like(plain)
+    un._call("sil_unet_conv3x3_dgrad", un._p(dyc), cout, un._p(wtc), un._p(plain), c0, None, 0,
+             N, H, W, None, un._s())
+    req = _Req(un, *layer)
+    un._call("sil_unet_conv3x3_dgrad", un._p(dyc), cout, un._p(wtc), un._p(fused), c0, None, 0,
+             N, H, W, req.addr, un._s())
+    torch.cuda.synchronize()
+    assert torch.equal(plain.cpu().view(torch.int16), fused.cpu().view(torch.int16))
+    _check_bn_sums(un, "conv dgrad", fused, layer, req)
+
+
+@pytest.mark.parametrize("N,H,W,cin,cout", [(2, 8, 8, 64, 32), (1, 5, 7, 256, 128),
+                                            (2, 4, 6, 16, 16)])
+def test_bn_sums_in_upconv_input_gradient(un, N, H, W, cin, cout):
+    _say(f"case upconv dgrad + bn sums N={N} H={H} W={W} cin={cin} cout={cout}")
+    g = torch.Generator().manual_seed(N * 7 + H + cin)
+    dy = _bf((N, 2 * H, 2 * W, cout), g)
+    wt = _bf((cin, 2, 2, cout), g, 0.2)
+    C = cin
+    if 256 % (C // 8):
+        pytest.skip("channel groups must divide 256")
+    layer = _bn_layer(g, N * H * W, cin)
+    dyc, wtc = dy.cuda(), wt.cuda()
+    plain = torch.empty((N, H, W, cin), dtype=torch.bfloat16, device="cuda")
+    fused = torch.empty_like(plain)
+    un._call("sil_unet_upconv_dgrad", un._p(dyc), un._p(wtc), un._p(plain), N, H, W, cin, cout,
+             None, un._s())
+    req = _Req(un, *layer)
+    un._call("sil_unet_upconv_dgrad", un._p(dyc), un._p(wtc), un._p(fused), N, H, W, cin, cout,
+             req.addr, un._s())
+    torch.cuda.synchronize()
+    assert torch.equal(plain.cpu().view(torch.int16), fused.cpu().view(torch.int16))
+    _check_bn_sums(un, "upconv dgrad", fused, layer, req)
+
+
+def test_bn_sums_in_pool_and_head_backward(un):
+    """Max-pool backward (with the skip gradient added) and head backward
+    with the batch-norm sums; then the apply step from given sums against
+    float64 (the bound of test_bn_relu_backward)."""
+    _say("case maxpool/head backward + bn sums, bn apply")
+    g = torch.Generator().manual_seed(31)
+    N, H, W, C = 2, 12, 20, 32
+    x = _bf((N, H, W, C), g)
+    xc = x.cuda()
+    y = torch.empty((N, H // 2, W // 2, C), dtype=torch.bfloat16, device="cuda")
+    idx = torch.empty((N, H // 2, W // 2, C), dtype=torch.uint8, device="cuda")
+    un._call("sil_unet_maxpool", un._p(xc), un._p(y), un._p(idx), N, H, W, C, un._s())
+    dyc, dadd = _bf((N, H // 2, W // 2, C), g).cuda(), _bf((N, H, W, C), g).cuda()
+    plain = torch.empty((N, H, W, C), dtype=torch.bfloat16, device="cuda")
+    fused = torch.empty_like(plain)
+    un._call("sil_unet_maxpool_bwd", un._p(dyc), un._p(idx), un._p(dadd), un._p(plain), N, H, W, C,
+             None, un._s())
+    layer = _bn_layer(g, N * H * W, C)
+    req = _Req(un, *layer)
+    un._call("sil_unet_maxpool_bwd", un._p(dyc), un._p(idx), un._p(dadd), un._p(fused), N, H, W, C,
+             req.addr, un._s())
+    torch.cuda.synchronize()
+    assert torch.equal(plain.cpu().view(torch.int16), fused.cpu().view(torch.int16))
+    _check_bn_sums(un, "maxpool bwd", fused, layer, req)
+
+    P = 3000
+    hx = _bf((P, C), g).cuda()
+    w = (torch.randn((3, C), generator=g) * 0.3).cuda()
+    dl = (torch.randn((P, 3), generator=g) * 1e-3).cuda()
+    outs = []
+    hlayer = _bn_layer(g, P, C)
+    hreq = _Req(un, *hlayer)
+    for r in (None, hreq.addr):
+        dx = torch.empty((P, C), dtype=torch.bfloat16, device="cuda")
+        dw, db = torch.zeros((3, C), device="cuda"), torch.zeros(3, device="cuda")
+        un._call("sil_unet_head_bwd", un._p(hx), un._p(w), un._p(dl), None, un._p(dx), un._p(dw),
+                 un._p(db), P, C, r, un._s())
+        outs.append(dx)
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0].cpu().view(torch.int16), outs[1].cpu().view(torch.int16))
+    _check_bn_sums(un, "head bwd", outs[1], hlayer, hreq)
+
+    # the apply step from the sums formed above
+    z, mr, gamma, beta = hlayer
+    dz = torch.empty((P, C), dtype=torch.bfloat16, device="cuda")
+    zc, mrc, gc, bc = hreq.t
+    un._call("sil_unet_bn_relu_bwd_apply", un._p(outs[1]), un._p(zc), un._p(mrc), un._p(gc),
+             un._p(bc), un._p(hreq.s_d), un._p(hreq.s_x), un._p(dz), P, C, un._s())
+    torch.cuda.synchronize()
+    s1, s2, e1, e2, zh, d, amb = _bn_sums_ref(outs[1].cpu(), z, mr, gamma, beta)
+    k = gamma.double() * mr[1].double()
+    ref = k * (d - (s1 + zh * s2) / P)
+    bound = BF * ref.abs() + k.abs() * (8 * U32 * (d.abs() + (s1.abs() + zh.abs() * s2.abs()) / P)
+                                        + (e1 + zh.abs() * e2) / P)
+    bound = torch.where(amb, torch.full((), float("inf")).double(), bound)
+    _check(dz, ref, bound, "bn_relu_bwd_apply dz")
