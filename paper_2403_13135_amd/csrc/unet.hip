@@ -685,14 +685,16 @@ struct GemmTN {
 // tiles.  A block owns 32 output channels (n0) and a 32-channel input chunk (cc)
 // and walks pixel tiles blockIdx.x, blockIdx.x + gridDim.x, ...  Per tile, dy^T
 // (32 channels x 256 pixels) and x^T of the 10 x 34 halo tile are staged in
-// LDS, x^T in three copies shifted by 0, 1 and 2 columns so that every tap's
-// 8-pixel MFMA operands stay 16-byte aligned; the K steps are the tile's 8 rows
-// of 32 pixels.  The 36 output blocks of 16 x 16 (9 taps x 2 x 2) are spread
-// 9 per wave.  Staging stores pixel pairs as 4-byte words (2-byte stores for
-// the odd-shifted copy).  The next tile's loads are in flight during the
-// current tile's MFMAs; partial sums reach dw with one fp32 atomic per element
-// per block.  Requires cout, c0 and c1 divisible by 32.
-constexpr int kXRow = kCIH * kCTW + 8;  // u16 per staged x^T channel row (padded)
+// LDS (x^T halo rows kXHalo elements apart); the K steps are the tile's 8 rows
+// of 32 pixels.  A tap shifted by dx columns needs its 8-pixel MFMA operand
+// dx elements past a 16-byte boundary: it is built in registers from the
+// aligned 16 bytes and the next 4 (byte-align for dx = 1, a dword shift for
+// dx = 2).  Each wave owns one of the 2 x 2 output blocks of 16 x 16 for all 9
+// taps.  Staging stores pixel pairs as 4-byte words.  The next tile's loads
+// are in flight during the current tile's MFMAs; partial sums reach dw with one
+// fp32 atomic per element per block.  Requires cout, c0 and c1 divisible by 32.
+constexpr int kXHalo = 40;                    // u16 per staged x^T halo row (34 used)
+constexpr int kXRow = kCIH * kXHalo + 24;     // u16 per staged x^T channel row (padded)
 constexpr int kARow = kCTH * kCTW + 8;  // u16 per staged dy^T channel row (padded)
 
 // Column of a staged channel row, swizzled: channel rows 16-31 exchange
@@ -708,7 +710,7 @@ __global__ __launch_bounds__(kGT) void k_wgrad3_lds(GemmTN g) {
   constexpr int X_SLOTS = kCIH * (kCIW / 2) * 4;   // 10 rows x 17 pairs x 4 groups = 680
   constexpr int X_R = (X_SLOTS + kGT - 1) / kGT;   // 3
   __shared__ u16 Sa[32][kARow];
-  __shared__ u16 Sx[3][32][kXRow];
+  __shared__ u16 Sx[32][kXRow];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int32_t ct = g.c0 + g.c1;
   const int32_t nblk_ci = ct / 32;
@@ -776,25 +778,9 @@ __global__ __launch_bounds__(kGT) void k_wgrad3_lds(GemmTN g) {
       const uint32_t w1[4] = {rx[r][1].x, rx[r][1].y, rx[r][1].z, rx[r][1].w};
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const uint32_t lo = (w0[t] & 0xffffu) | (w1[t] << 16);          // channel 2t
-        const uint32_t hi = (w0[t] >> 16) | (w1[t] & 0xffff0000u);     // channel 2t+1
-        const int ch0 = 8 * grp + 2 * t;
-        // copy d holds halo column c + d at column c
-        const int c0 = hr * kCTW + 2 * hp;
-        if (hp <= 15) {
-          *(uint32_t*)&Sx[0][ch0][swz(ch0, c0)] = lo;
-          *(uint32_t*)&Sx[0][ch0 + 1][swz(ch0 + 1, c0)] = hi;
-        }
-        if (hp >= 1) {
-          *(uint32_t*)&Sx[2][ch0][swz(ch0, c0 - 2)] = lo;
-          *(uint32_t*)&Sx[2][ch0 + 1][swz(ch0 + 1, c0 - 2)] = hi;
-          Sx[1][ch0][swz(ch0, c0 - 1)] = (u16)(lo & 0xffffu);
-          Sx[1][ch0 + 1][swz(ch0 + 1, c0 - 1)] = (u16)(hi & 0xffffu);
-        }
-        if (hp <= 15) {
-          Sx[1][ch0][swz(ch0, c0)] = (u16)(lo >> 16);
-          Sx[1][ch0 + 1][swz(ch0 + 1, c0)] = (u16)(hi >> 16);
-        }
+        const int ch0 = 8 * grp + 2 * t, c0 = hr * kXHalo + 2 * hp;
+        *(uint32_t*)&Sx[ch0][c0] = (w0[t] & 0xffffu) | (w1[t] << 16);          // channel 2t
+        *(uint32_t*)&Sx[ch0 + 1][c0] = (w0[t] >> 16) | (w1[t] & 0xffff0000u);  // channel 2t+1
       }
     }
   };
@@ -824,11 +810,19 @@ __global__ __launch_bounds__(kGT) void k_wgrad3_lds(GemmTN g) {
         if (s < kCTH)
           arow[s] = __builtin_bit_cast(
               bf16x8, *(const uint4*)&Sa[ar][swz(ar, kCTW * s + 8 * (lane >> 4))]);
+        // halo columns 8q .. 8q+9 of halo row s (q = lane / 16): the operands of
+        // the three column shifts
+        const int xc = kXHalo * s + 8 * (lane >> 4);
+        const uint4 c0 = *(const uint4*)&Sx[xr][xc];
+        const uint32_t c1 = *(const uint32_t*)&Sx[xr][xc + 8];
         bf16x8 bx[3];
-#pragma unroll
-        for (int dx = 0; dx < 3; ++dx)
-          bx[dx] = __builtin_bit_cast(
-              bf16x8, *(const uint4*)&Sx[dx][xr][swz(xr, kCTW * s + 8 * (lane >> 4))]);
+        bx[0] = __builtin_bit_cast(bf16x8, c0);
+        bx[1] = __builtin_bit_cast(
+            bf16x8, make_uint4(__builtin_amdgcn_alignbyte(c0.y, c0.x, 2),
+                               __builtin_amdgcn_alignbyte(c0.z, c0.y, 2),
+                               __builtin_amdgcn_alignbyte(c0.w, c0.z, 2),
+                               __builtin_amdgcn_alignbyte(c1, c0.w, 2)));
+        bx[2] = __builtin_bit_cast(bf16x8, make_uint4(c0.y, c0.z, c0.w, c1));
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy) {
           const int r = s - dy;
