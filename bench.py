@@ -138,6 +138,21 @@ def run_variants(sil, scene, H, W, stream, reps=20):
                      "algorithmic_bytes_per_px": bpp,
                      "achieved_gbs": H * W * bpp / (ms / 1e3) / 1e9}
         del ws, buf
+    # the colour rendering of the class ids (1 byte in, 3 out per pixel)
+    labels, _ = sil.label(scene, sil.Params(dtype=sil.U16), W=W, stream=stream)
+    rgb = sil.render_rgb(labels, W=W, stream=stream)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        sil.render_rgb(labels, W=W, out=rgb, stream=stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    out["render_rgb"] = {"ms": ms, "gpx_s": H * W / (ms / 1e3) / 1e9,
+                         "algorithmic_bytes_per_px": 4,
+                         "achieved_gbs": H * W * 4 / (ms / 1e3) / 1e9}
+    del labels, rgb
     return out
 
 

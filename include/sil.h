@@ -260,6 +260,19 @@ int sil_label_ex_noalloc(const void* scene, int32_t nbands, const int32_t sel[3]
                          int64_t mask_pitch, uint32_t* counts, uint8_t* rgb, int64_t rgb_pitch,
                          sil_chip_info* chips, void* stream);
 
+/* Colour rendering of a class-id plane (section III-A labels scenes in red
+ * for snow-covered / thick ice, blue for thin or young ice and green for open
+ * water; section III-B merges the three class masks, each in its colour, into
+ * one image).  labels: [H][lpitch] bytes, class ids 0 water, 1 thin ice,
+ * 2 thick ice (as sil_label writes them); rgb: [H][rgb_pitch] bytes of
+ * interleaved R, G, B, rgb_pitch >= 3 W.  Class 0 -> (0, 255, 0), 1 -> (0, 0,
+ * 255), 2 -> (255, 0, 0), any other value -> (0, 0, 0).  Device pointers,
+ * asynchronous on stream.  Errors (nothing enqueued): SIL_EINVAL for a NULL
+ * pointer, H or W < 1, lpitch < W or rgb_pitch < 3 W; SIL_EDEVICE on a
+ * launch failure. */
+int sil_render_rgb(const uint8_t* labels, int32_t H, int32_t W, int64_t lpitch, uint8_t* rgb,
+                   int64_t rgb_pitch, void* stream);
+
 /* Human-readable text of a return code (static storage). */
 const char* sil_strerror(int code);
 

@@ -507,3 +507,22 @@ int sil_ref_label_ex(const void* scene, int32_t nbands, const int32_t* sel, int3
   free(Vm);
   return SIL_REF_OK;
 }
+
+/* ---- colour rendering of the class ids (sections III-A, III-B) --------- */
+
+void sil_ref_render_rgb(const uint8_t* labels, int32_t H, int32_t W, int64_t lpitch,
+                        uint8_t* rgb, int64_t rgb_pitch) {
+  for (int32_t y = 0; y < H; ++y) {
+    for (int32_t x = 0; x < W; ++x) {
+      const uint8_t c = labels[(int64_t)y * lpitch + x];
+      uint8_t r = 0, g = 0, b = 0;
+      if (c == 0) g = 255;      /* open water: green */
+      else if (c == 1) b = 255; /* thin ice: blue */
+      else if (c == 2) r = 255; /* thick ice: red */
+      uint8_t* o = rgb + (int64_t)y * rgb_pitch + 3 * (int64_t)x;
+      o[0] = r;
+      o[1] = g;
+      o[2] = b;
+    }
+  }
+}

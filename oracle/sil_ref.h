@@ -125,6 +125,16 @@ void sil_ref_hsv8(uint8_t r, uint8_t g, uint8_t b, uint8_t* h, uint8_t* s, uint8
 void sil_ref_hsv8_many(const uint8_t* rgb, int64_t n, uint8_t* hsv);
 uint8_t sil_ref_filtered_band(uint8_t c, uint8_t v, uint8_t vc);
 
+/* Colour rendering of a class-id plane (section III-A names the colours of
+ * the labelled scenes: red for snow-covered / thick ice, blue for thin or
+ * young ice, green for open water; section III-B merges the class masks, each
+ * in its colour, into one image).  labels [H][lpitch] with 0 water, 1 thin,
+ * 2 thick; rgb [H][rgb_pitch] interleaved (R, G, B): water (0, 255, 0), thin
+ * (0, 0, 255), thick (255, 0, 0), any other id (0, 0, 0).  Bytes of rgb past
+ * 3 W in a row are left as they are. */
+void sil_ref_render_rgb(const uint8_t* labels, int32_t H, int32_t W, int64_t lpitch,
+                        uint8_t* rgb, int64_t rgb_pitch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -97,6 +97,9 @@ def lib():
         L.sil_ref_hsv8_many.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
         L.sil_ref_filtered_band.argtypes = [ctypes.c_uint8, ctypes.c_uint8, ctypes.c_uint8]
         L.sil_ref_filtered_band.restype = ctypes.c_uint8
+        L.sil_ref_render_rgb.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64]
+        L.sil_ref_render_rgb.restype = None
         L.sil_ref_strerror.argtypes = [ctypes.c_int]
         L.sil_ref_strerror.restype = ctypes.c_char_p
         _lib = L
@@ -270,3 +273,15 @@ def hsv8(rgb: np.ndarray) -> np.ndarray:
 
 def filtered_band(c: int, v: int, vc: int) -> int:
     return int(lib().sil_ref_filtered_band(c, v, vc))
+
+
+def render_rgb(labels: np.ndarray, W: int = None) -> np.ndarray:
+    """Colour image [H, W, 3] (R, G, B) of a class-id plane [H, >=W] u8
+    (sections III-A/III-B colours: water green, thin ice blue, thick ice red,
+    other ids black)."""
+    lab = np.ascontiguousarray(labels, dtype=np.uint8)
+    H, pitch = lab.shape
+    W = pitch if W is None else W
+    out = np.zeros((H, W, 3), dtype=np.uint8)
+    lib().sil_ref_render_rgb(lab.ctypes.data, H, W, pitch, out.ctypes.data, 3 * W)
+    return out

@@ -34,6 +34,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <type_traits>
 
@@ -955,6 +956,43 @@ void launch_single(const Shared& sh, const Scene& sc, bool fast24, int filter,
   }
 }
 
+// Colour of a class id as a little-endian (R, G, B) triple in the low 24 bits:
+// water green, thin ice blue, thick ice red, anything else black.
+__device__ __forceinline__ uint32_t class_rgb(uint32_t c) {
+  return (c == 0u ? 0x00ff00u : 0u) | (c == 1u ? 0xff0000u : 0u) | (c == 2u ? 0x0000ffu : 0u);
+}
+
+// Four pixels per thread: one 4-byte read of class ids and three 4-byte writes
+// of their 12 colour bytes when the rows allow (VEC), else byte by byte.
+template <bool VEC>
+__global__ void k_render_rgb(const uint8_t* labels, int32_t H, int32_t W, int64_t lpitch,
+                             uint8_t* rgb, int64_t rgb_pitch) {
+  const int32_t nq = (W + 3) / 4;
+  const int64_t n = (int64_t)H * nq;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t y = (int32_t)(i / nq), x = 4 * (int32_t)(i - (int64_t)y * nq);
+    const uint8_t* lrow = labels + (int64_t)y * lpitch;
+    uint8_t* crow = rgb + (int64_t)y * rgb_pitch + 3 * (int64_t)x;
+    if (VEC && x + 4 <= W) {
+      const uint32_t l4 = *(const uint32_t*)(lrow + x);
+      const uint32_t c0 = class_rgb(l4 & 255u), c1 = class_rgb((l4 >> 8) & 255u),
+                     c2 = class_rgb((l4 >> 16) & 255u), c3 = class_rgb(l4 >> 24);
+      uint32_t* o = (uint32_t*)crow;
+      o[0] = c0 | (c1 << 24);
+      o[1] = (c1 >> 8) | (c2 << 16);
+      o[2] = (c2 >> 16) | (c3 << 8);
+    } else {
+      for (int32_t j = 0; j < 4 && x + j < W; ++j) {
+        const uint32_t c = class_rgb(lrow[x + j]);
+        crow[3 * j] = (uint8_t)c;
+        crow[3 * j + 1] = (uint8_t)(c >> 8);
+        crow[3 * j + 2] = (uint8_t)(c >> 16);
+      }
+    }
+  }
+}
+
 template <typename T>
 void launch_batch(const Shared& sh, const Batch& bt, bool fast24, hipStream_t stream) {
   const dim3 grid(deal_grid(bt.prefix[bt.n])), block(kThreads);
@@ -1116,6 +1154,26 @@ int sil_label_batch(const sil_job* jobs, int32_t njobs, const sil_params* p, voi
     launch_batch<uint16_t>(sh, bt, fast24, st);
   else
     launch_batch<uint8_t>(sh, bt, false, st);
+  if (hipGetLastError() != hipSuccess) return SIL_EDEVICE;
+  return SIL_OK;
+}
+
+int sil_render_rgb(const uint8_t* labels, int32_t H, int32_t W, int64_t lpitch, uint8_t* rgb,
+                   int64_t rgb_pitch, void* stream) {
+  if (!labels || !rgb || H < 1 || W < 1 || lpitch < W || rgb_pitch < 3 * (int64_t)W)
+    return SIL_EINVAL;
+  const int64_t n = (int64_t)H * ((W + 3) / 4);
+  const int grid = (int)std::min<int64_t>((n + 255) / 256, 8192);
+  const bool vec = ((uintptr_t)labels % 4 == 0) && lpitch % 4 == 0 &&
+                   ((uintptr_t)rgb % 4 == 0) && rgb_pitch % 4 == 0;
+  hipStream_t st = (hipStream_t)stream;
+  (void)hipGetLastError();
+  if (vec)
+    hipLaunchKernelGGL(k_render_rgb<true>, dim3(grid), dim3(256), 0, st, labels, H, W, lpitch,
+                       rgb, rgb_pitch);
+  else
+    hipLaunchKernelGGL(k_render_rgb<false>, dim3(grid), dim3(256), 0, st, labels, H, W, lpitch,
+                       rgb, rgb_pitch);
   if (hipGetLastError() != hipSuccess) return SIL_EDEVICE;
   return SIL_OK;
 }

@@ -108,6 +108,10 @@ def lib() -> ctypes.CDLL:
                                    ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
         L.sil_label_ex.restype = ctypes.c_int
         L.sil_label_ex_noalloc.argtypes = L.sil_label_ex.argtypes[:-3] + [ctypes.c_void_p]
+        L.sil_render_rgb.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                     ctypes.c_void_p]
+        L.sil_render_rgb.restype = ctypes.c_int
         L.sil_label_ex_noalloc.restype = ctypes.c_int
         L.sil_strerror.argtypes = [ctypes.c_int]
         L.sil_strerror.restype = ctypes.c_char_p
@@ -240,6 +244,29 @@ def label(scene: torch.Tensor, params: Optional[Params] = None, sel=(0, 1, 2),
                          ctypes.c_void_p(s.cuda_stream))
     _check(rc)
     return (labels, hist, chip_t) if chips else (labels, hist)
+
+
+def render_rgb(labels: torch.Tensor, W: Optional[int] = None, out: Optional[torch.Tensor] = None,
+               stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """Colour image of a class-id plane with ``sil_render_rgb``: labels
+    [H, >=W] uint8 on the GPU (any row stride) -> [H, W, 3] uint8 (R, G, B):
+    water green, thin ice blue, thick ice red, other ids black.  ``out`` may be
+    a uint8 [H, W, 3] tensor with unit strides in its last two dimensions."""
+    if labels.dtype != torch.uint8 or labels.dim() != 2 or not labels.is_cuda \
+            or labels.stride(1) != 1:
+        raise ValueError("labels must be a uint8 [H, >=W] GPU tensor with unit column stride")
+    H = labels.shape[0]
+    W = labels.shape[1] if W is None else int(W)
+    if out is None:
+        out = torch.empty((H, W, 3), dtype=torch.uint8, device=labels.device)
+    if out.dtype != torch.uint8 or out.shape != (H, W, 3) or out.stride(2) != 1 \
+            or out.stride(1) != 3:
+        raise ValueError(f"out must be uint8 [{H}, {W}, 3] with interleaved pixels")
+    s = stream if stream is not None else torch.cuda.current_stream(labels.device)
+    _check(lib().sil_render_rgb(ctypes.c_void_p(labels.data_ptr()), H, W, labels.stride(0),
+                                ctypes.c_void_p(out.data_ptr()), out.stride(0),
+                                ctypes.c_void_p(s.cuda_stream)))
+    return out
 
 
 def decode_chip_info(raw) -> list:

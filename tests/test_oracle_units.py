@@ -206,3 +206,48 @@ def test_stretch_matches_fractions():
         if hi <= lo:
             continue
         assert R.stretch(m, lo, hi) == brute.stretch(m, lo, hi), (m, lo, hi)
+
+
+# ---- colour rendering ---------------------------------------------------------
+
+def _palette():
+    pal = np.zeros((256, 3), dtype=np.uint8)  # ids the paper does not name: black
+    for cid, _name, r, g, b in _read_table("paper_class_colours.txt"):
+        pal[int(cid)] = (int(r), int(g), int(b))
+    return pal
+
+
+def test_render_rgb_uses_the_papers_colours():
+    """Every id 0..255 once, in a row of odd length: the three classes get
+    the colours the paper names (golden file), every other id black."""
+    ids = np.arange(256, dtype=np.uint8)[::-1].reshape(1, 256)
+    lab = np.zeros((2, 257), dtype=np.uint8)
+    lab[0, :256] = ids
+    lab[1, :] = 1
+    out = R.render_rgb(lab)
+    pal = _palette()
+    assert (out[0, :256] == pal[ids[0]]).all()
+    assert (out[1] == pal[1]).all()
+    assert tuple(out[0, 256]) == tuple(pal[0])
+
+
+def test_render_rgb_of_labelled_scene():
+    """End to end: a scene with one V per class (filter off) renders as the
+    paper's colours of those classes."""
+    v = np.array([10, 100, 230, 30, 31, 204, 205], dtype=np.uint8)
+    scene = np.stack([v, v // 2, v // 3])[:, None, :]
+    labels, _ = R.label(scene, R.make_params(filter=0, patch_h=1, patch_w=len(v)))
+    out = R.render_rgb(labels)
+    want = _palette()[[0, 1, 2, 0, 1, 1, 2]]
+    assert (out[0] == want).all()
+
+
+def test_render_rgb_leaves_row_padding():
+    """rgb rows longer than 3 W keep their bytes past 3 W."""
+    lib = R.lib()
+    lab = np.array([[0, 1, 2], [2, 1, 0]], dtype=np.uint8)
+    rgb = np.full((2, 11), 7, dtype=np.uint8)
+    lib.sil_ref_render_rgb(lab.ctypes.data, 2, 3, 3, rgb.ctypes.data, 11)
+    assert (rgb[:, 9:] == 7).all()
+    pal = _palette()
+    assert (rgb[:, :9].reshape(2, 3, 3) == pal[lab]).all()
