@@ -268,14 +268,18 @@ def run_learned(steps, n_fallback, n_capacity, fb_batch, seeds_per_size):
     test_sc = learn.make_scenes(3, 2048, seed0=4000)
     X, Y = learn.build_training_set(train_sc)
     model = unet.UNet(widths, seed=0)
-    say(f"U-Net training, {steps} steps")
-    losses, sec = learn.train(model, X, Y, steps=steps, batch=32, lr=1e-3)
+    say(f"U-Net training, {steps} steps, each replaying one recorded HIP graph")
+    losses, sec = learn.train(model, X, Y, steps=steps, batch=32, lr=1e-3, graph=True)
     flops_step = 3 * learn.unet_flops_per_image(widths) * 32
     ev = learn.evaluate(model, test_sc)
+    # the same step launched eagerly, on a second model, for comparison
+    say("U-Net training, 12 eager steps")
+    _, sec_eager = learn.train(unet.UNet(widths, seed=0), X, Y, steps=12, batch=32, lr=1e-3)
     out = {"widths": list(widths), "batch": 32, "train_chips": int(X.shape[0]), "steps": steps,
            "step_ms": sec * 1e3, "images_per_s": 32 / sec,
            "tflops": flops_step / sec / 1e12,
            "mfma_frac_of_bf16_dense_peak": flops_step / sec / 2.5e15,
+           "step_ms_eager_launches": sec_eager * 1e3,
            "loss_first_last": [losses[0], float(np.mean(losses[-10:]))], "held_out": ev}
     del X, Y, train_sc
     torch.cuda.empty_cache()

@@ -214,9 +214,18 @@ typedef struct sil_unet_adam_tensor {
 } sil_unet_adam_tensor;
 
 /* sil_unet_adam's update (without the bf16 copy) on `count` tensors in one
- * launch per 64 tensors. */
+ * launch per 64 tensors.  The step number (>= 1) is `step`, or, when step_dev
+ * (a device int32) is non-NULL, the value it holds when the kernel runs: a
+ * launch captured in a graph then takes the step current at each replay (the
+ * caller advances it, e.g. with sil_unet_counter_add in the same graph).  The
+ * bias corrections 1 - beta^step are formed on the device. */
 int sil_unet_adam_multi(const sil_unet_adam_tensor* t, int32_t count, float lr, float beta1,
-                        float beta2, float eps, int32_t step, void* stream);
+                        float beta2, float eps, int32_t step, const int32_t* step_dev,
+                        void* stream);
+
+/* counter[0] += v on the device (a one-thread kernel: capturable, unlike a
+ * host write). */
+int sil_unet_counter_add(int32_t* counter, int32_t v, void* stream);
 
 #define SIL_UNET_W_CONV3 1 /* w [cout][3][3][cin]; wt [cin][3][3][cout] flipped (sil_unet_flip3x3) */
 #define SIL_UNET_W_UP2 2   /* w [2][2][cout][cin]; wt [cin][2][2][cout] (sil_unet_up_t) */

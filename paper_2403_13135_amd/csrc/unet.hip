@@ -1676,8 +1676,14 @@ __device__ __forceinline__ int list_find(const int32_t* blk0, int count, int b) 
 }
 
 // Adam with the arithmetic of k_adam, on every tensor of the list
-__global__ void k_adam_multi(AdamList L, float lr, float b1, float b2, float eps, float c1,
-                             float c2) {
+// The step number comes from the arguments or, when step_dev is set, from
+// device memory, so that a launch recorded in a graph uses the value current
+// when the graph is replayed; the bias corrections are formed on the device in
+// both cases.
+__global__ void k_adam_multi(AdamList L, float lr, float b1, float b2, float eps, int32_t step,
+                             const int32_t* step_dev) {
+  const float t = (float)(step_dev ? *step_dev : step);
+  const float c1 = 1.f - powf(b1, t), c2 = 1.f - powf(b2, t);
   const int i = list_find(L.blk0, L.count, blockIdx.x);
   float* w = L.t[i].w;
   const float* g = L.t[i].g;
@@ -1702,6 +1708,10 @@ __global__ void k_adam_multi(AdamList L, float lr, float b1, float b2, float eps
 // gradients.  Element e is the e-th element of both outputs: wb[e] =
 // bf16(w[e]), and wt[e] gathers its source from w, so that every store is
 // coalesced and the scattered reads hit the cache.
+__global__ void k_counter_add(int32_t* c, int32_t v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) c[0] += v;
+}
+
 __global__ void k_prep_weights(PrepList L) {
   const int i = list_find(L.blk0, L.count, blockIdx.x);
   const float* w = L.t[i].w;
@@ -2255,8 +2265,9 @@ int sil_unet_adam(float* w, const float* g, float* m, float* v, void* wbf, int64
 }
 
 int sil_unet_adam_multi(const sil_unet_adam_tensor* t, int32_t count, float lr, float beta1,
-                        float beta2, float eps, int32_t step, void* stream) {
-  if (!t || count <= 0 || step < 1) return SIL_EINVAL;
+                        float beta2, float eps, int32_t step, const int32_t* step_dev,
+                        void* stream) {
+  if (!t || count <= 0 || (!step_dev && step < 1)) return SIL_EINVAL;
   int64_t blocks = 0;
   for (int32_t i = 0; i < count; ++i) {
     if (!t[i].w || !t[i].g || !t[i].m || !t[i].v || t[i].n <= 0) return SIL_EINVAL;
@@ -2264,7 +2275,6 @@ int sil_unet_adam_multi(const sil_unet_adam_tensor* t, int32_t count, float lr, 
   }
   if (blocks > INT32_MAX) return SIL_EINVAL;
   (void)hipGetLastError();
-  const float c1 = 1.f - powf(beta1, (float)step), c2 = 1.f - powf(beta2, (float)step);
   for (int32_t s0 = 0; s0 < count; s0 += kMulti) {
     AdamList L{};
     L.count = std::min(kMulti, count - s0);
@@ -2276,8 +2286,15 @@ int sil_unet_adam_multi(const sil_unet_adam_tensor* t, int32_t count, float lr, 
     }
     L.blk0[L.count] = b;
     hipLaunchKernelGGL(k_adam_multi, dim3(b), dim3(256), 0, (hipStream_t)stream, L, lr, beta1,
-                       beta2, eps, c1, c2);
+                       beta2, eps, step, step_dev);
   }
+  return done();
+}
+
+int sil_unet_counter_add(int32_t* counter, int32_t v, void* stream) {
+  if (!counter) return SIL_EINVAL;
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(k_counter_add, dim3(1), dim3(64), 0, (hipStream_t)stream, counter, v);
   return done();
 }
 

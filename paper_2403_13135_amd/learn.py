@@ -94,26 +94,36 @@ def build_training_set(scenes: List[Scene]):
 
 
 def train(model: unet.UNet, X: torch.Tensor, Y: torch.Tensor, steps: int, batch: int = 32,
-          lr: float = 1e-3, seed: int = 0, log_every: int = 0):
-    """Adam on random batches; returns (losses, seconds per step after warm-up)."""
+          lr: float = 1e-3, seed: int = 0, log_every: int = 0, graph: bool = False):
+    """Adam on random batches; returns (losses, seconds per step after warm-up).
+    With graph=True the first two steps run eagerly and every later step
+    replays one recorded HIP graph of the whole step (unet.CapturedStep)."""
     opt = unet.Adam(model.params, lr=lr)
     g = torch.Generator().manual_seed(seed)
     losses, t_steps = [], []
+    captured = None
     for step in range(steps):
         idx = torch.randint(0, X.shape[0], (batch,), generator=g).to(X.device)
         xb, yb = X.index_select(0, idx), Y.index_select(0, idx)
+        if graph and captured is None and step >= 2:
+            captured = unet.CapturedStep(model, opt, xb, yb)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        opt.zero_grad()
-        loss, _ = model.forward(xb, yb)
-        model.backward(loss)
-        opt.step()
-        model.update_running_stats()
+        if captured is not None:
+            loss = captured(xb, yb)
+        else:
+            opt.zero_grad()
+            loss = model.forward(xb, yb)[0]
+            model.backward(loss)
+            opt.step()
+            model.update_running_stats()
         torch.cuda.synchronize()
         t_steps.append(time.perf_counter() - t0)
         losses.append(loss.item())
+        loss = None  # no autograd graph of an eager step may be alive when the step is recorded
         if log_every and step % log_every == 0:
             print(f"step {step} loss {losses[-1]:.4f} {t_steps[-1] * 1e3:.1f} ms", flush=True)
+    opt.sync_step()
     warm = t_steps[min(5, len(t_steps) - 1):]
     return losses, float(np.median(warm))
 

@@ -56,7 +56,8 @@ def _lib():
             "sil_unet_argmax": [vp, vp, i64, vp],
             "sil_unet_chips_input": [vp, i32, i32, i64, vp, i32, i32, f32, vp, vp],
             "sil_unet_adam": [vp, vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp],
-            "sil_unet_adam_multi": [vp, i32, f32, f32, f32, f32, i32, vp],
+            "sil_unet_adam_multi": [vp, i32, f32, f32, f32, f32, i32, vp, vp],
+            "sil_unet_counter_add": [vp, i32, vp],
             "sil_unet_prep_weights": [vp, i32, vp],
             "sil_unet_bn_ema": [vp, i32, f32, f32, vp],
             "sil_unet_bn_fold": [vp, i32, f32, vp],
@@ -572,7 +573,10 @@ class UNet:
 
 class Adam:
     """Adam on the model's fp32 master weights: every tensor with a gradient in
-    one multi-tensor launch."""
+    one multi-tensor launch.  With use_device_step() the step number lives in
+    device memory and is advanced by a kernel, so that a step captured in a
+    graph counts correctly on every replay (self.t is then brought up to date
+    by sync_step())."""
 
     def __init__(self, params: Dict[str, torch.Tensor], lr=1e-3, betas=(0.9, 0.999), eps=1e-8):
         self.params = params
@@ -580,8 +584,17 @@ class Adam:
         self.m = {k: torch.zeros_like(v) for k, v in params.items()}
         self.v = {k: torch.zeros_like(v) for k, v in params.items()}
         self.t = 0
+        self.t_dev = None  # device int32: the number of the next step
         self._key = None
         self._arr = None
+
+    def use_device_step(self):
+        dev = next(iter(self.params.values())).device
+        self.t_dev = torch.full((1,), self.t + 1, dtype=torch.int32, device=dev)
+
+    def sync_step(self):
+        if self.t_dev is not None:
+            self.t = int(self.t_dev.item()) - 1
 
     @torch.no_grad()
     def step(self):
@@ -601,11 +614,50 @@ class Adam:
             self._key = key
         _call("sil_unet_adam_multi", ctypes.cast(self._arr, ctypes.c_void_p), len(self._arr),
               ctypes.c_float(self.lr), ctypes.c_float(self.b1), ctypes.c_float(self.b2),
-              ctypes.c_float(self.eps), self.t, _s())
+              ctypes.c_float(self.eps), self.t, _p(self.t_dev), _s())
+        if self.t_dev is not None:
+            _call("sil_unet_counter_add", _p(self.t_dev), 1, _s())
 
     def zero_grad(self):
         for p in self.params.values():
             p.grad = None
+
+
+class CapturedStep:
+    """One training step (forward, backward, Adam, running statistics) recorded
+    once in a HIP graph (torch.cuda.graph over the library's launches) and
+    replayed: no host work and no launch gaps per step.  The batch goes through
+    static input tensors; the model's buffers, the step's zeroed scratch and
+    the optimizer's step counter stay at the addresses recorded.  Call after at
+    least one eager step (which sizes the scratch pool), with no autograd graph
+    of an earlier step still alive (drop its loss tensor first: its gradient
+    accumulators belong to the stream it ran on).  Recording launches nothing;
+    every replay is one training step."""
+
+    def __init__(self, model: "UNet", opt: Adam, x: torch.Tensor, labels: torch.Tensor):
+        self.model, self.opt = model, opt
+        self.x = x.clone()
+        self.labels = labels.clone()
+        if opt.t_dev is None:
+            opt.use_device_step()
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            opt.zero_grad()
+            self.loss, _ = model.forward(self.x, self.labels)
+            model.backward(self.loss)
+            opt.step()
+            model.update_running_stats()
+        opt.zero_grad()
+        opt.t -= 1  # recording counted a step on the host that did not run
+
+    def __call__(self, x: torch.Tensor, labels: torch.Tensor) -> torch.Tensor:
+        """Copy the batch in, replay; returns the (static) loss tensor."""
+        self.x.copy_(x)
+        self.labels.copy_(labels)
+        self.graph.replay()
+        self.opt.t += 1
+        return self.loss
 
 
 def chips_input(scene: torch.Tensor, origins: torch.Tensor, chip: int = 256,

@@ -349,3 +349,88 @@ def test_training_steps_reduce_loss(un):
         losses.append(loss.item())
     _say(f"losses {losses[0]:.3f} -> {losses[-1]:.3f}")
     assert losses[-1] < 0.5 * losses[0]
+
+
+def _eager_step(model, opt, x, labels):
+    opt.zero_grad()
+    loss, _ = model.forward(x, labels)
+    model.backward(loss)
+    opt.step()
+    model.update_running_stats()
+    return loss
+
+
+def _copy_state(dst_model, dst_opt, src_model, src_opt):
+    with torch.no_grad():
+        for k in src_model.params:
+            dst_model.params[k].copy_(src_model.params[k])
+            dst_opt.m[k].copy_(src_opt.m[k])
+            dst_opt.v[k].copy_(src_opt.v[k])
+        for n in src_model.running:
+            for a, b in zip(dst_model.running[n], src_model.running[n]):
+                a.copy_(b)
+    src_opt.sync_step()
+    dst_opt.t = src_opt.t
+
+
+def test_captured_training_step_replays(un):
+    """The training step recorded in a HIP graph (unet.CapturedStep), replayed
+    four times with other GPU work and synchronisations in between: each replay
+    is compared with two eager steps taken from the same state on twin models.
+    The order of fp32 atomics (batch-norm sums, weight gradients) differs from
+    run to run and, through bf16 roundings, can move small gradients a lot, so
+    the bound is what separates the two eager steps: over all weights, the
+    replay's mean distance from the first eager step is at most twice the
+    second eager step's, plus 0.1 % of a learning rate; every weight stays within
+    2.5 learning rates (the most one Adam update can move) and the loss within
+    twice the eager steps' difference or 5e-4 relative.  The step counter
+    advances once per replay."""
+    widths = (8, 8, 16, 16)
+    lr = 1e-3
+    g = torch.Generator().manual_seed(9)
+    N, H, W = 4, 64, 64
+    batches = []
+    for _ in range(6):
+        base = torch.rand((N, H, W), generator=g)
+        x = torch.zeros((N, H, W, 8), dtype=torch.bfloat16)
+        for c in range(3):
+            x[..., c] = (base + 0.05 * torch.randn((N, H, W), generator=g)).to(torch.bfloat16)
+        batches.append((x.cuda(), (base * 3).clamp(max=2.99).long().to(torch.uint8).cuda()))
+    mg, m1, m2 = (un.UNet(widths, seed=4) for _ in range(3))
+    og, o1, o2 = (un.Adam(m.params, lr=lr) for m in (mg, m1, m2))
+    _eager_step(mg, og, *batches[0])  # sizes the scratch pool before recording
+    cap = un.CapturedStep(mg, og, *batches[1])
+    t0 = int(og.t_dev.item())
+    losses = []
+    for k in range(1, 5):
+        _say(f"case captured step replay {k}")
+        _copy_state(m1, o1, mg, og)
+        _copy_state(m2, o2, mg, og)
+        l1 = _eager_step(m1, o1, *batches[k])
+        l2 = _eager_step(m2, o2, *batches[k])
+        scratch = torch.randn(1 << 20, device="cuda").sum()  # other work between replays
+        lg = cap(*batches[k])
+        torch.cuda.synchronize()
+        # (one training step changes the loss by about 2e-3 relative here)
+        tol = max(2 * abs(l2.item() - l1.item()), 5e-4 * abs(l1.item()))
+        assert abs(lg.item() - l1.item()) <= tol, (lg.item(), l1.item(), l2.item())
+        losses.append(lg.item())
+        dsum = nsum = cnt = 0.0
+        with torch.no_grad():
+            for key in mg.params:
+                d = (mg.params[key] - m1.params[key]).abs()
+                assert d.max().item() <= 2.5 * lr, (key, d.max().item())
+                dsum += d.sum().item()
+                nsum += (m2.params[key] - m1.params[key]).abs().sum().item()
+                cnt += d.numel()
+        # over all weights: no further from the first eager step than twice the second's distance
+        assert dsum / cnt <= 2 * nsum / cnt + 1e-3 * lr, (dsum / cnt, nsum / cnt)
+        for n in mg.running:
+            for a, b, c in zip(mg.running[n], m1.running[n], m2.running[n]):
+                tol = 3 * (c - b).abs().max().item() + 1e-4 * b.abs().max().item()
+                assert (a - b).abs().max().item() <= tol, n
+        del scratch
+    assert int(og.t_dev.item()) == t0 + 4
+    og.sync_step()
+    assert og.t == t0 + 3
+    assert len(set(losses)) == len(losses)  # each replay read its own batch

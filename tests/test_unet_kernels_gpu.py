@@ -332,7 +332,7 @@ def test_adam_multi_tensor(un):
     arr = un._array(un._AdamTensor, items)
     un._call("sil_unet_adam_multi", ctypes.cast(arr, ctypes.c_void_p), len(arr),
              ctypes.c_float(lr), ctypes.c_float(b1), ctypes.c_float(b2), ctypes.c_float(eps),
-             step, un._s())
+             step, None, un._s())
     torch.cuda.synchronize()
     f = lambda a: float(np.float32(a))
     b1f, b2f = f(b1), f(b2)
