@@ -1772,6 +1772,10 @@ constexpr int kRedBlocks = 1024;
 #define SIL_BNRED_BLOCKS 256
 #endif
 constexpr int kBnRedBlocks = SIL_BNRED_BLOCKS;
+// Pooling and head backward with the batch-norm sums: per-pixel work plus one
+// atomic per channel per block.  512 blocks measured fastest (1024 queue twice
+// the same-address atomics; 256 or 384 leave too few waves for the streaming).
+constexpr int kGradRedBlocks = 512;
 #ifndef SIL_BNRELU_BLOCKS
 #define SIL_BNRELU_BLOCKS 2048
 #endif
@@ -2195,7 +2199,7 @@ int sil_unet_maxpool_bwd(const void* dy, const uint8_t* idx, const void* dadd, v
   (void)hipGetLastError();
   const int64_t n = (int64_t)N * H * W * (C / 8);
   // with the batch-norm sums: a bounded grid, so that each block's atomics cover more pixels
-  const int grid = bn ? std::min(grid_for(n), kRedBlocks) : grid_for(n);
+  const int grid = bn ? std::min(grid_for(n), kGradRedBlocks) : grid_for(n);
   hipLaunchKernelGGL(k_maxpool_bwd, dim3(grid), dim3(256), 0, (hipStream_t)stream,
                      (const u16*)dy, idx, (const u16*)dadd, (u16*)dx, N, H, W, C, b);
   return done();
@@ -2227,7 +2231,7 @@ int sil_unet_head_bwd(const void* x, const float* w, const float* dlogits, const
   BnGrad b;
   if (!bn_grad_of(bn, C, &b)) return SIL_EINVAL;
   (void)hipGetLastError();
-  hipLaunchKernelGGL(k_head_bwd, dim3(std::min(grid_for(P * (C / 8) / 2048 + 1, 1), kRedBlocks)),
+  hipLaunchKernelGGL(k_head_bwd, dim3(std::min(grid_for(P * (C / 8) / 2048 + 1, 1), kGradRedBlocks)),
                      dim3(256), 0, (hipStream_t)stream, (const u16*)x, w, dlogits, dscale,
                      (u16*)dx, dw, db, P, C, b);
   return done();
