@@ -171,6 +171,15 @@ int sil_unet_head(const void* x, const float* w, const float* b, float* logits, 
 int sil_unet_softmax_xent(const float* logits, const uint8_t* labels, float* loss,
                           float* dlogits, float scale, int64_t P, void* stream);
 
+/* The head and the softmax cross-entropy in one pass (section III-C): per
+ * pixel the logits of sil_unet_head, then the loss and dlogits of
+ * sil_unet_softmax_xent, with the same arithmetic (identical dlogits and
+ * logits).  loss[0] accumulates; logits (fp32 [P][3]) is nullable: written
+ * only when given.  labels u8 [P] in 0..2. */
+int sil_unet_head_xent(const void* x, const float* w, const float* b, const uint8_t* labels,
+                       float* loss, float* dlogits, float* logits, float scale, int64_t P,
+                       int32_t C, void* stream);
+
 /* Head backward: with d = dlogits * dscale[0] (dscale: nullable device fp32
  * scalar, the gradient arriving at the loss; NULL means 1), dx [P][C] bf16 =
  * d w; dw fp32 [3][C] += sum_p d x; db fp32 [3] += sum_p d.  bn (nullable):

@@ -1451,54 +1451,102 @@ __global__ void k_maxpool_bwd(const u16* dy, const uint8_t* idx, const u16* dadd
   if (with_bn) bacc.flush(bn, lds, G, 0);
 }
 
-__global__ void k_head(const u16* x, const float* w, const float* b, float* logits, int64_t P,
-                       int32_t C) {
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P;
-       p += (int64_t)gridDim.x * blockDim.x) {
-    float l0 = b[0], l1 = b[1], l2 = b[2];
-    for (int32_t c0 = 0; c0 < C; c0 += 8) {
-      float f[8];
-      unpack8(*(const uint4*)(x + p * C + c0), f);
+// Logits of pixel p under the 1x1 head: l_k = b_k + sum_c x[p][c] w[k][c].
+__device__ __forceinline__ void head_logits(const u16* x, const float* w, const float* b,
+                                            int64_t p, int32_t C, float l[3]) {
+  l[0] = b[0];
+  l[1] = b[1];
+  l[2] = b[2];
+  for (int32_t c0 = 0; c0 < C; c0 += 8) {
+    float f[8];
+    unpack8(*(const uint4*)(x + p * C + c0), f);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        l0 += f[j] * w[c0 + j];
-        l1 += f[j] * w[C + c0 + j];
-        l2 += f[j] * w[2 * C + c0 + j];
-      }
+    for (int j = 0; j < 8; ++j) {
+      l[0] += f[j] * w[c0 + j];
+      l[1] += f[j] * w[C + c0 + j];
+      l[2] += f[j] * w[2 * C + c0 + j];
     }
-    logits[3 * p] = l0;
-    logits[3 * p + 1] = l1;
-    logits[3 * p + 2] = l2;
   }
 }
 
-__global__ void k_softmax_xent(const float* logits, const uint8_t* labels, float* loss,
-                               float* dlogits, float scale, int64_t P) {
-  __shared__ float part[256];
-  float acc = 0.f;
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P;
-       p += (int64_t)gridDim.x * blockDim.x) {
-    const float a = logits[3 * p], b = logits[3 * p + 1], c = logits[3 * p + 2];
-    const float mx = fmaxf(a, fmaxf(b, c));
-    const float ea = expf(a - mx), eb = expf(b - mx), ec = expf(c - mx);
-    const float s = ea + eb + ec;
-    const int y = labels[p];
-    const float ly = y == 0 ? a : (y == 1 ? b : c);
-    acc += (logf(s) + mx - ly) * scale;
-    if (dlogits) {
-      const float inv = 1.f / s;
-      dlogits[3 * p] = (ea * inv - (y == 0)) * scale;
-      dlogits[3 * p + 1] = (eb * inv - (y == 1)) * scale;
-      dlogits[3 * p + 2] = (ec * inv - (y == 2)) * scale;
-    }
+// Softmax cross-entropy of one pixel with label y: returns scale * -log
+// softmax(l)[y]; dl (nullable) = (softmax(l) - onehot(y)) * scale.
+__device__ __forceinline__ float xent_px(const float l[3], int y, float scale, float* dl) {
+  const float mx = fmaxf(l[0], fmaxf(l[1], l[2]));
+  const float ea = expf(l[0] - mx), eb = expf(l[1] - mx), ec = expf(l[2] - mx);
+  const float s = ea + eb + ec;
+  const float ly = y == 0 ? l[0] : (y == 1 ? l[1] : l[2]);
+  if (dl) {
+    const float inv = 1.f / s;
+    dl[0] = (ea * inv - (y == 0)) * scale;
+    dl[1] = (eb * inv - (y == 1)) * scale;
+    dl[2] = (ec * inv - (y == 2)) * scale;
   }
-  part[threadIdx.x] = acc;
+  return (logf(s) + mx - ly) * scale;
+}
+
+// Block sum of v into *out with one atomic per block (blockDim.x == 256).
+__device__ __forceinline__ void block_add(float v, float* out) {
+  __shared__ float part[256];
+  part[threadIdx.x] = v;
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) atomicAdd(loss, part[0]);
+  if (threadIdx.x == 0) atomicAdd(out, part[0]);
+}
+
+__global__ void k_head(const u16* x, const float* w, const float* b, float* logits, int64_t P,
+                       int32_t C) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    float l[3];
+    head_logits(x, w, b, p, C, l);
+    logits[3 * p] = l[0];
+    logits[3 * p + 1] = l[1];
+    logits[3 * p + 2] = l[2];
+  }
+}
+
+__global__ void k_softmax_xent(const float* logits, const uint8_t* labels, float* loss,
+                               float* dlogits, float scale, int64_t P) {
+  float acc = 0.f;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const float l[3] = {logits[3 * p], logits[3 * p + 1], logits[3 * p + 2]};
+    float dl[3];
+    acc += xent_px(l, labels[p], scale, dlogits ? dl : nullptr);
+    if (dlogits) {
+      dlogits[3 * p] = dl[0];
+      dlogits[3 * p + 1] = dl[1];
+      dlogits[3 * p + 2] = dl[2];
+    }
+  }
+  block_add(acc, loss);
+}
+
+// The head and the loss in one pass: the logits stay in registers (written
+// out only when asked for), saving their write and re-read.
+__global__ void k_head_xent(const u16* x, const float* w, const float* b, const uint8_t* labels,
+                            float* loss, float* dlogits, float* logits, float scale, int64_t P,
+                            int32_t C) {
+  float acc = 0.f;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    float l[3], dl[3];
+    head_logits(x, w, b, p, C, l);
+    acc += xent_px(l, labels[p], scale, dl);
+    dlogits[3 * p] = dl[0];
+    dlogits[3 * p + 1] = dl[1];
+    dlogits[3 * p + 2] = dl[2];
+    if (logits) {
+      logits[3 * p] = l[0];
+      logits[3 * p + 1] = l[1];
+      logits[3 * p + 2] = l[2];
+    }
+  }
+  block_add(acc, loss);
 }
 
 // Head backward in one pass over x: thread t owns channel group g = t % (C/8)
@@ -2220,6 +2268,18 @@ int sil_unet_softmax_xent(const float* logits, const uint8_t* labels, float* los
   (void)hipGetLastError();
   hipLaunchKernelGGL(k_softmax_xent, dim3(std::min(grid_for(P), kRedBlocks)), dim3(256), 0, (hipStream_t)stream,
                      logits, labels, loss, dlogits, scale, P);
+  return done();
+}
+
+int sil_unet_head_xent(const void* x, const float* w, const float* b, const uint8_t* labels,
+                       float* loss, float* dlogits, float* logits, float scale, int64_t P,
+                       int32_t C, void* stream) {
+  if (!x || !w || !b || !labels || !loss || !dlogits || P <= 0 || C <= 0 || C % 8)
+    return SIL_EINVAL;
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(k_head_xent, dim3(std::min(grid_for(P), kRedBlocks)), dim3(256), 0,
+                     (hipStream_t)stream, (const u16*)x, w, b, labels, loss, dlogits, logits, scale,
+                     P, C);
   return done();
 }
 

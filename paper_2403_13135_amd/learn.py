@@ -113,7 +113,7 @@ def train(model: unet.UNet, X: torch.Tensor, Y: torch.Tensor, steps: int, batch:
             loss = captured(xb, yb)
         else:
             opt.zero_grad()
-            loss = model.forward(xb, yb)[0]
+            loss = model.forward(xb, yb, with_logits=False)[0]
             model.backward(loss)
             opt.step()
             model.update_running_stats()

@@ -52,6 +52,7 @@ def _lib():
             "sil_unet_maxpool_bwd": [vp, vp, vp, vp, i32, i32, i32, i32, vp, vp],
             "sil_unet_head": [vp, vp, vp, vp, i64, i32, vp],
             "sil_unet_softmax_xent": [vp, vp, vp, vp, f32, i64, vp],
+            "sil_unet_head_xent": [vp, vp, vp, vp, vp, vp, vp, f32, i64, i32, vp],
             "sil_unet_head_bwd": [vp, vp, vp, vp, vp, vp, vp, i64, i32, vp, vp],
             "sil_unet_argmax": [vp, vp, i64, vp],
             "sil_unet_chips_input": [vp, i32, i32, i64, vp, i32, i32, f32, vp, vp],
@@ -343,24 +344,25 @@ class UpConv2(torch.autograd.Function):
 
 
 class HeadXent(torch.autograd.Function):
-    """Mean softmax cross-entropy of the 1x1 head; returns (loss, logits)."""
+    """Mean softmax cross-entropy of the 1x1 head (head and loss in one
+    kernel); returns (loss, logits), logits empty unless with_logits."""
 
     @staticmethod
-    def forward(ctx, x, w, b, labels, pool=None, in_slot=None):
+    def forward(ctx, x, w, b, labels, pool=None, in_slot=None, with_logits=True):
         N, H, W, C = x.shape
         ctx.in_slot = in_slot
         P = N * H * W
-        logits = torch.empty((P, 3), dtype=torch.float32, device=x.device)
-        _call("sil_unet_head", _p(x), _p(w), _p(b), _p(logits), P, C, _s())
+        logits = torch.empty((P, 3) if with_logits else (0, 3), dtype=torch.float32,
+                             device=x.device)
         ctx.pool = pool
         loss = _zeros((1,), x.device)  # its own tensor: callers may keep it past the step
-        dlogits = torch.empty_like(logits)
-        _call("sil_unet_softmax_xent", _p(logits), _p(labels), _p(loss), _p(dlogits),
-              ctypes.c_float(1.0 / P), P, _s())
+        dlogits = torch.empty((P, 3), dtype=torch.float32, device=x.device)
+        _call("sil_unet_head_xent", _p(x), _p(w), _p(b), _p(labels), _p(loss), _p(dlogits),
+              _p(logits) if with_logits else None, ctypes.c_float(1.0 / P), P, C, _s())
         ctx.save_for_backward(x, w, dlogits)
         ctx.mark_non_differentiable(logits)
         ctx.set_materialize_grads(False)
-        return loss.view(()), logits.view(N, H, W, 3)
+        return loss.view(()), logits.view(N, H, W, 3) if with_logits else logits
 
     @staticmethod
     def backward(ctx, dloss, _dlogits):
@@ -372,14 +374,14 @@ class HeadXent(torch.autograd.Function):
         db = _zeros((3,), x.device, ctx.pool)
         if dloss is None:
             dx.zero_()
-            return dx, dw, db, None, None, None
+            return dx, dw, db, None, None, None, None
         # dlogits carries the 1/P of the mean; the kernel scales it by the
         # incoming gradient on the device (no host synchronisation)
         dl = dloss.contiguous()
         req, keep = (None, None) if ctx.in_slot is None else ctx.in_slot.request(ctx.pool)
         _call("sil_unet_head_bwd", _p(x), _p(w), _p(dlogits), _p(dl), _p(dx), _p(dw), _p(db), P, C,
               req, _s())
-        return dx, dw, db, None, None, None
+        return dx, dw, db, None, None, None, None
 
 
 def layer_specs(widths: Sequence[int], in_ch: int = IN_CH):
@@ -465,8 +467,10 @@ class UNet:
         arr = self._prep_train if with_transposed else self._prep_infer
         _call("sil_unet_prep_weights", ctypes.cast(arr, ctypes.c_void_p), len(arr), _s())
 
-    def forward(self, x: torch.Tensor, labels: torch.Tensor):
-        """x: bf16 [N, H, W, 8]; labels: uint8 [N, H, W].  Returns (loss, logits).
+    def forward(self, x: torch.Tensor, labels: torch.Tensor, with_logits: bool = True):
+        """x: bf16 [N, H, W, 8]; labels: uint8 [N, H, W].  Returns (loss, logits);
+        with_logits=False leaves the logits unwritten (an empty tensor), as
+        the training step needs only the loss and its gradient.
 
         Starts a training step: the step's zeroed scratch (batch-norm sums and
         gradient accumulators) is taken from one pool cleared here, so the
@@ -504,7 +508,7 @@ class UNet:
                                link)
             h, link = cbr(up, skips[i], f"dec{i}.conv0", None)
             h, link = cbr(h, None, f"dec{i}.conv1", link)
-        return HeadXent.apply(h, P["head.w"], P["head.b"], labels, self.pool, link)
+        return HeadXent.apply(h, P["head.w"], P["head.b"], labels, self.pool, link, with_logits)
 
     def backward(self, loss: torch.Tensor):
         """loss.backward() with a seed gradient of 1 kept on the device, so that
@@ -644,7 +648,7 @@ class CapturedStep:
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
             opt.zero_grad()
-            self.loss, _ = model.forward(self.x, self.labels)
+            self.loss, _ = model.forward(self.x, self.labels, with_logits=False)
             model.backward(self.loss)
             opt.step()
             model.update_running_stats()

@@ -228,6 +228,47 @@ def test_softmax_xent(un):
     _check(dl, ref, 16 * U32 * scale * (sm + 1.0), "dlogits")
 
 
+@pytest.mark.parametrize("P,C", [(5000, 32), (777, 8), (300, 256)])
+def test_head_xent_matches_head_then_softmax(un, P, C):
+    """The fused head + loss kernel against sil_unet_head followed by
+    sil_unet_softmax_xent (both pinned to float64 above): the same arithmetic
+    per pixel, so logits and dlogits are bit-identical; the loss is a sum of
+    the same per-block partials in another atomic order (float32 roundoff of
+    the block count)."""
+    _say(f"case head_xent P={P} C={C}")
+    g = torch.Generator().manual_seed(P + C)
+    x = _bf((P, C), g)
+    w = torch.randn((3, C), generator=g) * 0.3
+    b = torch.randn(3, generator=g)
+    labels = torch.randint(0, 3, (P,), generator=g).to(torch.uint8)
+    xc, wc, bc, yc = x.cuda(), w.cuda(), b.cuda(), labels.cuda()
+    scale = 1.0 / P
+    logits = torch.empty((P, 3), device="cuda")
+    loss0 = torch.zeros(1, device="cuda")
+    dl0 = torch.empty((P, 3), device="cuda")
+    un._call("sil_unet_head", un._p(xc), un._p(wc), un._p(bc), un._p(logits), P, C, un._s())
+    un._call("sil_unet_softmax_xent", un._p(logits), un._p(yc), un._p(loss0), un._p(dl0),
+             ctypes.c_float(scale), P, un._s())
+    for with_logits in (True, False):
+        lg = torch.full((P, 3), float("nan"), device="cuda")
+        loss = torch.zeros(1, device="cuda")
+        dl = torch.empty((P, 3), device="cuda")
+        un._call("sil_unet_head_xent", un._p(xc), un._p(wc), un._p(bc), un._p(yc), un._p(loss),
+                 un._p(dl), un._p(lg) if with_logits else None, ctypes.c_float(scale), P, C,
+                 un._s())
+        torch.cuda.synchronize()
+        assert torch.equal(dl, dl0)
+        if with_logits:
+            assert torch.equal(lg, logits)
+        else:
+            assert torch.isnan(lg).all()  # left unwritten
+        nblk = (P + 255) // 256
+        assert abs(loss.item() - loss0.item()) <= 2 * nblk * U32 * abs(loss0.item()) + 1e-30
+    with pytest.raises(un.sil.SilError):  # labels missing
+        un._call("sil_unet_head_xent", un._p(xc), un._p(wc), un._p(bc), None, un._p(loss0),
+                 un._p(dl0), None, ctypes.c_float(scale), P, C, un._s())
+
+
 def test_argmax_first_maximum(un):
     _say("case argmax")
     g = torch.Generator().manual_seed(14)
