@@ -659,6 +659,163 @@ __global__ __launch_bounds__(kGT) void k_conv3_lds(GemmNT g) {
   }
 }
 
+// ---- 3x3 convolution of an 8-channel input ---------------------------------------
+//
+// The first layer (the 3 bands padded to 8 channels): K = 9 taps x 8 channels,
+// so each 32-wide MFMA reduction step takes 4 taps (lane group q reads the 8
+// channels of tap 4s + q, shifted in the staged tile; taps past 8 are zero).
+// The 72 x BN weights stay in registers for the block's life (3 steps x NJ
+// fragments); per 8 x 32 output tile only the 10 x 34 input pixels (16 bytes
+// each) are staged in LDS, and the next tile's are loaded during the current
+// tile's MFMAs.  Wave w owns output rows 2w, 2w+1.  Requires c0 == 8, c1 == 0
+// and N % BN == 0; epilogues E_STORE (with BN sums) and E_AFFRELU.
+template <int EM, int BN>
+__global__ __launch_bounds__(kGT) void k_conv3_c8(GemmNT g) {
+  constexpr int NJ = BN / 16;
+  constexpr int IN_R = (kCPix + kGT - 1) / kGT;
+  __shared__ __attribute__((aligned(16))) u16 Si[kCPix * 8];
+  __shared__ __attribute__((aligned(16))) u16 So[kCTH * kCTW * kLdsRow];
+  __shared__ float red[4][2][BN];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int q4 = lane >> 4;
+  const int32_t n0 = blockIdx.y * BN;
+  const int32_t ntx = (g.W + kCTW - 1) / kCTW, nty = (g.H + kCTH - 1) / kCTH;
+  const int32_t ntiles = g.M / (g.H * g.W) * nty * ntx;
+
+  // weights: step s, fragment j, lane (n = 16j + lane % 16, tap 4s + lane / 16)
+  bf16x8 wb[3][NJ];
+#pragma unroll
+  for (int st = 0; st < 3; ++st)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int tap = 4 * st + q4;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (tap < 9) v = *(const uint4*)(g.b + ((int64_t)(n0 + 16 * j + (lane & 15)) * 9 + tap) * 8);
+      wb[st][j] = __builtin_bit_cast(bf16x8, v);
+    }
+  // staged-pixel offset of this lane's tap per step (taps past 8: none)
+  int toff[3];
+#pragma unroll
+  for (int st = 0; st < 3; ++st) {
+    const int tap = 4 * st + q4;
+    toff[st] = tap < 9 ? (tap / 3) * kCIW + tap % 3 : -1;
+  }
+
+  float s1[NJ], s2[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) s1[j] = s2[j] = 0.f;
+
+  uint4 ri[IN_R];
+  auto gload = [&](int32_t tile) {
+    const int32_t img = tile / (nty * ntx), rem = tile - img * nty * ntx;
+    const int32_t oy0 = (rem / ntx) * kCTH, ox0 = (rem % ntx) * kCTW;
+#pragma unroll
+    for (int r = 0; r < IN_R; ++r) {
+      const int p = tid + kGT * r;
+      ri[r] = make_uint4(0, 0, 0, 0);
+      if (p < kCPix) {
+        const int32_t y = oy0 - 1 + p / kCIW, x = ox0 - 1 + p % kCIW;
+        if ((uint32_t)y < (uint32_t)g.H && (uint32_t)x < (uint32_t)g.W)
+          ri[r] = *(const uint4*)(g.a0 + (((int64_t)img * g.H + y) * g.W + x) * 8);
+      }
+    }
+  };
+
+  if ((int32_t)blockIdx.x < ntiles) gload(blockIdx.x);
+  for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int32_t img = t / (nty * ntx), rem = t - img * nty * ntx;
+    const int32_t oy0 = (rem / ntx) * kCTH, ox0 = (rem % ntx) * kCTW;
+    __syncthreads();  // the previous tile's reads of Si and So are done
+#pragma unroll
+    for (int r = 0; r < IN_R; ++r) {
+      const int p = tid + kGT * r;
+      if (p < kCPix) *(uint4*)&Si[p * 8] = ri[r];
+    }
+    __syncthreads();
+    if (t + (int32_t)gridDim.x < ntiles) gload(t + gridDim.x);
+
+    f32x4 acc[4][NJ];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int st = 0; st < 3; ++st)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {  // output row 2*wave + i/2, column half i%2
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (toff[st] >= 0)
+          v = *(const uint4*)&Si[((2 * wave + (i >> 1)) * kCIW + 16 * (i & 1) + (lane & 15) +
+                                  toff[st]) * 8];
+        const bf16x8 a = __builtin_bit_cast(bf16x8, v);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wb[st][j], acc[i][j], 0, 0, 0);
+      }
+
+    // epilogue: acc[i][j][tt] is output pixel (oy0 + 2*wave + i/2, ox0 + 16*(i%2) +
+    // 4*(lane/16) + tt), channel n0 + 16j + lane%16; staged in LDS for 16-byte stores
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int32_t col = n0 + 16 * j + (lane & 15);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int32_t oy = oy0 + 2 * wave + (i >> 1);
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) {
+          const int32_t ox = ox0 + 16 * (i & 1) + 4 * (lane >> 4) + tt;
+          const int pl = 32 * (2 * wave + (i >> 1)) + 16 * (i & 1) + 4 * (lane >> 4) + tt;
+          const float v = acc[i][j][tt];
+          float o = v;
+          if constexpr (EM == E_STORE) {
+            if (oy < g.H && ox < g.W) {
+              s1[j] += v;
+              s2[j] += v * v;
+            }
+          } else if constexpr (EM == E_AFFRELU) {
+            const float z = v * g.scale[col] + g.shift[col];
+            o = z > 0.f ? z : 0.f;
+          }
+          So[pl * kLdsRow + 16 * j + (lane & 15)] = f2bf(o);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < BN / 8; ++r) {
+      const int q = tid + kGT * r;
+      const int pl = q / (BN / 8), sub = q % (BN / 8);
+      const int32_t oy = oy0 + pl / kCTW, ox = ox0 + pl % kCTW;
+      if (oy >= g.H || ox >= g.W) continue;
+      *(uint4*)(g.y0 + (((int64_t)img * g.H + oy) * g.W + ox) * g.N + n0 + 8 * sub) =
+          *(const uint4*)&So[pl * kLdsRow + 8 * sub];
+    }
+  }
+
+  if constexpr (EM == E_STORE) {
+    if (g.stats) {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        s1[j] += __shfl_xor(s1[j], 16);
+        s1[j] += __shfl_xor(s1[j], 32);
+        s2[j] += __shfl_xor(s2[j], 16);
+        s2[j] += __shfl_xor(s2[j], 32);
+        if (lane < 16) {
+          red[wave][0][16 * j + lane] = s1[j];
+          red[wave][1][16 * j + lane] = s2[j];
+        }
+      }
+      __syncthreads();
+      if (tid < BN) {
+        const float t1 = red[0][0][tid] + red[1][0][tid] + red[2][0][tid] + red[3][0][tid];
+        const float t2 = red[0][1][tid] + red[1][1][tid] + red[2][1][tid] + red[3][1][tid];
+        atomicAdd(&g.stats[n0 + tid], t1);
+        atomicAdd(&g.stats[g.N + n0 + tid], t2);
+      }
+    }
+  }
+}
+
 // ---- weight gradients ----------------------------------------------------------
 
 enum TMode : int { T_PLAIN = 0, T_IM2COL = 1, T_UPGATHER = 2 };
@@ -1883,8 +2040,22 @@ int launch_nt(const GemmNT& g, hipStream_t st) {
   return done();
 }
 
-// 3x3 convolutions whose channel counts allow it go through k_conv3_lds.
+// 3x3 convolutions whose channel counts allow it go through k_conv3_lds, or
+// k_conv3_c8 for an 8-channel input.
 bool conv_lds_ok(const GemmNT& g) { return g.c0 % kBK == 0 && g.c1 % kBK == 0 && g.N % 32 == 0; }
+bool conv_c8_ok(const GemmNT& g) { return g.c0 == 8 && g.c1 == 0 && g.N % 32 == 0; }
+
+template <int EM>
+int launch_conv_c8(const GemmNT& g, hipStream_t st) {
+  (void)hipGetLastError();
+  const int32_t ntiles =
+      g.M / (g.H * g.W) * ((g.H + kCTH - 1) / kCTH) * ((g.W + kCTW - 1) / kCTW);
+  auto kern = k_conv3_c8<EM, 32>;
+  const int gy = g.N / 32;
+  const int cap = std::max(1, resident_blocks((const void*)kern) / gy);
+  hipLaunchKernelGGL(kern, dim3(std::min(ntiles, cap), gy), dim3(kGT), 0, st, g);
+  return done();
+}
 
 template <int EM>
 int launch_conv_lds(const GemmNT& g, hipStream_t st) {
@@ -1983,6 +2154,7 @@ int sil_unet_conv3x3(const void* x0, int32_t c0, const void* x1, int32_t c1, con
   g.b = (const u16*)w;
   g.y0 = (u16*)y;
   g.stats = stats;
+  if (conv_c8_ok(g)) return launch_conv_c8<E_STORE>(g, (hipStream_t)stream);
   if (conv_lds_ok(g)) return launch_conv_lds<E_STORE>(g, (hipStream_t)stream);
   if ((c0 + c1) % kBK == 0) return launch_nt<A_IM2COL32, E_STORE>(g, (hipStream_t)stream);
   return launch_nt<A_IM2COL, E_STORE>(g, (hipStream_t)stream);
@@ -2008,6 +2180,7 @@ int sil_unet_conv3x3_affine_relu(const void* x0, int32_t c0, const void* x1, int
   g.y0 = (u16*)y;
   g.scale = scale;
   g.shift = shift;
+  if (conv_c8_ok(g)) return launch_conv_c8<E_AFFRELU>(g, (hipStream_t)stream);
   if (conv_lds_ok(g)) return launch_conv_lds<E_AFFRELU>(g, (hipStream_t)stream);
   if ((c0 + c1) % kBK == 0) return launch_nt<A_IM2COL32, E_AFFRELU>(g, (hipStream_t)stream);
   return launch_nt<A_IM2COL, E_AFFRELU>(g, (hipStream_t)stream);

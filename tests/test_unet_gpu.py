@@ -84,7 +84,8 @@ def _conv_refs(x, w, dy):
                                               (3, 4, 4, 128, 0, 256), (1, 16, 16, 32, 32, 32),
                                               (2, 8, 8, 64, 0, 64), (1, 8, 8, 64, 0, 128),
                                               (1, 8, 8, 32, 0, 128), (4, 256, 256, 32, 0, 32),
-                                              (2, 9, 45, 32, 32, 64), (1, 17, 33, 64, 0, 32)])
+                                              (2, 9, 45, 32, 32, 64), (1, 17, 33, 64, 0, 32),
+                                              (2, 19, 45, 8, 0, 32), (1, 9, 13, 8, 0, 64)])
 def test_conv3x3_forward_and_gradients(un, N, H, W, c0, c1, cout):
     _say(f"case conv3x3 {N, H, W, c0, c1, cout}")
     g = torch.Generator().manual_seed(N * 1000 + H * 10 + cout)
@@ -130,7 +131,8 @@ def test_conv3x3_forward_and_gradients(un, N, H, W, c0, c1, cout):
 
 @pytest.mark.parametrize("N,H,W,c0,c1,cout", [(2, 16, 16, 8, 0, 32), (1, 9, 13, 16, 16, 8),
                                               (2, 32, 32, 64, 64, 128), (3, 64, 64, 32, 0, 32),
-                                              (2, 9, 45, 32, 32, 64)])
+                                              (2, 9, 45, 32, 32, 64), (2, 19, 45, 8, 0, 32),
+                                              (1, 9, 13, 8, 0, 64)])
 def test_conv3x3_affine_relu_inference(un, N, H, W, c0, c1, cout):
     """The fused inference layer against a float32 CPU conv, affine and ReLU."""
     _say(f"case conv3x3 affine relu {N, H, W, c0, c1, cout}")
