@@ -172,8 +172,9 @@ struct Walk {
 
 // Walk step st into r.  VEC: one aligned vector per band at vcol (aligned
 // scenes; max_bands applies `sel`).  Otherwise element loads at the 4
-// (clamped) column offsets, packed the same way.
-template <typename T, bool VEC>
+// (clamped) column offsets, packed the same way.  HALO: also the halo column
+// (walks without the median skip it).
+template <typename T, bool VEC, bool HALO = true>
 __device__ __forceinline__ void load_step(const Walk<T>& wk, int st, Raw<T>& r) {
   const uint32_t ro = wk.roff(st);
 #pragma unroll
@@ -193,7 +194,7 @@ __device__ __forceinline__ void load_step(const Walk<T>& wk, int st, Raw<T>& r) 
       else
         r.v[b] = e[0] | (e[1] << 8) | (e[2] << 16) | (e[3] << 24);
     }
-    r.h[b] = *(const T*)(rb + (ro + wk.hoff));
+    if constexpr (HALO) r.h[b] = *(const T*)(rb + (ro + wk.hoff));
   }
 }
 

@@ -742,12 +742,12 @@ __global__ __launch_bounds__(kThreads, 4) void k_thresh_walk(Shared sh, Scene sc
     const uint32_t loff = (uint32_t)(x0 + 4 * lane);
     const bool vec4 = sc.label_vec != 0;
     uint32_t cnt = 0;  // three 10-bit class counters (at most 128 pixels per lane)
-    // walk steps 1..32 are the band's rows 0..31 (down) or 31..0 (up)
-    auto one_row = [&](int st, const Raw<T>& cur, auto perm) {
+    // walk steps 1..32 are the band's rows 0..31 (down) or 31..0 (up); no
+    // median, so no halo column
+    auto row_of = [&](int st) { return wy0 + (wk.down ? st - 1 : kRowsPerWave - st); };
+    auto classify = [&](const Raw<T>& cur, auto perm) {
       uint32_t x[4];
       max_bands<T, decltype(perm)::value>(cur, x, wk.sel);
-      const int32_t r = wy0 + (wk.down ? st - 1 : kRowsPerWave - st);
-      if (r >= ch) return;  // wave-uniform
       uint32_t packed = 0;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -755,25 +755,37 @@ __global__ __launch_bounds__(kThreads, 4) void k_thresh_walk(Shared sh, Scene sc
         packed |= c << (8 * j);
         cnt += j < nv ? 1u << (10 * c) : 0u;
       }
-      if (nv > 0) store_labels(sc.labels + (int64_t)(y0 + r) * sc.lpitch, loff, nv, vec4, packed);
+      return packed;
     };
     if (sc.vec) {
+      // the rows' labels are held until the walk's loads are done, then stored
+      // (the reads then stream without interleaved stores)
       Raw<T> ring[kPrefetch];
+      uint32_t held[kRowsPerWave];
 #pragma unroll
-      for (int p = 0; p < kPrefetch; ++p) load_step<T, true>(wk, 1 + p, ring[p]);
+      for (int p = 0; p < kPrefetch; ++p) load_step<T, true, false>(wk, 1 + p, ring[p]);
 #pragma unroll
       for (int st = 1; st <= kRowsPerWave; ++st) {
         const Raw<T> cur = ring[(st - 1) % kPrefetch];
         if (st + kPrefetch <= kRowsPerWave)
-          load_step<T, true>(wk, st + kPrefetch, ring[(st - 1) % kPrefetch]);
-        one_row(st, cur, std::true_type{});
+          load_step<T, true, false>(wk, st + kPrefetch, ring[(st - 1) % kPrefetch]);
+        held[st - 1] = row_of(st) < ch ? classify(cur, std::true_type{}) : 0u;
+      }
+#pragma unroll
+      for (int st = 1; st <= kRowsPerWave; ++st) {
+        const int32_t r = row_of(st);
+        if (r < ch && nv > 0)  // r: wave-uniform
+          store_labels(sc.labels + (int64_t)(y0 + r) * sc.lpitch, loff, nv, vec4, held[st - 1]);
       }
     } else {
 #pragma unroll 1
       for (int st = 1; st <= kRowsPerWave; ++st) {
         Raw<T> cur;
-        load_step<T, false>(wk, st, cur);
-        one_row(st, cur, std::false_type{});
+        load_step<T, false, false>(wk, st, cur);
+        const int32_t r = row_of(st);
+        if (r >= ch) continue;  // wave-uniform
+        const uint32_t packed = classify(cur, std::false_type{});
+        if (nv > 0) store_labels(sc.labels + (int64_t)(y0 + r) * sc.lpitch, loff, nv, vec4, packed);
       }
     }
     const uint32_t c0 = wave_sum32(cnt & 1023u), c1 = wave_sum32((cnt >> 10) & 1023u),
