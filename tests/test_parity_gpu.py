@@ -244,7 +244,8 @@ def test_param_variants(sil):
 def test_full_tile_bitexact(sil):
     """The 10980x10980 uint16 tile (3 bands, 10 % haze / 5 % shadow), chip and
     patch 256, in the launch configuration the benchmark times; every label,
-    count and chip statistic against the oracle."""
+    count and chip statistic against the oracle, with the filter and without
+    it (thresholds only)."""
     spec = synth.config_tile()
     _say("case full tile: generating")
     s = synth.generate(spec)
@@ -256,6 +257,10 @@ def test_full_tile_bitexact(sil):
     o = run_oracle(s, fields)
     assert_same(g, o, "full tile")
     del o
+    # thresholds only (filter 0), as the benchmark's thresholds-only mode runs it
+    f0 = dict(fields, filter=0)
+    _say("case full tile: filter 0, gpu and oracle")
+    assert_same(run_gpu(sil, s, f0, label_pad=11008 - 10980), run_oracle(s, f0), "full tile filter0")
     # the same scene with padded (16-byte aligned) rows and unpadded label rows
     # gives the same result
     spec.pitch = 10984
